@@ -1,0 +1,157 @@
+"""Seeded synthetic workloads (problem descriptions and initial conditions).
+
+This module holds no arithmetic of the numerical method: it only builds the
+plain problem description (grid, system, boundary conditions, coefficients)
+and the initial state on the host in FP64 with numpy.  Both the GPU library's
+binding and the CPU oracle consume what it returns, so the two sides always
+start from the same bytes.
+
+Initial conditions are point values at cell centres; random draws come from
+``numpy.random.default_rng(seed)`` (PCG64).  For single-precision runs the
+initial state is rounded to FP32 once and the oracle starts from those
+rounded values.
+
+The problem description is a dict:
+
+    ndim, n (nx, ny, nz), lower, upper           grid (x fastest in memory)
+    system   "acoustics" | "shallow_water"
+    meqn     acoustics 1 + ndim (p, u, v[, w]); shallow water 3 (h, hu, hv)
+    limiter  "mc" | "none" (phi = 1) | "first_order"
+    efix     shallow water entropy fix on/off
+    bc_lo, bc_hi   per direction "extrap" | "wall" | "periodic"
+    rho, bulk      acoustics coefficients when has_aux is False
+    has_aux        acoustics: per-cell (rho, K) given in aux[2, nz, ny, nx]
+    grav           shallow water gravity
+    cfl_desired, cfl_max, dt_max, nsteps, dtype
+"""
+import math
+
+import numpy as np
+
+__all__ = ["problem", "CONFIGS", "cell_centers", "round_to", "random_states"]
+
+
+def _base(ndim, n, lower, upper, system, meqn, bc, **kw):
+    n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+    prob = {
+        "ndim": ndim,
+        "n": n,
+        "lower": tuple(float(v) for v in lower) + (0.0,) * (3 - len(lower)),
+        "upper": tuple(float(v) for v in upper) + (1.0,) * (3 - len(upper)),
+        "system": system,
+        "meqn": meqn,
+        "limiter": "mc",
+        "efix": True,
+        "bc_lo": (bc,) * 3,
+        "bc_hi": (bc,) * 3,
+        "rho": 1.0,
+        "bulk": 1.0,
+        "grav": 1.0,
+        "has_aux": False,
+        "cfl_desired": 0.9,
+        "cfl_max": 1.0,
+        "dt_max": float("inf"),
+        "nsteps": 1,
+        "dtype": "f64",
+    }
+    prob.update(kw)
+    return prob
+
+
+def cell_centers(prob):
+    """Cell-centre coordinate arrays (x, y, z), each shaped (nz, ny, nx)."""
+    nx, ny, nz = prob["n"]
+    axes = []
+    for k, m in enumerate((nx, ny, nz)):
+        lo, hi = prob["lower"][k], prob["upper"][k]
+        dx = (hi - lo) / m
+        axes.append(lo + (np.arange(m, dtype=np.float64) + 0.5) * dx)
+    z, y, x = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return x, y, z
+
+
+def round_to(q, dtype):
+    """The initial state as the given precision sees it, returned in FP64."""
+    if dtype in ("f32", np.float32):
+        return np.ascontiguousarray(q, dtype=np.float32).astype(np.float64)
+    return np.ascontiguousarray(q, dtype=np.float64)
+
+
+def acoustics2d_pulse(n=128, dtype="f64", nsteps=100):
+    """2D linear acoustics, 128 x 128 on [0,1]^2, rho = 1, K = 4 (c = 2),
+    p0 = exp(-((x-.5)^2 + (y-.5)^2) / 0.01), u = v = 0, extrapolation
+    boundaries, MC limiter, CFL 0.9, 100 steps."""
+    prob = _base(2, (n, n), (0, 0), (1, 1), "acoustics", 3, "extrap", rho=1.0, bulk=4.0,
+                 nsteps=nsteps, dtype=dtype, name="acoustics2d_pulse")
+    x, y, _ = cell_centers(prob)
+    q = np.zeros((3,) + x.shape)
+    q[0] = np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / 0.01)
+    return prob, round_to(q, dtype), None
+
+
+def sw_radial_dam(n=2048, dtype="f32", nsteps=1000, noise=True, seed=0):
+    """2D shallow water, n x n on [-2.5, 2.5]^2, g = 1; radial dam break
+    h = 2 for r < 0.5 else 1, plus seeded U(-1e-3, 1e-3) per cell on h
+    (drawn in memory order, y-major); hu = hv = 0; reflecting walls, CFL 0.9."""
+    prob = _base(2, (n, n), (-2.5, -2.5), (2.5, 2.5), "shallow_water", 3, "wall", grav=1.0,
+                 nsteps=nsteps, dtype=dtype, name="sw_radial_dam", seed=seed, noise=noise)
+    x, y, _ = cell_centers(prob)
+    r = np.sqrt(x * x + y * y)
+    q = np.zeros((3,) + x.shape)
+    q[0] = np.where(r < 0.5, 2.0, 1.0)
+    if noise:
+        rng = np.random.default_rng(seed)
+        q[0] += rng.uniform(-1e-3, 1e-3, size=x.shape)
+    return prob, round_to(q, dtype), None
+
+
+def acoustics3d_layers(n=256, dtype="f32", nsteps=200, seed=0):
+    """3D linear acoustics, n^3 on [0,1]^3, q = (p, u, v, w); two-layer medium
+    rho = 1, K = 1 for z < 0.5 and rho = 4, K = 1 above (by cell centre);
+    p = exp(-|x - x0|^2 / 0.05^2) with x0 ~ U[0.2, 0.8]^3 (seeded);
+    extrapolation boundaries, 200 steps."""
+    prob = _base(3, (n, n, n), (0, 0, 0), (1, 1, 1), "acoustics", 4, "extrap", has_aux=True,
+                 nsteps=nsteps, dtype=dtype, name="acoustics3d_layers", seed=seed)
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(0.2, 0.8, size=3)
+    x, y, z = cell_centers(prob)
+    q = np.zeros((4,) + x.shape)
+    q[0] = np.exp(-((x - x0[0]) ** 2 + (y - x0[1]) ** 2 + (z - x0[2]) ** 2) / 0.05 ** 2)
+    aux = np.empty((2,) + x.shape)
+    aux[0] = np.where(z < 0.5, 1.0, 4.0)
+    aux[1] = 1.0
+    prob["x0"] = tuple(float(v) for v in x0)
+    return prob, round_to(q, dtype), round_to(aux, dtype)
+
+
+def problem(name, **kw):
+    """(prob, q0, aux) for a named workload; keyword arguments override sizes."""
+    return CONFIGS[name](**kw)
+
+
+CONFIGS = {
+    "acoustics2d_pulse": acoustics2d_pulse,
+    "sw_radial_dam": sw_radial_dam,
+    "acoustics3d_layers": acoustics3d_layers,
+}
+
+
+def random_states(system, count, seed, meqn=3, depth=(0.5, 2.0), vel=0.5):
+    """Seeded random valid cell states (count, meqn) for interface-level tests:
+    shallow water depths in the given range and velocities up to vel; acoustics
+    pressures and velocities in [-1, 1]."""
+    rng = np.random.default_rng(seed)
+    if system == "shallow_water":
+        h = rng.uniform(depth[0], depth[1], size=count)
+        u = rng.uniform(-vel, vel, size=count)
+        v = rng.uniform(-vel, vel, size=count)
+        return np.stack([h, h * u, h * v], axis=1)
+    return rng.uniform(-1.0, 1.0, size=(count, meqn))
+
+
+def dx_of(prob, k):
+    return (prob["upper"][k] - prob["lower"][k]) / prob["n"][k]
+
+
+def cell_count(prob):
+    return int(math.prod(prob["n"]))

@@ -1,0 +1,88 @@
+"""Shared test helpers: norms and textbook exact solutions.
+
+Nothing here calls the GPU library or the oracle; these are the independent
+mathematical references the oracle is pinned against.
+"""
+import math
+
+import numpy as np
+
+
+def rel_linf(a, b):
+    """Per-field relative L-infinity error of a against reference b
+    (shape (meqn, ...)): max|a - b| / max(||b_m||_inf, 1e-3 max_m' ||b_m'||_inf).
+    Returns (max over fields, per-field list)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = np.array([np.max(np.abs(b[m])) for m in range(b.shape[0])])
+    floor = 1e-3 * scale.max() if scale.max() > 0 else 1.0
+    per = []
+    for m in range(b.shape[0]):
+        den = max(scale[m], floor)
+        per.append(float(np.max(np.abs(a[m] - b[m])) / den))
+    return max(per), per
+
+
+def sw_flux(q, g, normal):
+    """Physical shallow-water flux in the direction of component `normal`."""
+    tng = 3 - normal
+    h, mn, mt = q[0], q[normal], q[tng]
+    f = np.zeros(3)
+    f[0] = mn
+    f[normal] = mn * mn / h + 0.5 * g * h * h
+    f[tng] = mn * mt / h
+    return f
+
+
+def sw_dam_break_exact(hl, hr, g=1.0):
+    """Exact 1D dam break (u_l = u_r = 0, hl > hr): left rarefaction, right shock.
+    Newton on the middle depth h_m of
+      u_m = 2 (sqrt(g hl) - sqrt(g h_m))                      (1-rarefaction)
+      u_m = (h_m - hr) sqrt(g/2 (1/h_m + 1/hr))               (2-shock)
+    Returns dict(hm, um, shock, head, tail) and a sampler h(xi), u(xi)."""
+    def f(h):
+        return 2 * (math.sqrt(g * hl) - math.sqrt(g * h)) - (h - hr) * math.sqrt(
+            0.5 * g * (1 / h + 1 / hr))
+
+    h = 0.5 * (hl + hr)
+    for _ in range(100):
+        eps = 1e-7 * h
+        d = (f(h + eps) - f(h - eps)) / (2 * eps)
+        step = f(h) / d
+        h -= step
+        if abs(step) < 1e-15 * h:
+            break
+    hm = h
+    um = 2 * (math.sqrt(g * hl) - math.sqrt(g * hm))
+    shock = hm * um / (hm - hr)
+    head = -math.sqrt(g * hl)
+    tail = um - math.sqrt(g * hm)
+    cl = math.sqrt(g * hl)
+
+    def sample(xi):
+        xi = np.asarray(xi, dtype=np.float64)
+        h_out = np.empty_like(xi)
+        u_out = np.empty_like(xi)
+        left = xi <= head
+        fan = (xi > head) & (xi <= tail)
+        mid = (xi > tail) & (xi <= shock)
+        right = xi > shock
+        h_out[left] = hl
+        u_out[left] = 0.0
+        c = (2 * cl - xi[fan]) / 3.0
+        h_out[fan] = c * c / g
+        u_out[fan] = xi[fan] + c
+        h_out[mid] = hm
+        u_out[mid] = um
+        h_out[right] = hr
+        u_out[right] = 0.0
+        return h_out, u_out
+
+    return {"hm": hm, "um": um, "shock": shock, "head": head, "tail": tail}, sample
+
+
+def observed_order(errors, ns):
+    """Least-squares slope of -log(error) against log(n) for the finest pair."""
+    e1, e2 = errors[-2], errors[-1]
+    n1, n2 = ns[-2], ns[-1]
+    return math.log(e1 / e2) / math.log(n2 / n1)
