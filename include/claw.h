@@ -1,0 +1,171 @@
+/*
+ * claw.h -- C ABI of the MI355X (gfx950) dimension-split wave-propagation
+ * solver (the CUDACLAW method: Clawpack's second-order wave-propagation
+ * scheme with dimensional splitting, run on the GPU).
+ *
+ * The method (section 3 of the paper): each time step applies, direction by
+ * direction (x, then y, then z; equation LW-update), a sweep that solves a
+ * Riemann problem at every cell interface (waves W^p, speeds s^p and
+ * fluctuations A-dQ, A+dQ), limits the waves, forms the second-order
+ * correction flux F~ and updates every cell once (single-stage update,
+ * section 5.3).  The largest wave speed is reduced during the sweeps and a
+ * control step checks the CFL condition (equation CFL-condition), accepts the
+ * step or reverts it and picks the next time step (section 4.1).
+ *
+ * The user supplies the equations (Riemann solver kind), the grid, the
+ * boundary conditions and the limiter (section 4.1); set-up and evolution are
+ * driven from Python (section 6).
+ *
+ * Memory ownership: the library never allocates or frees device memory.  The
+ * caller allocates the state q, the optional aux array and a workspace of
+ * claw_workspace_bytes() bytes, keeps them alive until claw_destroy(), and
+ * passes a HIP stream on which every call enqueues its work.
+ *
+ * Layouts (device memory, dtype per the descriptor):
+ *   q   [meqn][nz][ny][nx], x fastest, no ghost cells.  Acoustics fields
+ *       (p, u, v[, w]); shallow water (h, hu, hv).
+ *   aux [2][nz][ny][nx]: density rho and bulk modulus K per cell (acoustics
+ *       with variable coefficients, maux = 2); NULL when maux = 0.
+ * q is rotation buffer 0.  Between calls the current state may live in a
+ * workspace buffer; claw_advance() ends with it copied back into q, and
+ * claw_sync_state() does the same on demand.
+ *
+ * Errors: every call returns a claw_status; nothing throws across the ABI.
+ * claw_last_error() gives a message for the last failing call of the thread.
+ * Calls on one solver must not overlap (one host thread at a time).
+ */
+#ifndef CLAW_H
+#define CLAW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct claw_solver claw_solver; /* opaque */
+
+typedef enum {
+    CLAW_OK = 0,
+    CLAW_E_INVALID = 1,     /* bad descriptor, pointer or argument */
+    CLAW_E_UNSUPPORTED = 2, /* valid but not implemented combination */
+    CLAW_E_HIP = 3,         /* HIP runtime failure */
+    CLAW_E_CFL = 4,         /* step rejected by the CFL check; state is Q^n bitwise */
+    CLAW_E_NONPHYSICAL = 5, /* depth <= 0 or not finite met in a sweep; state is Q^n */
+    CLAW_E_STATE = 6        /* step control failed (no usable dt, too many rejections) */
+} claw_status;
+
+typedef enum { CLAW_FP32 = 0, CLAW_FP64 = 1 } claw_dtype;
+/* Riemann solvers: linear acoustics (eq:acoustics, generalised to density
+ * rho and bulk modulus K) and shallow water (eq:SW) with the Roe solver and
+ * the Harten-Hyman entropy fix. */
+typedef enum { CLAW_RP_ACOUSTICS = 0, CLAW_RP_SHALLOW_WATER = 1 } claw_riemann;
+/* Ghost-cell rules (2 ghost cells per side): zero-order extrapolation,
+ * reflecting wall (normal velocity / momentum negated), periodic. */
+typedef enum { CLAW_BC_EXTRAP = 0, CLAW_BC_WALL = 1, CLAW_BC_PERIODIC = 2 } claw_bc;
+/* Wave limiter: MC; none (phi = 1, Lax-Wendroff); first order (no correction). */
+typedef enum { CLAW_LIM_MC = 0, CLAW_LIM_NONE = 1, CLAW_FIRST_ORDER = 2 } claw_limiter;
+
+typedef struct {
+    int32_t ndim;        /* 2 or 3 */
+    int32_t meqn;        /* acoustics 1 + ndim; shallow water 3 (2D only) */
+    int32_t mwaves;      /* acoustics 2; shallow water 3 */
+    int32_t maux;        /* 0, or 2 for acoustics with per-cell rho, K */
+    int64_t n[3];        /* cells per direction, x fastest; n[2] = 1 in 2D */
+    double lower[3];     /* domain corner */
+    double upper[3];
+    int32_t riemann;     /* claw_riemann */
+    int32_t limiter;     /* claw_limiter */
+    int32_t dtype;       /* claw_dtype */
+    int32_t efix;        /* shallow water: 1 = entropy fix (default) */
+    int32_t bc_lo[3];    /* claw_bc per direction */
+    int32_t bc_hi[3];
+    int32_t num_ghost;   /* must be 2 */
+    int32_t reserved;
+    double rho, bulk;    /* acoustics coefficients when maux = 0 */
+    double grav;         /* shallow water gravity */
+    double cfl_desired;  /* target Courant number for the next step (0.9) */
+    double cfl_max;      /* largest accepted Courant number (1.0) */
+    double dt_max;       /* upper bound on dt (+inf for none) */
+} claw_desc;
+
+/* Fills *d with defaults (MC limiter, entropy fix on, 2 ghosts, CFL 0.9 / 1.0,
+ * dt_max = +inf); the caller then sets grid, system and boundary conditions. */
+void claw_desc_init(claw_desc* d);
+
+/* Workspace size in bytes for descriptor d (two scratch state buffers, the
+ * derived acoustic coefficients and the control block).  CLAW_E_INVALID for a
+ * bad descriptor. */
+claw_status claw_workspace_bytes(const claw_desc* d, size_t* bytes);
+
+/* Validates d and binds the caller's device buffers.  q, aux, workspace are
+ * device pointers (aux NULL iff maux = 0); stream is a hipStream_t (NULL =
+ * the null stream).  Enqueues the set-up kernels (derived coefficients,
+ * control block) on the stream.  *out receives the handle. */
+claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* workspace,
+                        size_t workspace_bytes, void* stream, claw_solver** out);
+
+/* Speed-only pass (Riemann speeds of every direction on the current state,
+ * nothing updated) and host sync: *sigma = max_d max|s| / dx_d.  smax (may be
+ * NULL) receives max|s| per direction. */
+claw_status claw_cfl(claw_solver* h, double* sigma, double* smax);
+
+/* One trial step x, y (, z) with time step dt (section 4.1 pipeline).  If the
+ * Courant number dt * sigma exceeds cfl_max the step is reverted (state stays
+ * Q^n bitwise).  If cfl != NULL the call synchronises, stores the Courant
+ * number and returns CLAW_E_CFL for a rejected step, CLAW_E_NONPHYSICAL for a
+ * non-physical state; with cfl == NULL nothing is synchronised and the
+ * outcome is only recorded in the control block. */
+claw_status claw_step(claw_solver* h, double dt, double* cfl);
+
+/* One directional sweep dir (0, 1, 2) with time step dt, always accepted
+ * (a building block for tests; the result becomes the current state).
+ * smax (may be NULL) receives the largest |s| of the sweep (synchronises). */
+claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax);
+
+/* Adaptive stepping with revert (the production path): advances by nsteps
+ * accepted steps.  The first trial step is dt0 if dt0 > 0, else the dt_next
+ * left by a previous call, else cfl_desired / sigma of a speed pass.  Each
+ * trial's dt is min(dt_max, cfl_desired / sigma) of the previous trial.  The
+ * step sequence runs from a captured HIP graph with dt kept on the device;
+ * the call synchronises once at the end and leaves the state in q.
+ * *t receives the simulation time, *nreject the rejected trials of this call
+ * (either may be NULL). */
+claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t,
+                         int64_t* nreject);
+
+/* Prescribed time steps: one step per entry of dts (host array), each always
+ * accepted; cfl_log (host, may be NULL) receives each step's Courant number.
+ * Synchronises; the state is left in q. */
+claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts,
+                               double* cfl_log);
+
+/* Like claw_advance but launched eagerly with a HIP event pair around every
+ * kernel, for per-kernel timing: kernel_ms[k] receives the summed duration of
+ * the kernels of class k (0: x sweep, 1: y sweep, 2: z sweep, 3: control) and
+ * launches[k] their count (either may be NULL). */
+claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms,
+                               int64_t* launches);
+
+/* Enqueues a copy of the current state into q if it lives in a workspace
+ * buffer; no synchronisation. */
+claw_status claw_sync_state(claw_solver* h);
+
+/* Step-control scalars (synchronises).  Any output pointer may be NULL. */
+claw_status claw_get_control(claw_solver* h, double* t, double* dt_next, int64_t* accepted,
+                             int64_t* rejected);
+/* Restores t and dt_next (checkpoint / resume); enqueued, no sync. */
+claw_status claw_set_control(claw_solver* h, double t, double dt_next);
+
+/* Releases the handle (waits for its stream first).  Device buffers stay the
+ * caller's. */
+claw_status claw_destroy(claw_solver* h);
+
+const char* claw_status_string(claw_status s);
+const char* claw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

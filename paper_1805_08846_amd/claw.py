@@ -1,0 +1,311 @@
+"""ctypes binding of the C ABI in include/claw.h (argument marshalling only).
+
+Every function here forwards to the function of the same name in
+``libclaw.so``; all numerical work runs in the library's HIP kernels.  PyTorch
+supplies device memory (q, aux, the workspace) and the stream.  The library
+must have been built (``python -m paper_1805_08846_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libclaw.so")
+
+CLAW_OK, CLAW_E_INVALID, CLAW_E_UNSUPPORTED, CLAW_E_HIP, CLAW_E_CFL, CLAW_E_NONPHYSICAL, \
+    CLAW_E_STATE = range(7)
+CLAW_FP32, CLAW_FP64 = 0, 1
+CLAW_RP_ACOUSTICS, CLAW_RP_SHALLOW_WATER = 0, 1
+CLAW_BC_EXTRAP, CLAW_BC_WALL, CLAW_BC_PERIODIC = 0, 1, 2
+CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER = 0, 1, 2
+
+_BC = {"extrap": CLAW_BC_EXTRAP, "wall": CLAW_BC_WALL, "periodic": CLAW_BC_PERIODIC}
+_LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER}
+
+EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
+            "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
+            "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
+            "claw_status_string", "claw_last_error"]
+
+
+class claw_desc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("meqn", ctypes.c_int32),
+        ("mwaves", ctypes.c_int32),
+        ("maux", ctypes.c_int32),
+        ("n", ctypes.c_int64 * 3),
+        ("lower", ctypes.c_double * 3),
+        ("upper", ctypes.c_double * 3),
+        ("riemann", ctypes.c_int32),
+        ("limiter", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("efix", ctypes.c_int32),
+        ("bc_lo", ctypes.c_int32 * 3),
+        ("bc_hi", ctypes.c_int32 * 3),
+        ("num_ghost", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("rho", ctypes.c_double),
+        ("bulk", ctypes.c_double),
+        ("grav", ctypes.c_double),
+        ("cfl_desired", ctypes.c_double),
+        ("cfl_max", ctypes.c_double),
+        ("dt_max", ctypes.c_double),
+    ]
+
+
+class ClawError(RuntimeError):
+    def __init__(self, status, where, message):
+        super().__init__(f"{where}: {message} (status {status})")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_1805_08846_amd.build); there is no CPU fallback")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "claw_desc_init": (None, [P(claw_desc)]),
+        "claw_workspace_bytes": (i32, [P(claw_desc), P(ctypes.c_size_t)]),
+        "claw_create": (i32, [P(claw_desc), vp, vp, vp, ctypes.c_size_t, vp, P(vp)]),
+        "claw_cfl": (i32, [vp, P(dbl), P(dbl)]),
+        "claw_step": (i32, [vp, dbl, P(dbl)]),
+        "claw_sweep": (i32, [vp, i32, dbl, P(dbl)]),
+        "claw_advance": (i32, [vp, i64, dbl, P(dbl), P(i64)]),
+        "claw_advance_fixed": (i32, [vp, i64, P(dbl), P(dbl)]),
+        "claw_advance_timed": (i32, [vp, i64, P(dbl), P(i64)]),
+        "claw_sync_state": (i32, [vp]),
+        "claw_get_control": (i32, [vp, P(dbl), P(dbl), P(i64), P(i64)]),
+        "claw_set_control": (i32, [vp, dbl, dbl]),
+        "claw_destroy": (i32, [vp]),
+        "claw_status_string": (ctypes.c_char_p, [i32]),
+        "claw_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def library_path():
+    return _LIB_PATH
+
+
+def _check(status, where):
+    if status != CLAW_OK:
+        msg = _lib.claw_last_error().decode(errors="replace")
+        raise ClawError(status, where, msg or _lib.claw_status_string(status).decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# Thin wrappers with the C names
+# --------------------------------------------------------------------------
+
+def claw_desc_init():
+    d = claw_desc()
+    _lib.claw_desc_init(ctypes.byref(d))
+    return d
+
+
+def claw_workspace_bytes(desc):
+    n = ctypes.c_size_t(0)
+    _check(_lib.claw_workspace_bytes(ctypes.byref(desc), ctypes.byref(n)), "claw_workspace_bytes")
+    return n.value
+
+
+def claw_create(desc, q, aux, workspace, stream_handle):
+    h = ctypes.c_void_p(None)
+    _check(_lib.claw_create(ctypes.byref(desc), _ptr(q), _ptr(aux), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(),
+                            ctypes.c_void_p(stream_handle), ctypes.byref(h)), "claw_create")
+    return h
+
+
+def claw_cfl(h):
+    sigma = ctypes.c_double(0)
+    smax = (ctypes.c_double * 3)()
+    _check(_lib.claw_cfl(h, ctypes.byref(sigma), smax), "claw_cfl")
+    return sigma.value, list(smax)
+
+
+def claw_step(h, dt, sync=True):
+    """Returns (status, cfl); status CLAW_E_CFL means the step was reverted."""
+    if not sync:
+        _check(_lib.claw_step(h, float(dt), None), "claw_step")
+        return CLAW_OK, None
+    cfl = ctypes.c_double(0)
+    st = _lib.claw_step(h, float(dt), ctypes.byref(cfl))
+    if st not in (CLAW_OK, CLAW_E_CFL):
+        _check(st, "claw_step")
+    return st, cfl.value
+
+
+def claw_sweep(h, direction, dt):
+    sm = ctypes.c_double(0)
+    _check(_lib.claw_sweep(h, int(direction), float(dt), ctypes.byref(sm)), "claw_sweep")
+    return sm.value
+
+
+def claw_advance(h, nsteps, dt0=0.0):
+    t = ctypes.c_double(0)
+    nrej = ctypes.c_int64(0)
+    _check(_lib.claw_advance(h, int(nsteps), float(dt0), ctypes.byref(t), ctypes.byref(nrej)),
+           "claw_advance")
+    return t.value, nrej.value
+
+
+def claw_advance_fixed(h, dts):
+    dts = np.ascontiguousarray(dts, dtype=np.float64)
+    cfl = np.zeros(max(dts.size, 1))
+    _check(_lib.claw_advance_fixed(h, dts.size, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   cfl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "claw_advance_fixed")
+    return cfl[:dts.size]
+
+
+def claw_advance_timed(h, nsteps):
+    ms = (ctypes.c_double * 4)()
+    cnt = (ctypes.c_int64 * 4)()
+    _check(_lib.claw_advance_timed(h, int(nsteps), ms, cnt), "claw_advance_timed")
+    return list(ms), list(cnt)
+
+
+def claw_sync_state(h):
+    _check(_lib.claw_sync_state(h), "claw_sync_state")
+
+
+def claw_get_control(h):
+    t, dtn = ctypes.c_double(0), ctypes.c_double(0)
+    acc, rej = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(_lib.claw_get_control(h, ctypes.byref(t), ctypes.byref(dtn), ctypes.byref(acc),
+                                 ctypes.byref(rej)), "claw_get_control")
+    return {"t": t.value, "dt_next": dtn.value, "accepted": acc.value, "rejected": rej.value}
+
+
+def claw_set_control(h, t, dt_next):
+    _check(_lib.claw_set_control(h, float(t), float(dt_next)), "claw_set_control")
+
+
+def claw_destroy(h):
+    _check(_lib.claw_destroy(h), "claw_destroy")
+
+
+def claw_status_string(status):
+    return _lib.claw_status_string(int(status)).decode()
+
+
+def claw_last_error():
+    return _lib.claw_last_error().decode(errors="replace")
+
+
+# --------------------------------------------------------------------------
+# Convenience layer over torch tensors
+# --------------------------------------------------------------------------
+
+def desc_from_problem(prob):
+    """claw_desc for a problem description dict (see inputs.py)."""
+    d = claw_desc_init()
+    d.ndim = int(prob["ndim"])
+    n = list(prob["n"]) + [1] * (3 - len(prob["n"]))
+    for k in range(3):
+        d.n[k] = int(n[k])
+        d.lower[k] = float(prob["lower"][k])
+        d.upper[k] = float(prob["upper"][k])
+        d.bc_lo[k] = _BC[prob["bc_lo"][k]]
+        d.bc_hi[k] = _BC[prob["bc_hi"][k]]
+    d.meqn = int(prob["meqn"])
+    if prob["system"] == "acoustics":
+        d.riemann = CLAW_RP_ACOUSTICS
+        d.mwaves = 2
+        d.maux = 2 if prob.get("has_aux", False) else 0
+    else:
+        d.riemann = CLAW_RP_SHALLOW_WATER
+        d.mwaves = 3
+        d.maux = 0
+    d.limiter = _LIM[prob.get("limiter", "mc")]
+    d.dtype = CLAW_FP32 if prob.get("dtype", "f64") in ("f32", "float32") else CLAW_FP64
+    d.efix = 1 if prob.get("efix", True) else 0
+    d.rho = float(prob.get("rho", 1.0))
+    d.bulk = float(prob.get("bulk", 1.0))
+    d.grav = float(prob.get("grav", 1.0))
+    d.cfl_desired = float(prob.get("cfl_desired", 0.9))
+    d.cfl_max = float(prob.get("cfl_max", 1.0))
+    dm = prob.get("dt_max", float("inf"))
+    d.dt_max = float(dm) if dm is not None else math.inf
+    return d
+
+
+class Solver:
+    """A solver bound to torch device tensors q[meqn, nz, ny, nx] (and aux).
+
+    The workspace is allocated here with torch (the library never allocates);
+    all calls enqueue on the given torch stream (default: current stream)."""
+
+    def __init__(self, prob, q, aux=None, stream=None):
+        import torch
+        self.prob = prob
+        self.desc = desc_from_problem(prob)
+        want = torch.float32 if self.desc.dtype == CLAW_FP32 else torch.float64
+        if q.dtype != want or not q.is_cuda or not q.is_contiguous():
+            raise ValueError(f"q must be a contiguous {want} device tensor")
+        if aux is not None and (aux.dtype != want or not aux.is_contiguous()):
+            raise ValueError(f"aux must be a contiguous {want} device tensor")
+        self.q = q
+        self.aux = aux
+        self.stream = stream if stream is not None else torch.cuda.current_stream(q.device)
+        nbytes = claw_workspace_bytes(self.desc)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=q.device)
+        self.h = claw_create(self.desc, q, aux, self.workspace, self.stream.cuda_stream)
+
+    def cfl(self):
+        return claw_cfl(self.h)
+
+    def step(self, dt, sync=True):
+        return claw_step(self.h, dt, sync)
+
+    def sweep(self, direction, dt):
+        return claw_sweep(self.h, direction, dt)
+
+    def advance(self, nsteps, dt0=0.0):
+        return claw_advance(self.h, nsteps, dt0)
+
+    def advance_fixed(self, dts):
+        return claw_advance_fixed(self.h, dts)
+
+    def advance_timed(self, nsteps):
+        return claw_advance_timed(self.h, nsteps)
+
+    def sync_state(self):
+        claw_sync_state(self.h)
+
+    def control(self):
+        return claw_get_control(self.h)
+
+    def set_control(self, t, dt_next):
+        claw_set_control(self.h, t, dt_next)
+
+    def close(self):
+        if self.h is not None:
+            claw_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

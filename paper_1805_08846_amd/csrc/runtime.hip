@@ -1,0 +1,571 @@
+// runtime.hip -- the C ABI of include/claw.h: descriptor validation,
+// workspace plan, the step sequence of section 4.1 (sweeps x, y (, z), then
+// the CFL control kernel) enqueued on the caller's stream, and the captured
+// HIP graph that runs many adaptive steps without host round trips.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/claw.h"
+#include "claw_launch.h"
+
+using namespace claw;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+claw_status fail(claw_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+claw_status fail(claw_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(CLAW_E_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                        __LINE__);                                                             \
+    } while (0)
+
+constexpr size_t kAlign = 4096;
+constexpr int kGraphSteps = 32;  // trial steps per captured graph
+
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+    int64_t ncell;
+    size_t elem;
+    size_t state_bytes;
+    size_t off_ctrl, off_b1, off_b2, off_zc, total;
+};
+
+claw_status validate(const claw_desc* d) {
+    if (!d) return fail(CLAW_E_INVALID, "descriptor is NULL");
+    if (d->ndim != 2 && d->ndim != 3) return fail(CLAW_E_INVALID, "ndim must be 2 or 3 (got %d)", d->ndim);
+    for (int k = 0; k < 3; ++k) {
+        if (d->n[k] < 1) return fail(CLAW_E_INVALID, "n[%d] = %lld must be >= 1", k, (long long)d->n[k]);
+        if (k < d->ndim && !(d->upper[k] > d->lower[k]))
+            return fail(CLAW_E_INVALID, "upper[%d] must exceed lower[%d]", k, k);
+        if (d->bc_lo[k] < 0 || d->bc_lo[k] > 2 || d->bc_hi[k] < 0 || d->bc_hi[k] > 2)
+            return fail(CLAW_E_INVALID, "boundary condition of direction %d out of range", k);
+    }
+    if (d->ndim == 2 && d->n[2] != 1) return fail(CLAW_E_INVALID, "2D grids need n[2] = 1");
+    if (d->num_ghost != 2) return fail(CLAW_E_INVALID, "num_ghost must be 2 (got %d)", d->num_ghost);
+    if (d->dtype != CLAW_FP32 && d->dtype != CLAW_FP64) return fail(CLAW_E_INVALID, "unknown dtype");
+    if (d->limiter < 0 || d->limiter > 2) return fail(CLAW_E_INVALID, "unknown limiter");
+    if (!(d->cfl_desired > 0) || !(d->cfl_max >= d->cfl_desired))
+        return fail(CLAW_E_INVALID, "need 0 < cfl_desired <= cfl_max");
+    if (!(d->dt_max > 0)) return fail(CLAW_E_INVALID, "dt_max must be positive");
+    const int64_t ncell = d->n[0] * d->n[1] * d->n[2];
+    if (ncell > ((int64_t)1 << 40) / 8) return fail(CLAW_E_INVALID, "grid too large");
+    if (d->riemann == CLAW_RP_ACOUSTICS) {
+        if (d->meqn != 1 + d->ndim) return fail(CLAW_E_INVALID, "acoustics needs meqn = 1 + ndim");
+        if (d->mwaves != 2) return fail(CLAW_E_INVALID, "acoustics has mwaves = 2");
+        if (d->maux != 0 && d->maux != 2) return fail(CLAW_E_INVALID, "acoustics takes maux 0 or 2");
+        if (d->maux == 0 && !(d->rho > 0 && d->bulk > 0))
+            return fail(CLAW_E_INVALID, "acoustics needs rho > 0 and bulk > 0");
+    } else if (d->riemann == CLAW_RP_SHALLOW_WATER) {
+        if (d->ndim != 2) return fail(CLAW_E_UNSUPPORTED, "shallow water is 2D");
+        if (d->meqn != 3 || d->mwaves != 3) return fail(CLAW_E_INVALID, "shallow water has meqn = mwaves = 3");
+        if (d->maux != 0) return fail(CLAW_E_INVALID, "shallow water takes no aux");
+        if (!(d->grav > 0)) return fail(CLAW_E_INVALID, "grav must be positive");
+    } else {
+        return fail(CLAW_E_INVALID, "unknown Riemann solver %d", d->riemann);
+    }
+    return CLAW_OK;
+}
+
+Plan make_plan(const claw_desc* d) {
+    Plan p;
+    p.ncell = d->n[0] * d->n[1] * d->n[2];
+    p.elem = d->dtype == CLAW_FP64 ? 8 : 4;
+    p.state_bytes = (size_t)p.ncell * (size_t)d->meqn * p.elem;
+    p.off_ctrl = 0;
+    p.off_b1 = round_up(sizeof(Ctrl));
+    p.off_b2 = p.off_b1 + round_up(p.state_bytes);
+    p.off_zc = p.off_b2 + round_up(p.state_bytes);
+    p.total = p.off_zc + (d->maux ? round_up((size_t)p.ncell * 2 * p.elem) : 0);
+    return p;
+}
+
+}  // namespace
+
+struct claw_solver {
+    claw_desc d;
+    Plan plan;
+    int sys;
+    bool fp32;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    void* buf[3];
+    void* zc;
+    Ctrl* ctrl;
+    double dx[3];
+    hipGraphExec_t gexec;
+    hipGraph_t graph;
+    std::vector<hipEvent_t> events;
+};
+
+namespace {
+
+template <typename R>
+SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off) {
+    SweepArgs<R> a;
+    memset(&a, 0, sizeof a);
+    for (int i = 0; i < 3; ++i) a.buf[i] = (R*)h->buf[i];
+    a.zc = (const R*)h->zc;
+    a.ctrl = h->ctrl;
+    a.ncell = h->plan.ncell;
+    const int64_t nx = h->d.n[0], ny = h->d.n[1], nz = h->d.n[2];
+    a.nx = nx;
+    a.dir = dir;
+    a.src_off = src_off;
+    a.dst_off = dst_off;
+    a.bc_lo = h->d.bc_lo[dir];
+    a.bc_hi = h->d.bc_hi[dir];
+    a.limiter = h->d.limiter;
+    a.efix = h->d.efix;
+    a.grav = (R)h->d.grav;
+    if (h->sys == SYS_AC) {
+        a.Z0 = (R)sqrt(h->d.rho * h->d.bulk);
+        a.c0 = (R)sqrt(h->d.bulk / h->d.rho);
+    }
+    if (dir == 0) {
+        a.m = nx;
+        a.stride = 1;
+        a.nrows = ny * nz;
+    } else {
+        a.m = dir == 1 ? ny : nz;
+        a.stride = dir == 1 ? nx : nx * ny;
+        a.nlines_o = dir == 1 ? nz : ny;
+        a.ostride = dir == 1 ? nx * ny : nx;
+        // rows per wavefront: enough wavefronts to fill the chip, long
+        // enough chunks to keep the 3-interface halo small
+        const int64_t nstrip = (nx + 63) / 64;
+        const int64_t target_waves = 4096;
+        int64_t chunk = (a.m * nstrip * a.nlines_o + target_waves - 1) / target_waves;
+        if (chunk < 16) chunk = 16;
+        if (chunk > 512) chunk = 512;
+        chunk = (chunk + 3) / 4 * 4;
+        if (chunk > a.m) chunk = a.m;
+        a.chunk = chunk;
+    }
+    return a;
+}
+
+hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, bool speeds_only,
+                         hipStream_t s) {
+    if (h->fp32) {
+        SweepArgs<float> a = sweep_args<float>(h, dir, src_off, dst_off);
+        return launch_sweep<float>(a, h->sys, h->d.meqn, speeds_only, s);
+    }
+    SweepArgs<double> a = sweep_args<double>(h, dir, src_off, dst_off);
+    return launch_sweep<double>(a, h->sys, h->d.meqn, speeds_only, s);
+}
+
+// Buffer offsets of the sweeps of one step (relative to the current buffer):
+// x: cur -> cur+1, y: cur+1 -> cur+2, z: cur+2 -> cur+1.  Q^n is never written.
+void step_offsets(int ndim, int dir, int* src_off, int* dst_off) {
+    if (dir == 0) { *src_off = 0; *dst_off = 1; }
+    else if (dir == 1) { *src_off = 1; *dst_off = 2; }
+    else { *src_off = 2; *dst_off = 1; }
+    (void)ndim;
+}
+int result_offset(int ndim) { return ndim == 2 ? 2 : 1; }
+
+// One trial step (sweeps + control) on stream s; ev (optional) receives an
+// event before each kernel and one after the last.
+claw_status enqueue_trial(claw_solver* h, int mode, hipStream_t s, hipEvent_t* ev) {
+    for (int dir = 0; dir < h->d.ndim; ++dir) {
+        int so, dof;
+        step_offsets(h->d.ndim, dir, &so, &dof);
+        if (ev) HIP_TRY(hipEventRecord(ev[dir], s));
+        HIP_TRY(enqueue_sweep(h, dir, so, dof, false, s));
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim], s));
+    HIP_TRY(launch_control(h->ctrl, result_offset(h->d.ndim), mode, h->fp32, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim + 1], s));
+    return CLAW_OK;
+}
+
+claw_status read_ctrl(claw_solver* h, Ctrl* out) {
+    HIP_TRY(hipMemcpyAsync(out, h->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CLAW_OK;
+}
+
+claw_status sync_state(claw_solver* h) {
+    if (h->fp32)
+        HIP_TRY(launch_sync_state<float>(h->ctrl, (float*)h->buf[0], (float*)h->buf[1], (float*)h->buf[2],
+                                         h->plan.ncell * h->d.meqn, h->stream));
+    else
+        HIP_TRY(launch_sync_state<double>(h->ctrl, (double*)h->buf[0], (double*)h->buf[1],
+                                          (double*)h->buf[2], h->plan.ncell * h->d.meqn, h->stream));
+    return CLAW_OK;
+}
+
+claw_status speed_pass(claw_solver* h, hipStream_t s) {
+    HIP_TRY(launch_begin_speeds(h->ctrl, s));
+    for (int dir = 0; dir < h->d.ndim; ++dir) HIP_TRY(enqueue_sweep(h, dir, 0, 0, true, s));
+    return CLAW_OK;
+}
+
+// First trial step of an adaptive run: dt0, else dt_next, else from speeds.
+claw_status begin_adaptive(claw_solver* h, double dt0) {
+    if (dt0 > 0) {
+        HIP_TRY(launch_begin(h->ctrl, dt0, h->stream));
+        return CLAW_OK;
+    }
+    Ctrl c;
+    claw_status st = read_ctrl(h, &c);
+    if (st) return st;
+    if (c.dt_next > 0) {
+        HIP_TRY(launch_begin(h->ctrl, c.dt_next, h->stream));
+        return CLAW_OK;
+    }
+    st = speed_pass(h, h->stream);
+    if (st) return st;
+    HIP_TRY(launch_init_dt(h->ctrl, h->fp32, h->stream));
+    return CLAW_OK;
+}
+
+claw_status ctrl_status(const Ctrl& c) {
+    if (c.err == 5) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
+    if (c.err == 6) return fail(CLAW_E_STATE, "step control failed (no usable time step)");
+    if (c.err) return fail(CLAW_E_STATE, "step control error %d", c.err);
+    return CLAW_OK;
+}
+
+claw_status ensure_graph(claw_solver* h) {
+    if (h->gexec) return CLAW_OK;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    claw_status st = CLAW_OK;
+    for (int k = 0; k < kGraphSteps && st == CLAW_OK; ++k) st = enqueue_trial(h, MODE_ADAPT, h->cap_stream, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (st) {
+        if (g) hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CLAW_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        h->gexec = nullptr;
+        return fail(CLAW_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    h->graph = g;
+    return CLAW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void claw_desc_init(claw_desc* d) {
+    if (!d) return;
+    memset(d, 0, sizeof *d);
+    d->ndim = 2;
+    d->n[0] = d->n[1] = d->n[2] = 1;
+    d->upper[0] = d->upper[1] = d->upper[2] = 1.0;
+    d->limiter = CLAW_LIM_MC;
+    d->dtype = CLAW_FP64;
+    d->efix = 1;
+    d->num_ghost = 2;
+    d->rho = d->bulk = d->grav = 1.0;
+    d->cfl_desired = 0.9;
+    d->cfl_max = 1.0;
+    d->dt_max = INFINITY;
+}
+
+claw_status claw_workspace_bytes(const claw_desc* d, size_t* bytes) {
+    claw_status st = validate(d);
+    if (st) return st;
+    if (!bytes) return fail(CLAW_E_INVALID, "bytes is NULL");
+    *bytes = make_plan(d).total;
+    return CLAW_OK;
+}
+
+claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* workspace,
+                        size_t workspace_bytes, void* stream, claw_solver** out) {
+    claw_status st = validate(d);
+    if (st) return st;
+    if (!out) return fail(CLAW_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!q) return fail(CLAW_E_INVALID, "q is NULL");
+    if (!workspace) return fail(CLAW_E_INVALID, "workspace is NULL");
+    if ((d->maux != 0) != (aux != nullptr)) return fail(CLAW_E_INVALID, "aux must be given iff maux = 2");
+    Plan p = make_plan(d);
+    if (workspace_bytes < p.total)
+        return fail(CLAW_E_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, p.total);
+    if (((uintptr_t)q % 256) || ((uintptr_t)workspace % 256) || (aux && ((uintptr_t)aux % 16)))
+        return fail(CLAW_E_INVALID, "q and workspace must be 256-byte aligned");
+    claw_solver* h = new (std::nothrow) claw_solver();
+    if (!h) return fail(CLAW_E_HIP, "out of host memory");
+    h->d = *d;
+    h->plan = p;
+    h->fp32 = d->dtype == CLAW_FP32;
+    h->sys = d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC);
+    h->stream = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    h->ctrl = (Ctrl*)(ws + p.off_ctrl);
+    h->buf[0] = q;
+    h->buf[1] = ws + p.off_b1;
+    h->buf[2] = ws + p.off_b2;
+    h->zc = d->maux ? (void*)(ws + p.off_zc) : nullptr;
+    for (int k = 0; k < 3; ++k) h->dx[k] = k < d->ndim ? (d->upper[k] - d->lower[k]) / (double)d->n[k] : 1.0;
+    hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete h;
+        return fail(CLAW_E_HIP, "stream create failed: %s", hipGetErrorString(e));
+    }
+    e = launch_ctrl_init(h->ctrl, h->dx, d->ndim, d->cfl_desired, d->cfl_max, d->dt_max, h->stream);
+    if (e == hipSuccess && d->maux) {
+        if (h->fp32) e = launch_derive_zc<float>((const float*)aux, (float*)h->zc, p.ncell, h->stream);
+        else e = launch_derive_zc<double>((const double*)aux, (double*)h->zc, p.ncell, h->stream);
+    }
+    if (e != hipSuccess) {
+        hipStreamDestroy(h->cap_stream);
+        delete h;
+        return fail(CLAW_E_HIP, "set-up kernels failed: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return CLAW_OK;
+}
+
+claw_status claw_cfl(claw_solver* h, double* sigma, double* smax) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    claw_status st = speed_pass(h, h->stream);
+    if (st) return st;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    if (c.nonphys) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
+    double sg = 0;
+    for (int k = 0; k < 3; ++k) {
+        double v = 0;
+        if (k < h->d.ndim) {
+            if (h->fp32) {
+                float f;
+                memcpy(&f, &c.smax32[k], 4);
+                v = f;
+            } else {
+                memcpy(&v, &c.smax64[k], 8);
+            }
+            if (v / h->dx[k] > sg) sg = v / h->dx[k];
+        }
+        if (smax) smax[k] = v;
+    }
+    if (sigma) *sigma = sg;
+    return CLAW_OK;
+}
+
+claw_status claw_step(claw_solver* h, double dt, double* cfl) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (!(dt > 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be positive and finite");
+    HIP_TRY(launch_begin(h->ctrl, dt, h->stream));
+    claw_status st = enqueue_trial(h, MODE_STEP, h->stream, nullptr);
+    if (st) return st;
+    if (!cfl) return CLAW_OK;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    *cfl = c.cfl;
+    st = ctrl_status(c);
+    if (st) return st;
+    if (!c.last_accepted) return fail(CLAW_E_CFL, "step rejected: Courant number %.6g > %.6g", c.cfl, h->d.cfl_max);
+    return CLAW_OK;
+}
+
+claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (dir < 0 || dir >= h->d.ndim) return fail(CLAW_E_INVALID, "direction %d out of range", dir);
+    if (!(dt >= 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be finite and >= 0");
+    HIP_TRY(launch_begin(h->ctrl, dt, h->stream));
+    HIP_TRY(enqueue_sweep(h, dir, 0, 1, false, h->stream));
+    HIP_TRY(launch_accept_sweep(h->ctrl, 1, h->stream));
+    if (!smax) return CLAW_OK;
+    Ctrl c;
+    claw_status st = read_ctrl(h, &c);
+    if (st) return st;
+    if (c.nonphys) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
+    if (h->fp32) {
+        float f;
+        memcpy(&f, &c.smax32[dir], 4);
+        *smax = f;
+    } else {
+        memcpy(smax, &c.smax64[dir], 8);
+    }
+    return CLAW_OK;
+}
+
+claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t, int64_t* nreject) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
+    Ctrl c0;
+    claw_status st = read_ctrl(h, &c0);
+    if (st) return st;
+    if (nsteps > 0) {
+        st = begin_adaptive(h, dt0);
+        if (st) return st;
+        HIP_TRY(launch_set_target(h->ctrl, nsteps, h->stream));
+        st = ensure_graph(h);
+        if (st) return st;
+        int64_t remaining = nsteps;
+        for (int round = 0; round < 1000; ++round) {
+            const int64_t reps = (remaining + kGraphSteps - 1) / kGraphSteps;
+            for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+            Ctrl c;
+            st = read_ctrl(h, &c);
+            if (st) return st;
+            if (c.err) return ctrl_status(c);
+            if (c.done) break;
+            remaining = c.target - c.accepted;
+            if (remaining <= 0) break;
+        }
+    }
+    st = sync_state(h);
+    if (st) return st;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    if (t) *t = c.t;
+    if (nreject) *nreject = c.rejected - c0.rejected;
+    if (c.accepted - c0.accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
+    return CLAW_OK;
+}
+
+claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts, double* cfl_log) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (nsteps < 0 || (nsteps > 0 && !dts)) return fail(CLAW_E_INVALID, "bad step list");
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (!(dts[k] > 0) || !isfinite(dts[k])) return fail(CLAW_E_INVALID, "dts[%lld] not positive", (long long)k);
+        HIP_TRY(launch_begin(h->ctrl, dts[k], h->stream));
+        claw_status st = enqueue_trial(h, MODE_FIXED, h->stream, nullptr);
+        if (st) return st;
+        if (cfl_log) HIP_TRY(hipMemcpyAsync(&cfl_log[k], &h->ctrl->cfl, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    }
+    claw_status st = sync_state(h);
+    if (st) return st;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    return ctrl_status(c);
+}
+
+claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms, int64_t* launches) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
+    double ms[4] = {0, 0, 0, 0};
+    int64_t cnt[4] = {0, 0, 0, 0};
+    const int per = h->d.ndim + 2;
+    const int batch = 64;
+    if ((int)h->events.size() < batch * per) {
+        for (int i = (int)h->events.size(); i < batch * per; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->events.push_back(e);
+        }
+    }
+    claw_status st;
+    if (nsteps > 0) {
+        st = begin_adaptive(h, 0.0);
+        if (st) return st;
+        HIP_TRY(launch_set_target(h->ctrl, nsteps, h->stream));
+        int64_t remaining = nsteps;
+        while (remaining > 0) {
+            const int64_t n = remaining < batch ? remaining : batch;
+            for (int64_t k = 0; k < n; ++k) {
+                st = enqueue_trial(h, MODE_ADAPT, h->stream, &h->events[k * per]);
+                if (st) return st;
+            }
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (int64_t k = 0; k < n; ++k) {
+                hipEvent_t* ev = &h->events[k * per];
+                for (int j = 0; j <= h->d.ndim; ++j) {
+                    float v = 0;
+                    HIP_TRY(hipEventElapsedTime(&v, ev[j], ev[j + 1]));
+                    const int cls = j < h->d.ndim ? j : 3;
+                    ms[cls] += v;
+                    cnt[cls] += 1;
+                }
+            }
+            Ctrl c;
+            st = read_ctrl(h, &c);
+            if (st) return st;
+            if (c.err) return ctrl_status(c);
+            if (c.done) break;
+            remaining = c.target - c.accepted;
+        }
+    }
+    st = sync_state(h);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < 4; ++k) {
+        if (kernel_ms) kernel_ms[k] = ms[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    return CLAW_OK;
+}
+
+claw_status claw_sync_state(claw_solver* h) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    return sync_state(h);
+}
+
+claw_status claw_get_control(claw_solver* h, double* t, double* dt_next, int64_t* accepted, int64_t* rejected) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    Ctrl c;
+    claw_status st = read_ctrl(h, &c);
+    if (st) return st;
+    if (t) *t = c.t;
+    if (dt_next) *dt_next = c.dt_next;
+    if (accepted) *accepted = c.accepted;
+    if (rejected) *rejected = c.rejected;
+    return CLAW_OK;
+}
+
+claw_status claw_set_control(claw_solver* h, double t, double dt_next) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    if (!isfinite(t) || !(dt_next >= 0)) return fail(CLAW_E_INVALID, "bad control values");
+    HIP_TRY(launch_set_control(h->ctrl, t, dt_next, h->stream));
+    return CLAW_OK;
+}
+
+claw_status claw_destroy(claw_solver* h) {
+    if (!h) return CLAW_OK;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    for (hipEvent_t ev : h->events) hipEventDestroy(ev);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    delete h;
+    if (e != hipSuccess) return fail(CLAW_E_HIP, "stream sync failed: %s", hipGetErrorString(e));
+    return CLAW_OK;
+}
+
+const char* claw_status_string(claw_status s) {
+    switch (s) {
+        case CLAW_OK: return "ok";
+        case CLAW_E_INVALID: return "invalid argument";
+        case CLAW_E_UNSUPPORTED: return "unsupported";
+        case CLAW_E_HIP: return "HIP runtime error";
+        case CLAW_E_CFL: return "step rejected (CFL)";
+        case CLAW_E_NONPHYSICAL: return "non-physical state";
+        case CLAW_E_STATE: return "step control failed";
+    }
+    return "unknown status";
+}
+
+const char* claw_last_error(void) { return g_err; }
+
+}  // extern "C"

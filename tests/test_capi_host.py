@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library loads, exports every function include/claw.h declares, its
+descriptor struct matches the binding's layout, and descriptor validation
+rejects bad input before any HIP call is made.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "claw.h")
+
+
+@pytest.fixture(scope="module")
+def claw():
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(claw_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_function(claw):
+    lib = ctypes.CDLL(claw.library_path())
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared in claw.h but not exported"
+    assert sorted(claw.EXPORTED) == declared
+
+
+def test_descriptor_layout_matches_header(claw, tmp_path):
+    src = tmp_path / "layout.c"
+    fields = [f for f, _ in claw.claw_desc._fields_]
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(claw_desc, {f}));' for f in fields)
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "claw.h"\nint main(void){\n'
+                   + body + '\nprintf("sizeof %zu\\n", sizeof(claw_desc));\nreturn 0;}\n')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    got = dict(line.split() for line in out.strip().splitlines())
+    for f in fields:
+        assert int(got[f]) == getattr(claw.claw_desc, f).offset, f
+    assert int(got["sizeof"]) == ctypes.sizeof(claw.claw_desc)
+
+
+def _sw_desc(claw, n=64):
+    d = claw.claw_desc_init()
+    d.ndim = 2
+    d.n[0] = d.n[1] = n
+    d.n[2] = 1
+    d.lower[0] = d.lower[1] = -1.0
+    d.upper[0] = d.upper[1] = 1.0
+    d.riemann = claw.CLAW_RP_SHALLOW_WATER
+    d.meqn = d.mwaves = 3
+    d.dtype = claw.CLAW_FP32
+    return d
+
+
+def test_workspace_size(claw):
+    d = _sw_desc(claw, 64)
+    nb = claw.claw_workspace_bytes(d)
+    # two scratch state buffers plus the control block
+    assert nb >= 2 * 3 * 64 * 64 * 4
+    assert nb < 2 * 3 * 64 * 64 * 4 + 3 * 4096 + 4096
+
+
+@pytest.mark.parametrize("field,value", [
+    ("ndim", 4), ("meqn", 4), ("num_ghost", 3), ("dtype", 7), ("limiter", 9),
+    ("grav", -1.0), ("cfl_desired", 0.0), ("riemann", 5)])
+def test_bad_descriptors_are_rejected(claw, field, value):
+    d = _sw_desc(claw)
+    setattr(d, field, value)
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status in (claw.CLAW_E_INVALID, claw.CLAW_E_UNSUPPORTED)
+    assert claw.claw_last_error()
+
+
+def test_bad_grid_and_bc(claw):
+    d = _sw_desc(claw)
+    d.n[0] = 0
+    with pytest.raises(claw.ClawError):
+        claw.claw_workspace_bytes(d)
+    d = _sw_desc(claw)
+    d.bc_lo[1] = 3
+    with pytest.raises(claw.ClawError):
+        claw.claw_workspace_bytes(d)
+    d = _sw_desc(claw)
+    d.ndim = 3
+    d.n[2] = 4
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+
+
+def test_create_rejects_null_buffers_before_touching_the_gpu(claw):
+    d = _sw_desc(claw)
+    h = ctypes.c_void_p(None)
+    st = claw._lib.claw_create(ctypes.byref(d), None, None, None, 0, None, ctypes.byref(h))
+    assert st == claw.CLAW_E_INVALID
+    assert "q is NULL" in claw.claw_last_error()
+
+
+def test_null_handle_calls(claw):
+    for fn, args in [("claw_step", (None, 1.0, None)), ("claw_sync_state", (None,)),
+                     ("claw_advance", (None, 1, 0.0, None, None))]:
+        assert getattr(claw._lib, fn)(*args) == claw.CLAW_E_INVALID
+    assert claw._lib.claw_destroy(None) == claw.CLAW_OK
+
+
+def test_status_strings(claw):
+    for s in range(7):
+        assert claw.claw_status_string(s)

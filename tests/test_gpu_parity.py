@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64 runs must match the FP64 oracle within 1e-12 relative L-infinity per
+field; FP32 runs within 1e-5 (against the FP64 oracle started from the same
+FP32-rounded initial state).  Sizes span several tiles and ragged tails.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_08846_amd import inputs
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def claw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+def _dev_tensor(a, prob):
+    dt = torch.float64 if prob["dtype"] == "f64" else torch.float32
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device="cuda").contiguous()
+
+
+def _solver(claw, prob, q0, aux=None):
+    q = _dev_tensor(q0, prob)
+    a = _dev_tensor(aux, prob) if aux is not None else None
+    return claw.Solver(prob, q, a), q
+
+
+def _host(q):
+    torch.cuda.synchronize()
+    return q.double().cpu().numpy()
+
+
+def _prob2d(n, lower, upper, system, bc, **kw):
+    return inputs._base(2, n, lower, upper, system, 3, bc, **kw)
+
+
+# ---------------------------------------------------------------------------
+# whole runs
+# ---------------------------------------------------------------------------
+
+def test_acoustics_pulse_128_fp64_100_steps(claw):
+    prob, q0, _ = inputs.acoustics2d_pulse(n=128, nsteps=100)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(100)
+    ref = oracle.advance(prob, q0, None, 100)
+    err, per = rel_linf(_host(q), ref["q"])
+    print("acoustics 128^2 fp64 rel err", per)
+    assert err <= TOL["f64"]
+    assert nrej == ref["nreject"] == 0
+    assert t == pytest.approx(ref["t"], rel=1e-15, abs=0)
+    assert abs(t - 0.3515625) <= 1e-15
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sw_dam_break_adaptive(claw, dtype):
+    prob, q0, _ = inputs.sw_radial_dam(n=200, dtype=dtype, nsteps=150, seed=5)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(150)
+    ref = oracle.advance(prob, q0, None, 150)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"sw 200^2 {dtype} adaptive rel err", per, "t", t, ref["t"], "rej", nrej, ref["nreject"])
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sw_prescribed_steps(claw, dtype):
+    prob, q0, _ = inputs.sw_radial_dam(n=160, dtype=dtype, nsteps=100, seed=9)
+    ref = oracle.advance(prob, q0, None, 100)
+    dts = ref["dts"][ref["accepted"]]
+    s, q = _solver(claw, prob, q0)
+    cfl = s.advance_fixed(dts)
+    qf, cfl_ref = oracle.advance_fixed(prob, q0, None, dts)
+    err, per = rel_linf(_host(q), qf)
+    print(f"sw 160^2 {dtype} fixed rel err", per)
+    assert err <= TOL[dtype]
+    assert np.allclose(cfl, cfl_ref, rtol=1e-12 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_acoustics3d_layers(claw, dtype):
+    prob, q0, aux = inputs.acoustics3d_layers(n=40, dtype=dtype, nsteps=30, seed=2)
+    s, q = _solver(claw, prob, q0, aux)
+    t, nrej = s.advance(30)
+    ref = oracle.advance(prob, q0, aux, 30)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"acoustics3d 40^3 {dtype} rel err", per)
+    assert err <= TOL[dtype]
+    assert nrej == ref["nreject"]
+
+
+def test_acoustics3d_constant_ragged(claw):
+    prob = inputs._base(3, (37, 21, 13), (0, 0, 0), (1.3, 0.7, 0.5), "acoustics", 4, "extrap",
+                        rho=2.0, bulk=3.0, dtype="f64")
+    prob["bc_lo"] = ("wall", "periodic", "extrap")
+    prob["bc_hi"] = ("extrap", "periodic", "wall")
+    rng = np.random.default_rng(1)
+    q0 = rng.uniform(-1, 1, (4, 13, 21, 37))
+    s, q = _solver(claw, prob, q0)
+    s.advance(12)
+    ref = oracle.advance(prob, q0, None, 12)
+    err, per = rel_linf(_host(q), ref["q"])
+    assert err <= TOL["f64"], per
+
+
+# ---------------------------------------------------------------------------
+# single sweeps on random states, ragged sizes, every boundary rule
+# ---------------------------------------------------------------------------
+
+SIZES = [(3, 3), (1, 9), (9, 1), (127, 129), (300, 70), (70, 300), (251, 5)]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("system", ["shallow_water", "acoustics"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_single_sweep_random_states(claw, n, system, dtype, direction):
+    rng = np.random.default_rng(hash((n, system, dtype, direction)) % 2 ** 32)
+    bcs = ["extrap", "wall", "periodic"]
+    prob = _prob2d(n, (0, 0), (1.0, 1.5), system, "extrap", dtype=dtype, grav=1.3, rho=1.7,
+                   bulk=2.9)
+    prob["bc_lo"] = tuple(rng.choice(bcs) for _ in range(3))
+    prob["bc_hi"] = tuple(rng.choice(bcs) for _ in range(3))
+    ncell = n[0] * n[1]
+    if system == "shallow_water":
+        q0 = inputs.random_states("shallow_water", ncell, seed=3).T.reshape(3, 1, n[1], n[0])
+        smax_bound = 0.5 + math.sqrt(1.3 * 2.0)
+    else:
+        q0 = rng.uniform(-1, 1, (3, 1, n[1], n[0]))
+        smax_bound = math.sqrt(2.9 / 1.7)
+    q0 = inputs.round_to(q0, dtype)
+    dx = (prob["upper"][direction] - prob["lower"][direction]) / n[direction]
+    dt = 0.7 * dx / smax_bound
+    s, q = _solver(claw, prob, q0)
+    sm = s.sweep(direction, dt)
+    s.sync_state()
+    ref, sm_ref = oracle.sweep(prob, q0, None, direction, dt)
+    err, per = rel_linf(_host(q), ref)
+    tol = 1e-13 if dtype == "f64" else 2e-6
+    assert err <= tol, per
+    assert sm == pytest.approx(sm_ref, rel=1e-14 if dtype == "f64" else 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# exactness and invariants on the GPU
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_courant_one_exact_shift(claw, direction):
+    n = 128
+    prob = _prob2d((n, n), (0, 0), (1, 1), "acoustics", "periodic", rho=1.0, bulk=4.0)
+    rng = np.random.default_rng(7)
+    p1, u1 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    q0 = np.zeros((3, 1, n, n))
+    nrm = 1 + direction
+    if direction == 0:
+        q0[0], q0[nrm] = p1[None, :], u1[None, :]
+    else:
+        q0[0], q0[nrm] = p1[:, None], u1[:, None]
+    s, q = _solver(claw, prob, q0)
+    steps = 37
+    cfl = s.advance_fixed([1.0 / 256] * steps)
+    assert np.all(cfl == 1.0)
+    w1 = np.roll((-p1 + 2 * u1) / 4, -steps)
+    w2 = np.roll((p1 + 2 * u1) / 4, steps)
+    out = _host(q)
+    got_p = out[0, 0, 0, :] if direction == 0 else out[0, 0, :, 0]
+    got_u = out[nrm, 0, 0, :] if direction == 0 else out[nrm, 0, :, 0]
+    assert np.max(np.abs(got_p - (-2 * w1 + 2 * w2))) <= 1e-13
+    assert np.max(np.abs(got_u - (w1 + w2))) <= 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lake_at_rest_bitwise(claw, dtype):
+    n = 96
+    prob = _prob2d((n, n), (-1, -1), (1, 1), "shallow_water", "wall", grav=9.81, dtype=dtype)
+    q0 = np.zeros((3, 1, n, n))
+    q0[0] = 1.3
+    s, q = _solver(claw, prob, q0)
+    s.advance(20)
+    out = _host(q)
+    assert np.array_equal(out, inputs.round_to(q0, dtype))
+
+
+def test_mass_conservation_fp64(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=256, dtype="f64", seed=4)
+    s, q = _solver(claw, prob, q0)
+    s.advance(100)
+    out = _host(q)
+    m0, m1 = math.fsum(q0[0].ravel()), math.fsum(out[0].ravel())
+    assert abs(m1 - m0) <= 1e-13 * m0
+
+
+def test_revert_keeps_state_bitwise(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=128, dtype="f64", seed=6)
+    s, q = _solver(claw, prob, q0)
+    sigma, _ = s.cfl()
+    assert sigma == pytest.approx(oracle.sigma(prob, q0, None), rel=1e-13)
+    before = _host(q).copy()
+    st, cfl = s.step(2.0 / sigma)
+    assert st == claw.CLAW_E_CFL and cfl > 1.0
+    s.sync_state()
+    assert np.array_equal(_host(q), before)
+    st, cfl = s.step(0.5 / sigma)
+    assert st == claw.CLAW_OK and cfl <= 1.0
+    s.sync_state()
+    ref, _, _ = oracle.step(prob, q0, None, 0.5 / sigma)
+    assert rel_linf(_host(q), ref)[0] <= 1e-13
+
+
+def test_forced_rejection_in_advance(claw):
+    prob, q0, _ = inputs.acoustics2d_pulse(n=64, nsteps=10)
+    s, q = _solver(claw, prob, q0)
+    sig = oracle.sigma(prob, q0, None)
+    t, nrej = s.advance(10, dt0=1.2 / sig)
+    good = oracle.advance(prob, q0, None, 10)
+    assert nrej == 1
+    assert rel_linf(_host(q), good["q"])[0] <= 1e-12
+
+
+def test_nonphysical_depth_reported(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=64, dtype="f64", noise=False)
+    q0 = q0.copy()
+    q0[0, 0, 10, 20] = -0.5
+    s, q = _solver(claw, prob, q0)
+    with pytest.raises(claw.ClawError) as e:
+        s.advance(3, dt0=1e-3)
+    assert e.value.status == claw.CLAW_E_NONPHYSICAL
+    s.sync_state()
+    assert np.array_equal(_host(q), q0)
+
+
+def test_resume_equals_single_run_bitwise(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=128, dtype="f32", seed=8)
+    s1, q1 = _solver(claw, prob, q0)
+    s1.advance(40)
+    s1.advance(40)
+    c1 = s1.control()
+    s2, q2 = _solver(claw, prob, q0)
+    s2.advance(80)
+    c2 = s2.control()
+    assert np.array_equal(_host(q1), _host(q2))
+    assert c1["t"] == c2["t"] and c1["dt_next"] == c2["dt_next"]
+
+
+def test_graph_path_equals_eager_path_bitwise(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=150, dtype="f64", seed=10)
+    s1, q1 = _solver(claw, prob, q0)
+    s1.advance(70)
+    s2, q2 = _solver(claw, prob, q0)
+    ms, cnt = s2.advance_timed(70)
+    assert cnt[0] == cnt[1] == cnt[3] >= 70
+    assert np.array_equal(_host(q1), _host(q2))
+
+
+def test_run_to_run_determinism(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=333, dtype="f32", seed=12)
+    outs = []
+    for _ in range(2):
+        s, q = _solver(claw, prob, q0)
+        s.advance(30)
+        outs.append(_host(q))
+    assert np.array_equal(outs[0], outs[1])
