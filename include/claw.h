@@ -143,8 +143,9 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
 
 /* Like claw_advance but launched eagerly with a HIP event pair around every
  * kernel, for per-kernel timing: kernel_ms[k] receives the summed duration of
- * the kernels of class k (0: x sweep, 1: y sweep, 2: z sweep, 3: control) and
- * launches[k] their count (either may be NULL). */
+ * the sweeps in direction k (0: x, 1: y, 2: z; the step control runs inside
+ * the last sweep of a step; slot 3 is unused) and launches[k] their count
+ * (either array may be NULL; both have 4 entries). */
 claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms,
                                int64_t* launches);
 
@@ -161,6 +162,14 @@ claw_status claw_set_control(claw_solver* h, double t, double dt_next);
 /* Releases the handle (waits for its stream first).  Device buffers stay the
  * caller's. */
 claw_status claw_destroy(claw_solver* h);
+
+/* Achievable-bandwidth microbenchmark (the paper's achievable roof, section
+ * 7.1): streams over device buffers a (read, must be zero-filled) and b
+ * (written), each of `bytes` bytes, reps times per kernel, on `stream`, and
+ * stores GB/s in gbps[5]: copy, copy with non-temporal stores, read only,
+ * write only, write only non-temporal.  Synchronises. */
+claw_status claw_stream_bench(void* a, void* b, size_t bytes, int32_t reps, void* stream,
+                              double* gbps);
 
 const char* claw_status_string(claw_status s);
 const char* claw_last_error(void);

@@ -28,7 +28,7 @@ _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDE
 EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
             "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
             "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
-            "claw_status_string", "claw_last_error"]
+            "claw_stream_bench", "claw_status_string", "claw_last_error"]
 
 
 class claw_desc(ctypes.Structure):
@@ -85,6 +85,7 @@ def _load():
         "claw_get_control": (i32, [vp, P(dbl), P(dbl), P(i64), P(i64)]),
         "claw_set_control": (i32, [vp, dbl, dbl]),
         "claw_destroy": (i32, [vp]),
+        "claw_stream_bench": (i32, [vp, vp, ctypes.c_size_t, i32, vp, P(dbl)]),
         "claw_status_string": (ctypes.c_char_p, [i32]),
         "claw_last_error": (ctypes.c_char_p, []),
     }
@@ -203,6 +204,16 @@ def claw_set_control(h, t, dt_next):
 
 def claw_destroy(h):
     _check(_lib.claw_destroy(h), "claw_destroy")
+
+
+def claw_stream_bench(a, b, reps, stream_handle):
+    """Achievable bandwidth (GB/s) of copy, copy-nt, read, write, write-nt streams
+    over the device tensors a (zero-filled) and b of equal byte size."""
+    out = (ctypes.c_double * 5)()
+    nbytes = min(a.numel() * a.element_size(), b.numel() * b.element_size())
+    _check(_lib.claw_stream_bench(_ptr(a), _ptr(b), nbytes, int(reps),
+                                  ctypes.c_void_p(stream_handle), out), "claw_stream_bench")
+    return dict(zip(["copy", "copy_nt", "read", "write", "write_nt"], list(out)))
 
 
 def claw_status_string(status):

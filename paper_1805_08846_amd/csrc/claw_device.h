@@ -52,30 +52,34 @@ struct alignas(256) Ctrl {
     int32_t last_accepted;
     int32_t ndim;
     long long accepted, rejected, target, consecutive, trials;
+    unsigned int blocks_done;  // workgroups finished in the sweep that closes a step
 };
 
-// Per-launch arguments of a sweep kernel (passed by value).
+// Per-launch arguments of a sweep kernel (passed by value).  Element
+// offsets fit in 32 bits (the runtime rejects larger grids).
 template <typename R>
 struct SweepArgs {
     R* buf[3];          // rotation buffers (buf[0] is the caller's q)
     const R* zc;        // derived coefficients: Z field then c field (SYS_ACV)
     Ctrl* ctrl;
-    int64_t ncell;      // field stride
-    int64_t nx;         // cells along x (the contiguous direction)
-    int64_t m;          // cells along the sweep direction
-    int64_t stride;     // element stride along the sweep direction
-    int64_t nlines_o;   // column kernels: number of outer planes
-    int64_t ostride;    // column kernels: element stride between outer planes
-    int64_t nrows;      // row kernel: number of x-lines
+    int32_t ncell;      // field stride
+    int32_t nx;         // cells along x (the contiguous direction)
+    int32_t m;          // cells along the sweep direction
+    int32_t stride;     // element stride along the sweep direction
+    int32_t nlines_o;   // column kernels: number of outer planes
+    int32_t ostride;    // column kernels: element stride between outer planes
+    int32_t nrows;      // row kernel: number of x-lines
+    int32_t chunk;      // column kernels: cells along the sweep per wavefront
     int32_t dir;        // 0, 1, 2
     int32_t src_off;    // source buffer = (cur + src_off) % 3
     int32_t dst_off;    // destination buffer = (cur + dst_off) % 3
     int32_t bc_lo, bc_hi;
     int32_t limiter;
     int32_t efix;
-    int32_t speeds_only;
-    int64_t chunk;      // column kernels: rows per wave
+    int32_t result_off; // fused step control: buffer offset of the step's result
+    int32_t ctrl_mode;  // fused step control: MODE_* of the run
     R grav;
+    R sqrt_grav;
     R Z0, c0;           // constant-coefficient acoustics
 };
 
@@ -89,37 +93,48 @@ __device__ __forceinline__ double fsqrt(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ float frcp(float a) { return __builtin_amdgcn_rcpf(a); }
 __device__ __forceinline__ float fsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ float frsq(float a) { return __builtin_amdgcn_rsqf(a); }
 
-template <typename R>
-__device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
-template <typename R>
-__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
-template <typename R>
-__device__ __forceinline__ R rabs(R a) { return a < R(0) ? -a : a; }
+// min / max / abs as single VALU instructions (operands are never NaN on the
+// paths that use them; a NaN state is caught by the depth check)
+__device__ __forceinline__ float rmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ float rmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ float rabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ float rsign1(float a) { return __builtin_copysignf(1.0f, a); }
+__device__ __forceinline__ double rmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ double rmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ double rabs(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ double rsign1(double a) { return __builtin_copysign(1.0, a); }
 
-// Source index of cell i (possibly a ghost, -2 <= i < m + 2) along a line of
-// m cells; flip = the normal component changes sign (wall).
-__device__ __forceinline__ int64_t ghost_src(int64_t i, int64_t m, int bc_lo, int bc_hi,
-                                             bool& flip) {
+// Source index of cell i along a line of m cells under the boundary rules;
+// only -2 <= i <= m + 1 matter, other indices are clamped into that range
+// first.  flip = the normal component changes sign (wall).
+__device__ __forceinline__ int ghost_idx(int i, int m, int bc_lo, int bc_hi, bool& flip) {
+    i = i < -2 ? -2 : (i > m + 1 ? m + 1 : i);
     flip = false;
     if (i < 0) {
-        if (bc_lo == BC_EXTRAP) return 0;
         if (bc_lo == BC_WALL) {
             flip = true;
-            int64_t r = -1 - i;
+            int r = -1 - i;
             return r > m - 1 ? m - 1 : r;
         }
-        int64_t r = i % m;
-        return r < 0 ? r + m : r;
+        if (bc_lo == BC_PERIODIC) {
+            int r = i + m;
+            return r < 0 ? r + m : r;
+        }
+        return 0;
     }
     if (i >= m) {
-        if (bc_hi == BC_EXTRAP) return m - 1;
         if (bc_hi == BC_WALL) {
             flip = true;
-            int64_t r = 2 * m - 1 - i;
+            int r = 2 * m - 1 - i;
             return r < 0 ? 0 : r;
         }
-        return i % m;
+        if (bc_hi == BC_PERIODIC) {
+            int r = i - m;
+            return r >= m ? r - m : r;
+        }
+        return m - 1;
     }
     return i;
 }
@@ -144,19 +159,29 @@ struct Cell<R, SYS_ACV> {
 };
 // shallow water: depth, normal and tangential momentum plus derived per-cell
 // values shared by both interfaces of the cell
+__device__ __forceinline__ void sw_cell_derive(double h, double sg, double& ih, double& sqh, double& c) {
+    ih = 1.0 / h;
+    sqh = __builtin_sqrt(h);
+    c = sg * sqh;
+}
+__device__ __forceinline__ void sw_cell_derive(float h, float sg, float& ih, float& sqh, float& c) {
+    float r = frsq(h);  // 1/sqrt(h): sqrt(h) = h r, 1/h = r r
+    ih = r * r;
+    sqh = h * r;
+    c = sg * sqh;
+}
 template <typename R>
 struct Cell<R, SYS_SW> {
     R h, mn, mt;
     R u, v, sqh, c;
-    __device__ void derive(R g, bool& bad) {
+    __device__ void derive(R sg, bool& bad) {
         bool ok = h > R(0);  // false for NaN too
         bad = bad || !ok;
         R hh = ok ? h : R(1);
-        R ih = frcp(hh);
+        R ih;
+        sw_cell_derive(hh, sg, ih, sqh, c);
         u = mn * ih;
         v = mt * ih;
-        sqh = fsqrt(hh);
-        c = fsqrt(g * hh);
     }
 };
 
@@ -171,12 +196,11 @@ struct Iface {
 
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_AC>& l, const Cell<R, SYS_AC>& r,
-                                        R Z, R c, R, int, Iface<R, SYS_AC>& o) {
+                                        R Z, R c, R inv2Z, R, int, Iface<R, SYS_AC>& o) {
     R dp = r.p - l.p;
     R du = r.un - l.un;
-    R inv = frcp(Z + Z);
-    o.alpha[0] = (-dp + Z * du) * inv;
-    o.alpha[1] = (dp + Z * du) * inv;
+    o.alpha[0] = (-dp + Z * du) * inv2Z;
+    o.alpha[1] = (dp + Z * du) * inv2Z;
     o.s[0] = -c;
     o.s[1] = c;
     o.am[0] = -c;
@@ -187,7 +211,7 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_AC>& l, const Cell<R, 
 
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_ACV>& l, const Cell<R, SYS_ACV>& r,
-                                        R, R, R, int, Iface<R, SYS_ACV>& o) {
+                                        R, R, R, R, int, Iface<R, SYS_ACV>& o) {
     R dp = r.p - l.p;
     R du = r.un - l.un;
     R inv = frcp(l.Z + r.Z);
@@ -201,6 +225,17 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_ACV>& l, const Cell<R,
     o.e1 = r.Z;
 }
 
+// Roe speed of sound c^ = sqrt(g hbar) and 1 / (2 c^)
+__device__ __forceinline__ void roe_c(double x, double& c, double& i2c) {
+    c = __builtin_sqrt(x);
+    i2c = 0.5 / c;
+}
+__device__ __forceinline__ void roe_c(float x, float& c, float& i2c) {
+    float r = frsq(x);
+    c = x * r;
+    i2c = 0.5f * r;
+}
+
 // Roe solver with arithmetic-mean depth and sqrt(h)-weighted velocities plus
 // the Harten-Hyman entropy fix on the 1- and 3-waves.  The transonic test of
 // the fix, lambda_r = m/h - sqrt(g h) > 0 in the middle state, is taken as
@@ -209,16 +244,16 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_ACV>& l, const Cell<R,
 // test's boundary.
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, SYS_SW>& r,
-                                        R, R, R g, int efix, Iface<R, SYS_SW>& o) {
+                                        R, R, R, R g, int efix, Iface<R, SYS_SW>& o) {
     R hbar = R(0.5) * (l.h + r.h);
     R inv = frcp(l.sqh + r.sqh);
     R uhat = (l.sqh * l.u + r.sqh * r.u) * inv;
     R vhat = (l.sqh * l.v + r.sqh * r.v) * inv;
-    R chat = fsqrt(g * hbar);
+    R chat, i2c;
+    roe_c(g * hbar, chat, i2c);
     R dh = r.h - l.h;
     R dn = r.mn - l.mn;
     R dt = r.mt - l.mt;
-    R i2c = frcp(chat + chat);
     R s1 = uhat - chat;
     R s3 = uhat + chat;
     R a1 = (s3 * dh - dn) * i2c;
@@ -230,14 +265,14 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, 
         R lam_l = l.u - l.c;
         R hm = l.h + a1;
         R mm = l.mn + a1 * s1;
-        if (lam_l < R(0) && hm > R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
+        if (lam_l < R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
             R lam_r = fdiv(mm, hm) - fsqrt(g * hm);
             if (lam_r > R(0)) am1 = fdiv(lam_l * (lam_r - s1), lam_r - lam_l);
         }
         R lam_r3 = r.u + r.c;
         R hm3 = r.h - a3;
         R mm3 = r.mn - a3 * s3;
-        if (lam_r3 > R(0) && hm3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
+        if (lam_r3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
             R lam_l3 = fdiv(mm3, hm3) + fsqrt(g * hm3);
             if (lam_l3 < R(0)) am3 = fdiv(lam_l3 * (lam_r3 - s3), lam_r3 - lam_l3);
         }
@@ -255,20 +290,28 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, 
     o.e1 = R(0);
 }
 
-// r_p(this) . r_p(other) for the limiter's wave-projection ratio
+// Largest |s| of an interface (shallow water: |u^| <= max(|u^ - c^|, |u^ + c^|)).
 template <typename R>
-__device__ __forceinline__ R rdot(const Iface<R, SYS_SW>& a, const Iface<R, SYS_SW>& b, int p) {
-    if (p == 1) return R(1);
-    return R(1) + a.s[p] * b.s[p] + a.e0 * b.e0;
+__device__ __forceinline__ R iface_smax(const Iface<R, SYS_SW>& k) {
+    return rmax(rabs(k.s[0]), rabs(k.s[2]));
 }
 template <typename R, int SYS>
-__device__ __forceinline__ R rdot(const Iface<R, SYS>& a, const Iface<R, SYS>& b, int p) {
-    return p == 0 ? R(1) + a.e0 * b.e0 : R(1) + a.e1 * b.e1;
+__device__ __forceinline__ R iface_smax(const Iface<R, SYS>& k) {
+    return rmax(rabs(k.s[0]), rabs(k.s[1]));
 }
 
+// Limited wave strength phi(theta) * alpha of the MC limiter without forming
+// theta = n / (alpha |r|^2): with a = |alpha| and b = sign(alpha) n / |r|^2,
+//   phi(theta) alpha = sign(alpha) max(0, min((a + b) / 2, 2 a, 2 b)),
+// which is phi(theta) alpha exactly in real arithmetic and vanishes with alpha.
+// n = alpha_up (r_up . r) is the projection of the upwind wave.
 template <typename R>
-__device__ __forceinline__ R phi_mc(R theta) {
-    return rmax(R(0), rmin(R(0.5) * (R(1) + theta), rmin(R(2), theta + theta)));
+__device__ __forceinline__ R mc_limited(R alpha, R n_over_r2) {
+    const R sg = rsign1(alpha);
+    const R a = rabs(alpha);
+    const R b = sg * n_over_r2;
+    const R m = rmax(R(0), rmin(R(0.5) * (a + b), rmin(a + a, b + b)));
+    return sg * m;
 }
 
 // Output of one limited interface: contributions to its left and right cell
@@ -280,35 +323,92 @@ struct Contrib {
     R Rr[3];
 };
 
-// Limits interface k with its neighbours km (k - 1) and kp (k + 1) and forms
-// the contributions.  nu = dt / dx.
+// Limited strengths phi_p alpha_p of interface k given its neighbours km
+// (k - 1) and kp (k + 1).
+template <typename R>
+__device__ __forceinline__ void limited(const Iface<R, SYS_SW>& k, const Iface<R, SYS_SW>& km,
+                                        const Iface<R, SYS_SW>& kp, int limiter, R (&w)[3]) {
+    if (limiter == LIM_NONE) {
+        w[0] = k.alpha[0];
+        w[1] = k.alpha[1];
+        w[2] = k.alpha[2];
+        return;
+    }
+    // |r_1|^2 and |r_3|^2 share one reciprocal
+    const R r1 = R(1) + k.s[0] * k.s[0] + k.e0 * k.e0;
+    const R r3 = R(1) + k.s[2] * k.s[2] + k.e0 * k.e0;
+    const R t = frcp(r1 * r3);
+    const R ir1 = t * r3, ir3 = t * r1;
+    // upwind neighbour by the sign of each speed
+    const bool p1 = k.s[0] > R(0), p2 = k.s[1] > R(0), p3 = k.s[2] > R(0);
+    const R a1u = p1 ? km.alpha[0] : kp.alpha[0];
+    const R s1u = p1 ? km.s[0] : kp.s[0];
+    const R v1u = p1 ? km.e0 : kp.e0;
+    const R a3u = p3 ? km.alpha[2] : kp.alpha[2];
+    const R s3u = p3 ? km.s[2] : kp.s[2];
+    const R v3u = p3 ? km.e0 : kp.e0;
+    const R a2u = p2 ? km.alpha[1] : kp.alpha[1];
+    const R n1 = a1u * (R(1) + s1u * k.s[0] + v1u * k.e0);
+    const R n3 = a3u * (R(1) + s3u * k.s[2] + v3u * k.e0);
+    w[0] = mc_limited(k.alpha[0], n1 * ir1);
+    w[1] = mc_limited(k.alpha[1], a2u);
+    w[2] = mc_limited(k.alpha[2], n3 * ir3);
+}
+
+// Acoustics: wave 1 moves left (upwind neighbour k + 1), wave 2 right (k - 1).
+template <typename R>
+__device__ __forceinline__ void limited(const Iface<R, SYS_AC>& k, const Iface<R, SYS_AC>& km,
+                                        const Iface<R, SYS_AC>& kp, int limiter, R (&w)[2]) {
+    if (limiter == LIM_NONE) {
+        w[0] = k.alpha[0];
+        w[1] = k.alpha[1];
+        return;
+    }
+    // constant coefficients: r_p is the same at every interface
+    w[0] = mc_limited(k.alpha[0], kp.alpha[0]);
+    w[1] = mc_limited(k.alpha[1], km.alpha[1]);
+}
+template <typename R>
+__device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<R, SYS_ACV>& km,
+                                        const Iface<R, SYS_ACV>& kp, int limiter, R (&w)[2]) {
+    if (limiter == LIM_NONE) {
+        w[0] = k.alpha[0];
+        w[1] = k.alpha[1];
+        return;
+    }
+    // r_1 = (-Z_l, 1), r_2 = (Z_r, 1)
+    const R r1 = R(1) + k.e0 * k.e0;
+    const R r2 = R(1) + k.e1 * k.e1;
+    const R t = frcp(r1 * r2);
+    const R n1 = kp.alpha[0] * (R(1) + kp.e0 * k.e0);
+    const R n2 = km.alpha[1] * (R(1) + km.e1 * k.e1);
+    w[0] = mc_limited(k.alpha[0], n1 * (t * r2));
+    w[1] = mc_limited(k.alpha[1], n2 * (t * r1));
+}
+
+// Limits interface k and forms its contributions to the left cell
+// (A-dQ + F~) and the right cell (A+dQ - F~).  nu = dt / dx.
 template <typename R, int SYS>
 __device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Iface<R, SYS>& km,
                                               const Iface<R, SYS>& kp, R nu, int limiter,
                                               Contrib<R>& out) {
     constexpr int MW = Iface<R, SYS>::MW;
+    R w[MW];
+    if (limiter == LIM_FIRST) {
+#pragma unroll
+        for (int p = 0; p < MW; ++p) w[p] = R(0);
+    } else {
+        limited(k, km, kp, limiter, w);
+    }
     R kl[MW], kr[MW];
 #pragma unroll
     for (int p = 0; p < MW; ++p) {
-        R sp = k.s[p];
-        R as = rabs(sp);
-        R beta = R(0);
-        // a wave whose squared length is zero (underflow included) gets no
-        // correction; any other wave has a normal-range divisor below
-        if (limiter != LIM_FIRST && k.alpha[p] * k.alpha[p] != R(0)) {
-            R phi = R(1);
-            if (limiter == LIM_MC) {
-                // upwind neighbour by the sign of the speed
-                const Iface<R, SYS>& up = sp > R(0) ? km : kp;
-                R num = up.alpha[p] * rdot(up, k, p);
-                R den = k.alpha[p] * rdot(k, k, p);
-                phi = phi_mc(fdiv(num, den));
-            }
-            beta = R(0.5) * as * (R(1) - nu * as) * phi;
-        }
-        R a = k.am[p] + beta;
-        kl[p] = a * k.alpha[p];
-        kr[p] = (sp - a) * k.alpha[p];
+        const R sp = k.s[p];
+        const R as = rabs(sp);
+        const R cw = R(0.5) * as * (R(1) - nu * as) * w[p];  // F~ share of wave p
+        const R am = k.am[p] * k.alpha[p];                     // A-dQ share
+        kl[p] = am + cw;
+        kr[p] = (sp * k.alpha[p] - am) - cw;
     }
     if constexpr (SYS == SYS_SW) {
         R l13 = kl[0] + kl[2];
@@ -329,45 +429,42 @@ __device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Ifac
     }
 }
 
-template <typename R, int SYS>
-__device__ __forceinline__ R iface_smax(const Iface<R, SYS>& k) {
-    R m = R(0);
-#pragma unroll
-    for (int p = 0; p < Iface<R, SYS>::MW; ++p) m = rmax(m, rabs(k.s[p]));
-    return m;
-}
-
 // ---------------------------------------------------------------------------
 // Wave-level helpers
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T lane_prev(T v) {  // value of lane - 1
-    return __shfl_up(v, 1, 64);
+// DPP wave shifts: lane_prev gives lane i the value of lane i - 1, lane_next
+// the value of lane i + 1 (lane 0 / lane 63 receive 0).
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
+__device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
+__device__ __forceinline__ double lane_prev(double v) {
+    return __hiloint2double(dpp_shr1(__double2hiint(v)), dpp_shr1(__double2loint(v)));
 }
-template <typename T>
-__device__ __forceinline__ T lane_next(T v) {  // value of lane + 1
-    return __shfl_down(v, 1, 64);
+__device__ __forceinline__ double lane_next(double v) {
+    return __hiloint2double(dpp_shl1(__double2hiint(v)), dpp_shl1(__double2loint(v)));
 }
 
+// neighbour data a limiter needs: strengths, speeds and eigenvector numbers
 template <typename R, int SYS>
 __device__ __forceinline__ void iface_prev(const Iface<R, SYS>& in, Iface<R, SYS>& out) {
 #pragma unroll
     for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
         out.alpha[p] = lane_prev(in.alpha[p]);
-        out.s[p] = lane_prev(in.s[p]);
+        if constexpr (SYS == SYS_SW) out.s[p] = lane_prev(in.s[p]);
     }
-    out.e0 = lane_prev(in.e0);
-    out.e1 = lane_prev(in.e1);
+    if constexpr (SYS != SYS_AC) out.e0 = lane_prev(in.e0);
+    if constexpr (SYS == SYS_ACV) out.e1 = lane_prev(in.e1);
 }
 template <typename R, int SYS>
 __device__ __forceinline__ void iface_next(const Iface<R, SYS>& in, Iface<R, SYS>& out) {
 #pragma unroll
     for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
         out.alpha[p] = lane_next(in.alpha[p]);
-        out.s[p] = lane_next(in.s[p]);
+        if constexpr (SYS == SYS_SW) out.s[p] = lane_next(in.s[p]);
     }
-    out.e0 = lane_next(in.e0);
-    out.e1 = lane_next(in.e1);
+    if constexpr (SYS != SYS_AC) out.e0 = lane_next(in.e0);
+    if constexpr (SYS == SYS_ACV) out.e1 = lane_next(in.e1);
 }
 
 template <typename R>
@@ -378,13 +475,15 @@ __device__ __forceinline__ R wave_max(R v) {
 }
 
 // Per-direction speed maximum: non-negative IEEE values order like their bit
-// patterns, so an unsigned atomic max is exact and order independent.
+// patterns, so an unsigned atomic max is exact and order independent.  A
+// cached read first skips the atomic when a larger value is already known
+// (a stale read only costs an unneeded atomic).
 __device__ __forceinline__ void publish_smax(Ctrl* c, int dir, float v) {
-    unsigned int bits = __float_as_uint(v);
+    const unsigned bits = __float_as_uint(v);
     if (bits > __atomic_load_n(&c->smax32[dir], __ATOMIC_RELAXED)) atomicMax(&c->smax32[dir], bits);
 }
 __device__ __forceinline__ void publish_smax(Ctrl* c, int dir, double v) {
-    unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
     if (bits > __atomic_load_n(&c->smax64[dir], __ATOMIC_RELAXED)) atomicMax(&c->smax64[dir], bits);
 }
 
@@ -395,11 +494,107 @@ __device__ __forceinline__ float ctrl_nu<float>(const Ctrl* c, int dir) { return
 template <>
 __device__ __forceinline__ double ctrl_nu<double>(const Ctrl* c, int dir) { return c->dtdx[dir]; }
 
-// Block-wide max of v published once per workgroup (blockDim.x a multiple of 64).
+enum { MODE_ADAPT = 0, MODE_STEP = 1, MODE_FIXED = 2 };
+
+// ---------------------------------------------------------------------------
+// Step control (section 4.1; equation CFL-condition): Courant number from the
+// per-direction speed maxima, accept or revert, next trial step.  Runs in one
+// thread, either in the last workgroup of the sweep that closes a step or in
+// a one-thread kernel.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void set_trial_dt(Ctrl* c, double dt) {
+    c->dt = dt;
+    for (int d = 0; d < 3; ++d) {
+        double v = d < c->ndim ? dt / c->dx[d] : 0.0;
+        c->dtdx[d] = v;
+        c->dtdx_f[d] = (float)v;
+        c->smax32[d] = 0u;
+        c->smax64[d] = 0ull;
+    }
+    c->nonphys = 0;
+}
+
+// Reads of values other workgroups updated with atomics: coherent atomic
+// reads inside the kernel that produced them, plain loads in a later kernel.
+__device__ __forceinline__ double smax_of(Ctrl* c, int d, bool fp32, bool same_kernel) {
+    if (fp32)
+        return (double)__uint_as_float(same_kernel ? atomicMax(&c->smax32[d], 0u) : c->smax32[d]);
+    return __longlong_as_double((long long)(same_kernel ? atomicMax(&c->smax64[d], 0ull) : c->smax64[d]));
+}
+
+__device__ __forceinline__ double sigma_of(Ctrl* c, bool fp32, bool same_kernel = false) {
+    double sigma = 0.0;
+    for (int d = 0; d < c->ndim; ++d) {
+        double v = smax_of(c, d, fp32, same_kernel) / c->dx[d];
+        if (v > sigma) sigma = v;
+    }
+    return sigma;
+}
+
+// next trial step min(dt_max, cfl_desired / sigma); false if none exists
+__device__ __forceinline__ bool next_dt(const Ctrl* c, double sigma, double* dt) {
+    if (sigma > 0.0) {
+        double v = c->cfl_desired / sigma;
+        *dt = v < c->dt_max ? v : c->dt_max;
+        return true;
+    }
+    if (__builtin_isfinite(c->dt_max)) {
+        *dt = c->dt_max;
+        return true;
+    }
+    return false;
+}
+
+__device__ __forceinline__ void control_step(Ctrl* c, int result_off, int mode, bool fp32,
+                                             bool same_kernel) {
+    if (c->done) return;
+    const double sigma = sigma_of(c, fp32, same_kernel);
+    const double cfl = c->dt * sigma;
+    c->cfl = cfl;
+    c->trials += 1;
+    if (same_kernel ? atomicOr(&c->nonphys, 0) : c->nonphys) {  // the state stays Q^n
+        c->err = 5;
+        c->done = 1;
+        c->last_accepted = 0;
+        c->rejected += 1;
+        return;
+    }
+    const bool accept = mode == MODE_FIXED ? true : (cfl <= c->cfl_max);
+    if (accept) {
+        c->cur = (c->cur + result_off) % 3;
+        c->t += c->dt;
+        c->accepted += 1;
+        c->consecutive = 0;
+    } else {
+        c->rejected += 1;
+        c->consecutive += 1;
+        if (c->consecutive > 64) {
+            c->err = 6;
+            c->done = 1;
+        }
+    }
+    c->last_accepted = accept ? 1 : 0;
+    double dtn = 0.0;
+    if (!next_dt(c, sigma, &dtn)) {
+        c->err = 6;
+        c->done = 1;
+        return;
+    }
+    c->dt_next = dtn;
+    if (mode == MODE_ADAPT) {
+        set_trial_dt(c, dtn);
+        if (c->accepted >= c->target) c->done = 1;
+    }
+}
+
+// Block-wide max of v published once per workgroup (blockDim.x a multiple of
+// 64); with close_step the last workgroup to finish runs the step control.
 template <typename R>
-__device__ __forceinline__ void block_publish_smax(Ctrl* c, int dir, R v, bool bad) {
+__device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v, bool bad,
+                                             bool close_step) {
     __shared__ R red[16];
     __shared__ int redbad[16];
+    Ctrl* c = a.ctrl;
     v = wave_max(v);
     int anybad = __any(bad) ? 1 : 0;
     const int w = threadIdx.x >> 6;
@@ -417,6 +612,19 @@ __device__ __forceinline__ void block_publish_smax(Ctrl* c, int dir, R v, bool b
         }
         publish_smax(c, dir, m);
         if (b) atomicOr(&c->nonphys, 1);
+        if (close_step) {
+            // The counter increment must not be performed before this
+            // workgroup's maximum and flag: wait for the atomics above to
+            // complete.  All three are device-coherent atomics, so no cache
+            // flush is needed; the state itself is published by the kernel
+            // boundary.
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            const unsigned total = gridDim.x * gridDim.y * gridDim.z;
+            if (atomicAdd(&c->blocks_done, 1u) == total - 1) {
+                c->blocks_done = 0u;
+                control_step(c, a.result_off, a.ctrl_mode, sizeof(R) == 4, true);
+            }
+        }
     }
 }
 

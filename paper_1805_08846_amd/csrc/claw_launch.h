@@ -7,12 +7,12 @@
 
 namespace claw {
 
-// One directional sweep (or its speed-only pass) of system sys with meqn
-// fields; a.dir selects the row (0) or column (1, 2) kernel.
+// One directional sweep of system sys with meqn fields; a.dir selects the
+// row (0) or column (1, 2) kernel.  kind: 0 sweep, 1 speed-only pass, 2 sweep
+// that closes a step (its last workgroup runs the step control with
+// a.ctrl_mode and a.result_off).
 template <typename R>
-hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds_only, hipStream_t s);
-
-enum { MODE_ADAPT = 0, MODE_STEP = 1, MODE_FIXED = 2 };
+hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, int kind, hipStream_t s);
 
 // Step-control kernels (one thread; see control.hip).
 hipError_t launch_begin(Ctrl* c, double dt, hipStream_t s);

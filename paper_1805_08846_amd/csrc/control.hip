@@ -1,7 +1,8 @@
-// control.hip -- time-step control on the device (section 4.1: the CFL
-// number from the reduced wave speeds, equation CFL-condition; accept the
-// step or revert it and redo it with a smaller step) plus the small set-up
-// kernels (derived acoustic coefficients, copy of the state back into q).
+// control.hip -- one-thread kernels that set up the device control block
+// (trial step, first step from a speed pass, step target) and the small
+// element-wise set-up kernels (derived acoustic coefficients, copy of the
+// state back into q).  The per-step CFL decision itself (section 4.1) runs
+// in the last workgroup of the sweep that closes a step (control_step).
 //
 // All step-control scalars stay in the device control block, so a captured
 // graph of many steps runs without any host round trip.
@@ -10,18 +11,6 @@
 #include "claw_launch.h"
 
 namespace claw {
-
-__device__ static void set_trial_dt(Ctrl* c, double dt) {
-    c->dt = dt;
-    for (int d = 0; d < 3; ++d) {
-        double v = d < c->ndim ? dt / c->dx[d] : 0.0;
-        c->dtdx[d] = v;
-        c->dtdx_f[d] = (float)v;
-        c->smax32[d] = 0u;
-        c->smax64[d] = 0ull;
-    }
-    c->nonphys = 0;
-}
 
 __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndim, double cfl_desired,
                             double cfl_max, double dt_max) {
@@ -46,6 +35,7 @@ __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndi
     c->target = 0;
     c->consecutive = 0;
     c->trials = 0;
+    c->blocks_done = 0u;
     set_trial_dt(c, 0.0);
 }
 
@@ -59,34 +49,6 @@ __global__ void k_begin_speeds(Ctrl* c) {
     set_trial_dt(c, c->dt);
     c->done = 0;
     c->err = 0;
-}
-
-__device__ static double smax_of(const Ctrl* c, int d, bool fp32) {
-    if (fp32) return (double)__uint_as_float(c->smax32[d]);
-    return __longlong_as_double((long long)c->smax64[d]);
-}
-
-__device__ static double sigma_of(const Ctrl* c, bool fp32) {
-    double sigma = 0.0;
-    for (int d = 0; d < c->ndim; ++d) {
-        double v = smax_of(c, d, fp32) / c->dx[d];
-        if (v > sigma) sigma = v;
-    }
-    return sigma;
-}
-
-// next trial step min(dt_max, cfl_desired / sigma); false if none exists
-__device__ static bool next_dt(const Ctrl* c, double sigma, double* dt) {
-    if (sigma > 0.0) {
-        double v = c->cfl_desired / sigma;
-        *dt = v < c->dt_max ? v : c->dt_max;
-        return true;
-    }
-    if (isfinite(c->dt_max)) {
-        *dt = c->dt_max;
-        return true;
-    }
-    return false;
 }
 
 // First trial step from the speed-only pass that ran just before.
@@ -112,46 +74,10 @@ __global__ void k_set_target(Ctrl* c, long long nsteps) {
     c->err = 0;
 }
 
-// Closes a trial step: Courant number, accept or revert, next trial step.
+// Step control as its own one-thread kernel (used when the control is not
+// fused into the last sweep).
 __global__ void k_control(Ctrl* c, int result_off, int mode, int fp32) {
-    if (c->done) return;
-    const double sigma = sigma_of(c, fp32 != 0);
-    const double cfl = c->dt * sigma;
-    c->cfl = cfl;
-    c->trials += 1;
-    if (c->nonphys) {  // the state stays Q^n
-        c->err = 5;
-        c->done = 1;
-        c->last_accepted = 0;
-        c->rejected += 1;
-        return;
-    }
-    const bool accept = mode == MODE_FIXED ? true : (cfl <= c->cfl_max);
-    if (accept) {
-        c->cur = (c->cur + result_off) % 3;
-        c->t += c->dt;
-        c->accepted += 1;
-        c->consecutive = 0;
-    } else {
-        c->rejected += 1;
-        c->consecutive += 1;
-        if (c->consecutive > 64) {
-            c->err = 6;
-            c->done = 1;
-        }
-    }
-    c->last_accepted = accept ? 1 : 0;
-    double dtn = 0.0;
-    if (!next_dt(c, sigma, &dtn)) {
-        c->err = 6;
-        c->done = 1;
-        return;
-    }
-    c->dt_next = dtn;
-    if (mode == MODE_ADAPT) {
-        set_trial_dt(c, dtn);
-        if (c->accepted >= c->target) c->done = 1;
-    }
+    control_step(c, result_off, mode, fp32 != 0, false);
 }
 
 __global__ void k_accept_sweep(Ctrl* c, int result_off) {

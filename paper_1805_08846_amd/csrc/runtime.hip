@@ -4,6 +4,7 @@
 // HIP graph that runs many adaptive steps without host round trips.
 #include <math.h>
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -66,7 +67,9 @@ claw_status validate(const claw_desc* d) {
         return fail(CLAW_E_INVALID, "need 0 < cfl_desired <= cfl_max");
     if (!(d->dt_max > 0)) return fail(CLAW_E_INVALID, "dt_max must be positive");
     const int64_t ncell = d->n[0] * d->n[1] * d->n[2];
-    if (ncell > ((int64_t)1 << 40) / 8) return fail(CLAW_E_INVALID, "grid too large");
+    if (ncell * (int64_t)(d->meqn > 2 ? d->meqn : 2) >= ((int64_t)1 << 31) || d->n[1] > 65535 * 4 ||
+        d->n[2] > 65535)
+        return fail(CLAW_E_UNSUPPORTED, "grid too large for 32-bit element offsets");
     if (d->riemann == CLAW_RP_ACOUSTICS) {
         if (d->meqn != 1 + d->ndim) return fail(CLAW_E_INVALID, "acoustics needs meqn = 1 + ndim");
         if (d->mwaves != 2) return fail(CLAW_E_INVALID, "acoustics has mwaves = 2");
@@ -117,61 +120,6 @@ struct claw_solver {
 
 namespace {
 
-template <typename R>
-SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off) {
-    SweepArgs<R> a;
-    memset(&a, 0, sizeof a);
-    for (int i = 0; i < 3; ++i) a.buf[i] = (R*)h->buf[i];
-    a.zc = (const R*)h->zc;
-    a.ctrl = h->ctrl;
-    a.ncell = h->plan.ncell;
-    const int64_t nx = h->d.n[0], ny = h->d.n[1], nz = h->d.n[2];
-    a.nx = nx;
-    a.dir = dir;
-    a.src_off = src_off;
-    a.dst_off = dst_off;
-    a.bc_lo = h->d.bc_lo[dir];
-    a.bc_hi = h->d.bc_hi[dir];
-    a.limiter = h->d.limiter;
-    a.efix = h->d.efix;
-    a.grav = (R)h->d.grav;
-    if (h->sys == SYS_AC) {
-        a.Z0 = (R)sqrt(h->d.rho * h->d.bulk);
-        a.c0 = (R)sqrt(h->d.bulk / h->d.rho);
-    }
-    if (dir == 0) {
-        a.m = nx;
-        a.stride = 1;
-        a.nrows = ny * nz;
-    } else {
-        a.m = dir == 1 ? ny : nz;
-        a.stride = dir == 1 ? nx : nx * ny;
-        a.nlines_o = dir == 1 ? nz : ny;
-        a.ostride = dir == 1 ? nx * ny : nx;
-        // rows per wavefront: enough wavefronts to fill the chip, long
-        // enough chunks to keep the 3-interface halo small
-        const int64_t nstrip = (nx + 63) / 64;
-        const int64_t target_waves = 4096;
-        int64_t chunk = (a.m * nstrip * a.nlines_o + target_waves - 1) / target_waves;
-        if (chunk < 16) chunk = 16;
-        if (chunk > 512) chunk = 512;
-        chunk = (chunk + 3) / 4 * 4;
-        if (chunk > a.m) chunk = a.m;
-        a.chunk = chunk;
-    }
-    return a;
-}
-
-hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, bool speeds_only,
-                         hipStream_t s) {
-    if (h->fp32) {
-        SweepArgs<float> a = sweep_args<float>(h, dir, src_off, dst_off);
-        return launch_sweep<float>(a, h->sys, h->d.meqn, speeds_only, s);
-    }
-    SweepArgs<double> a = sweep_args<double>(h, dir, src_off, dst_off);
-    return launch_sweep<double>(a, h->sys, h->d.meqn, speeds_only, s);
-}
-
 // Buffer offsets of the sweeps of one step (relative to the current buffer):
 // x: cur -> cur+1, y: cur+1 -> cur+2, z: cur+2 -> cur+1.  Q^n is never written.
 void step_offsets(int ndim, int dir, int* src_off, int* dst_off) {
@@ -182,18 +130,102 @@ void step_offsets(int ndim, int dir, int* src_off, int* dst_off) {
 }
 int result_offset(int ndim) { return ndim == 2 ? 2 : 1; }
 
+int col_chunk(int64_t m, int64_t nx, int64_t nlines_o) {
+    // cells along the sweep per wavefront: enough wavefronts to fill the chip,
+    // chunks long enough to keep the 3-interface halo small
+    static const int64_t target_waves = [] {
+        const char* e = getenv("CLAW_COL_WAVES");
+        return e ? (int64_t)atoll(e) : (int64_t)4096;
+    }();
+    static const int64_t forced = [] {
+        const char* e = getenv("CLAW_COL_CHUNK");
+        return e ? (int64_t)atoll(e) : (int64_t)0;
+    }();
+    const int64_t nstrip = (nx + 63) / 64;
+    int64_t chunk = forced > 0 ? forced : (m * nstrip * nlines_o + target_waves - 1) / target_waves;
+    if (forced <= 0) {
+        if (chunk < 16) chunk = 16;
+        if (chunk > 1024) chunk = 1024;
+        chunk = (chunk + 3) / 4 * 4;
+    }
+    if (chunk > m) chunk = m;
+    if (chunk < 1) chunk = 1;
+    return (int)chunk;
+}
+
+template <typename R>
+SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off) {
+    SweepArgs<R> a;
+    memset(&a, 0, sizeof a);
+    for (int i = 0; i < 3; ++i) a.buf[i] = (R*)h->buf[i];
+    a.zc = (const R*)h->zc;
+    a.ctrl = h->ctrl;
+    a.ncell = (int32_t)h->plan.ncell;
+    const int64_t nx = h->d.n[0], ny = h->d.n[1], nz = h->d.n[2];
+    a.nx = (int32_t)nx;
+    a.dir = dir;
+    a.src_off = src_off;
+    a.dst_off = dst_off;
+    a.bc_lo = h->d.bc_lo[dir];
+    a.bc_hi = h->d.bc_hi[dir];
+    a.limiter = h->d.limiter;
+    a.efix = h->d.efix;
+    a.grav = (R)h->d.grav;
+    a.sqrt_grav = (R)sqrt(h->d.grav);
+    a.result_off = result_offset(h->d.ndim);
+    a.ctrl_mode = MODE_ADAPT;
+    if (h->sys == SYS_AC) {
+        a.Z0 = (R)sqrt(h->d.rho * h->d.bulk);
+        a.c0 = (R)sqrt(h->d.bulk / h->d.rho);
+    }
+    if (dir == 0) {
+        a.m = (int32_t)nx;
+        a.stride = 1;
+        a.nrows = (int32_t)(ny * nz);
+    } else {
+        a.m = (int32_t)(dir == 1 ? ny : nz);
+        a.stride = (int32_t)(dir == 1 ? nx : nx * ny);
+        a.nlines_o = (int32_t)(dir == 1 ? nz : ny);
+        a.ostride = (int32_t)(dir == 1 ? nx * ny : nx);
+        a.chunk = col_chunk(a.m, nx, a.nlines_o);
+    }
+    return a;
+}
+
+// kind: 0 sweep, 1 speed pass, 2 sweep closing a step with control mode `mode`
+hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, int kind, int mode,
+                         hipStream_t s) {
+    if (h->fp32) {
+        SweepArgs<float> a = sweep_args<float>(h, dir, src_off, dst_off);
+        a.ctrl_mode = mode;
+        return launch_sweep<float>(a, h->sys, h->d.meqn, kind, s);
+    }
+    SweepArgs<double> a = sweep_args<double>(h, dir, src_off, dst_off);
+    a.ctrl_mode = mode;
+    return launch_sweep<double>(a, h->sys, h->d.meqn, kind, s);
+}
+
 // One trial step (sweeps + control) on stream s; ev (optional) receives an
 // event before each kernel and one after the last.
+bool fused_control() {
+    static const bool fused = [] {
+        const char* e = getenv("CLAW_FUSED_CONTROL");
+        return e && e[0] == '1';
+    }();
+    return fused;
+}
+
 claw_status enqueue_trial(claw_solver* h, int mode, hipStream_t s, hipEvent_t* ev) {
+    const bool fused = fused_control();
     for (int dir = 0; dir < h->d.ndim; ++dir) {
         int so, dof;
         step_offsets(h->d.ndim, dir, &so, &dof);
+        const bool last = dir == h->d.ndim - 1;
         if (ev) HIP_TRY(hipEventRecord(ev[dir], s));
-        HIP_TRY(enqueue_sweep(h, dir, so, dof, false, s));
+        HIP_TRY(enqueue_sweep(h, dir, so, dof, (last && fused) ? 2 : 0, mode, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim], s));
-    HIP_TRY(launch_control(h->ctrl, result_offset(h->d.ndim), mode, h->fp32, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim + 1], s));
+    if (!fused) HIP_TRY(launch_control(h->ctrl, result_offset(h->d.ndim), mode, h->fp32, s));
     return CLAW_OK;
 }
 
@@ -215,7 +247,7 @@ claw_status sync_state(claw_solver* h) {
 
 claw_status speed_pass(claw_solver* h, hipStream_t s) {
     HIP_TRY(launch_begin_speeds(h->ctrl, s));
-    for (int dir = 0; dir < h->d.ndim; ++dir) HIP_TRY(enqueue_sweep(h, dir, 0, 0, true, s));
+    for (int dir = 0; dir < h->d.ndim; ++dir) HIP_TRY(enqueue_sweep(h, dir, 0, 0, 1, MODE_ADAPT, s));
     return CLAW_OK;
 }
 
@@ -391,7 +423,7 @@ claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax) {
     if (dir < 0 || dir >= h->d.ndim) return fail(CLAW_E_INVALID, "direction %d out of range", dir);
     if (!(dt >= 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be finite and >= 0");
     HIP_TRY(launch_begin(h->ctrl, dt, h->stream));
-    HIP_TRY(enqueue_sweep(h, dir, 0, 1, false, h->stream));
+    HIP_TRY(enqueue_sweep(h, dir, 0, 1, 0, MODE_ADAPT, h->stream));
     HIP_TRY(launch_accept_sweep(h->ctrl, 1, h->stream));
     if (!smax) return CLAW_OK;
     Ctrl c;
@@ -467,7 +499,7 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
     if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
     double ms[4] = {0, 0, 0, 0};
     int64_t cnt[4] = {0, 0, 0, 0};
-    const int per = h->d.ndim + 2;
+    const int per = h->d.ndim + 1;
     const int batch = 64;
     if ((int)h->events.size() < batch * per) {
         for (int i = (int)h->events.size(); i < batch * per; ++i) {
@@ -491,12 +523,11 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
             HIP_TRY(hipStreamSynchronize(h->stream));
             for (int64_t k = 0; k < n; ++k) {
                 hipEvent_t* ev = &h->events[k * per];
-                for (int j = 0; j <= h->d.ndim; ++j) {
+                for (int j = 0; j < h->d.ndim; ++j) {
                     float v = 0;
                     HIP_TRY(hipEventElapsedTime(&v, ev[j], ev[j + 1]));
-                    const int cls = j < h->d.ndim ? j : 3;
-                    ms[cls] += v;
-                    cnt[cls] += 1;
+                    ms[j] += v;
+                    cnt[j] += 1;
                 }
             }
             Ctrl c;

@@ -5,15 +5,17 @@
 // Row kernel (x sweep, the contiguous direction).  A wavefront owns a row
 // segment: every lane holds CPL consecutive cells loaded with one 16-byte
 // vector load per field, solves the CPL interfaces at the left faces of its
-// cells and exchanges the missing neighbours (left cell, neighbouring waves,
-// the next lane's left-cell contribution) with the adjacent lanes, so each
-// interface is solved once.  The first and last lane of a wave only supply
-// halo interfaces; neighbouring waves overlap by 2 * CPL cells.
+// cells and takes what it misses (left neighbour cell, neighbouring waves,
+// the next lane's left-cell contribution) from the adjacent lanes with DPP
+// wave shifts, so each interface is solved once.  The first and last lane
+// of a wave only supply halo interfaces; neighbouring waves overlap by
+// 2 * CPL cells.  The four wavefronts of a workgroup take four rows.
 //
 // Column kernel (y and z sweeps).  A wavefront owns 64 adjacent columns (one
 // per lane, coalesced rows) and marches along the sweep direction over a
-// chunk of rows with a rolling register window, so each interface is solved
-// once per chunk; rows are prefetched PF rows ahead.
+// chunk of cells with a rolling register window, so each interface is solved
+// once per chunk; rows are prefetched PF rows ahead.  The column kernel that
+// closes a step also runs the CFL control in its last workgroup.
 //
 // Ghost cells are never stored: a cell index outside the grid is mapped to its
 // source cell by the boundary rule (section 4.1) when it is loaded.
@@ -27,53 +29,14 @@ struct VecOf {
     typedef R type __attribute__((ext_vector_type(CPL)));
 };
 
-// Loads the MEQN fields (plus derived coefficients for SYS_ACV) of the cells
-// xl .. xl+CPL-1 of a row into q / zc with ghost mapping at the row ends.
-template <typename R, int SYS, int MEQN, int CPL>
-__device__ __forceinline__ void row_load(const R* __restrict__ src, const R* __restrict__ zcg,
-                                         int64_t ncell, int64_t base, int64_t xl, int64_t nx,
-                                         int bc_lo, int bc_hi, bool vec_ok, R (&q)[CPL][MEQN],
-                                         R (&zc)[CPL][2]) {
-    if (vec_ok && xl >= 0 && xl + CPL <= nx) {
-        typedef typename VecOf<R, CPL>::type V;
-#pragma unroll
-        for (int e = 0; e < MEQN; ++e) {
-            V v = *reinterpret_cast<const V*>(src + e * ncell + base + xl);
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
-        }
-        if constexpr (SYS == SYS_ACV) {
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                V v = *reinterpret_cast<const V*>(zcg + f * ncell + base + xl);
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
-            }
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            bool flip;
-            int64_t s = ghost_src(xl + c, nx, bc_lo, bc_hi, flip);
-#pragma unroll
-            for (int e = 0; e < MEQN; ++e) q[c][e] = src[e * ncell + base + s];
-            if (flip) q[c][1] = -q[c][1];
-            if constexpr (SYS == SYS_ACV) {
-                zc[c][0] = zcg[base + s];
-                zc[c][1] = zcg[ncell + base + s];
-            }
-        }
-    }
-}
-
 template <typename R, int SYS, int MEQN>
 __device__ __forceinline__ void make_cell(const R (&q)[MEQN], const R (&zc)[2], int nrm, int tng,
-                                          R g, bool& bad, Cell<R, SYS>& c) {
+                                          R sg, bool& bad, Cell<R, SYS>& c) {
     if constexpr (SYS == SYS_SW) {
         c.h = q[0];
         c.mn = q[nrm];
         c.mt = q[tng];
-        c.derive(g, bad);
+        c.derive(sg, bad);
     } else if constexpr (SYS == SYS_ACV) {
         c.p = q[0];
         c.un = q[nrm];
@@ -110,14 +73,15 @@ __device__ __forceinline__ void cell_prev(const Cell<R, SYS>& in, Cell<R, SYS>& 
 template <typename R, int SYS, int MEQN>
 __device__ __forceinline__ void apply_update(R (&q)[MEQN], const R (&Rl)[3], const R (&Lr)[3],
                                              R nu, int nrm, int tng) {
-    if constexpr (SYS == SYS_SW) {
-        q[0] = q[0] - nu * (Rl[0] + Lr[0]);
-        q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
-        q[tng] = q[tng] - nu * (Rl[2] + Lr[2]);
-    } else {
-        q[0] = q[0] - nu * (Rl[0] + Lr[0]);
-        q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
-    }
+    q[0] = q[0] - nu * (Rl[0] + Lr[0]);
+    q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
+    if constexpr (SYS == SYS_SW) q[tng] = q[tng] - nu * (Rl[2] + Lr[2]);
+}
+
+template <typename R, int SYS>
+__device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
+    if constexpr (SYS == SYS_AC) return frcp(a.Z0 + a.Z0);
+    return R(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -127,6 +91,7 @@ template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS>
 __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
+    typedef typename VecOf<R, CPL>::type V;
     Ctrl* ctrl = a.ctrl;
     if (ctrl->done) return;
     const int cur = ctrl->cur;
@@ -134,43 +99,71 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
     R* __restrict__ dst = a.buf[(cur + a.dst_off) % 3];
     const R nu = ctrl_nu<R>(ctrl, 0);
     const int lane = threadIdx.x & 63;
-    const int64_t P = 62 * CPL;
-    const int64_t nx = a.nx;
-    const int64_t segs = (nx + P - 1) / P;
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const bool active = gw < a.nrows * segs;
-    const int64_t row = active ? gw / segs : 0;
-    const int64_t seg = active ? gw % segs : 0;
-    const int64_t x0 = seg * P;
-    const int64_t xl = x0 - CPL + (int64_t)lane * CPL;
-    const int64_t base = row * nx;
+    const int nx = a.nx;
+    const int row = (int)(blockIdx.y + blockIdx.z * gridDim.y) * 4 + (int)(threadIdx.x >> 6);
+    const bool active = row < a.nrows;
+    const int x0 = (int)blockIdx.x * (62 * CPL);
+    const int xl = x0 - CPL + lane * CPL;
+    const unsigned base = (unsigned)((active ? row : 0) * nx);
     const bool vec_ok = (nx % CPL) == 0 && (a.ncell % CPL) == 0;
+    const bool interior = vec_ok && xl >= 0 && xl + CPL <= nx;
+    const R inv2Z = ac_inv2Z<R, SYS>(a);
     constexpr int nrm = 1, tng = 2;
 
+    // load the lane's cells (ghost cells synthesised at the row ends)
     R q[CPL][MEQN];
     R zc[CPL][2];
-    row_load<R, SYS, MEQN, CPL>(src, a.zc, a.ncell, base, xl, nx, a.bc_lo, a.bc_hi, vec_ok, q, zc);
+    if (interior) {
+#pragma unroll
+        for (int e = 0; e < MEQN; ++e) {
+            V v = *reinterpret_cast<const V*>(src + (size_t)e * a.ncell + base + (unsigned)xl);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
+        }
+        if constexpr (SYS == SYS_ACV) {
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                V v = *reinterpret_cast<const V*>(a.zc + (size_t)f * a.ncell + base + (unsigned)xl);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            bool flip;
+            const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
+#pragma unroll
+            for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
+            if (flip) q[c][nrm] = -q[c][nrm];
+            if constexpr (SYS == SYS_ACV) {
+                zc[c][0] = a.zc[sidx];
+                zc[c][1] = a.zc[(size_t)a.ncell + sidx];
+            }
+        }
+    }
 
     bool bad = false;
     C cell[CPL];
 #pragma unroll
-    for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.grav, bad, cell[c]);
+    for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.sqrt_grav, bad, cell[c]);
     if (!active) bad = false;
 
     // interfaces at the left face of each cell of this lane
     C left;
     cell_prev(cell[CPL - 1], left);
     I f[CPL];
-    riemann(left, cell[0], a.Z0, a.c0, a.grav, a.efix, f[0]);
+    riemann(left, cell[0], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[0]);
 #pragma unroll
-    for (int c = 1; c < CPL; ++c) riemann(cell[c - 1], cell[c], a.Z0, a.c0, a.grav, a.efix, f[c]);
+    for (int c = 1; c < CPL; ++c) riemann(cell[c - 1], cell[c], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[c]);
 
     // largest speed over the interfaces j = x, 0 <= j <= nx, owned by lanes 1..62
+    // (and by lane 63 for j = nx when the row ends exactly at its first cell)
     R sm = R(0);
     if (active) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const int64_t j = xl + c;
+            const int j = xl + c;
             const bool own = (lane >= 1 && lane <= 62 && j >= 0 && j <= nx) ||
                              (lane == 63 && c == 0 && j == nx);
             if (own) sm = rmax(sm, iface_smax(f[c]));
@@ -197,27 +190,27 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
             else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nu, nrm, tng);
         }
         if (active && lane >= 1 && lane <= 62) {
-            if (vec_ok && xl + CPL <= nx) {
-                typedef typename VecOf<R, CPL>::type V;
+            if (interior) {
 #pragma unroll
                 for (int e = 0; e < MEQN; ++e) {
                     V v;
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) v[c] = q[c][e];
-                    *reinterpret_cast<V*>(dst + e * a.ncell + base + xl) = v;
+                    *reinterpret_cast<V*>(dst + (size_t)e * a.ncell + base + (unsigned)xl) = v;
                 }
             } else {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) {
                     if (xl + c < nx) {
 #pragma unroll
-                        for (int e = 0; e < MEQN; ++e) dst[e * a.ncell + base + xl + c] = q[c][e];
+                        for (int e = 0; e < MEQN; ++e)
+                            dst[(size_t)e * a.ncell + base + (unsigned)(xl + c)] = q[c][e];
                     }
                 }
             }
         }
     }
-    block_publish_smax(ctrl, 0, sm, bad);
+    block_finish(a, 0, sm, bad, false);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,26 +224,27 @@ struct ColCell {
 
 template <typename R, int SYS, int MEQN, int NRM>
 __device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __restrict__ zcg,
-                                         int64_t ncell, int64_t colbase, int64_t y, int64_t m,
-                                         int64_t stride, int bc_lo, int bc_hi,
+                                         const SweepArgs<R>& a, int colbase, int y,
                                          ColCell<R, SYS, MEQN>& out) {
     bool flip;
-    const int64_t s = ghost_src(y, m, bc_lo, bc_hi, flip);
-    const int64_t off = colbase + s * stride;
+    const unsigned off = (unsigned)(colbase + ghost_idx(y, a.m, a.bc_lo, a.bc_hi, flip) * a.stride);
 #pragma unroll
-    for (int e = 0; e < MEQN; ++e) out.q[e] = src[e * ncell + off];
+    for (int e = 0; e < MEQN; ++e) out.q[e] = src[(size_t)e * a.ncell + off];
     if (flip) out.q[NRM] = -out.q[NRM];
     if constexpr (SYS == SYS_ACV) {
         out.zc[0] = zcg[off];
-        out.zc[1] = zcg[ncell + off];
+        out.zc[1] = zcg[(size_t)a.ncell + off];
     }
 }
 
-template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
+// KIND: 0 sweep, 1 speed-only pass, 2 sweep that closes a step (runs the
+// step control in its last workgroup)
+template <typename R, int SYS, int MEQN, int NRM, int PF, int KIND>
 __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
     using CC = ColCell<R, SYS, MEQN>;
+    constexpr bool SPEEDS = KIND == 1;
     constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
     Ctrl* ctrl = a.ctrl;
     if (ctrl->done) return;
@@ -259,44 +253,40 @@ __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
     R* __restrict__ dst = a.buf[(cur + a.dst_off) % 3];
     const int dir = a.dir;
     const R nu = ctrl_nu<R>(ctrl, dir);
+    const R inv2Z = ac_inv2Z<R, SYS>(a);
     const int lane = threadIdx.x & 63;
-    const int64_t nx = a.nx, m = a.m, chunk = a.chunk;
-    const int64_t nstrip = (nx + 63) / 64;
-    const int64_t nchunk = (m + chunk - 1) / chunk;
-    const int64_t gw = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const bool active = gw < nstrip * nchunk * a.nlines_o;
-    const int64_t strip = active ? gw % nstrip : 0;
-    const int64_t t = active ? gw / nstrip : 0;
-    const int64_t ck = t % nchunk;
-    const int64_t o = t / nchunk;
-    const int64_t x = strip * 64 + lane;
-    const bool xin = active && x < nx;
-    const int64_t colbase = o * a.ostride + (x < nx ? x : nx - 1);
-    const int64_t y0 = ck * chunk;
-    const int64_t y1 = active ? (y0 + chunk < m ? y0 + chunk : m) : y0;
+    const int nx = a.nx, m = a.m;
+    const int nstrip = (nx + 63) >> 6;
+    const int strip = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const bool sactive = strip < nstrip;
+    const int x = strip * 64 + lane;
+    const bool xin = sactive && x < nx;
+    const int colbase = (int)blockIdx.z * a.ostride + (x < nx ? x : nx - 1);
+    const int y0 = (int)blockIdx.y * a.chunk;
+    const int y1 = sactive ? (y0 + a.chunk < m ? y0 + a.chunk : m) : y0;
 
     bool bad = false;
     R sm = R(0);
     CC w0, w1;  // cells y and y+1 of the window
-    C c0, c1;
+    C c1;
     I fb, fc;   // interfaces j = y and j = y + 1
     R Rb[3];    // right-cell contribution of interface j = y
     {
         CC wm2, wm1;
-        C cm2, cm1;
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, y0 - 2, m, a.stride, a.bc_lo, a.bc_hi, wm2);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, y0 - 1, m, a.stride, a.bc_lo, a.bc_hi, wm1);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, y0, m, a.stride, a.bc_lo, a.bc_hi, w0);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, y0 + 1, m, a.stride, a.bc_lo, a.bc_hi, w1);
-        make_cell<R, SYS, MEQN>(wm2.q, wm2.zc, NRM, TNG, a.grav, bad, cm2);
-        make_cell<R, SYS, MEQN>(wm1.q, wm1.zc, NRM, TNG, a.grav, bad, cm1);
-        make_cell<R, SYS, MEQN>(w0.q, w0.zc, NRM, TNG, a.grav, bad, c0);
-        make_cell<R, SYS, MEQN>(w1.q, w1.zc, NRM, TNG, a.grav, bad, c1);
+        C cm2, cm1, c0;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 2, wm2);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 1, wm1);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0, w0);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 + 1, w1);
+        make_cell<R, SYS, MEQN>(wm2.q, wm2.zc, NRM, TNG, a.sqrt_grav, bad, cm2);
+        make_cell<R, SYS, MEQN>(wm1.q, wm1.zc, NRM, TNG, a.sqrt_grav, bad, cm1);
+        make_cell<R, SYS, MEQN>(w0.q, w0.zc, NRM, TNG, a.sqrt_grav, bad, c0);
+        make_cell<R, SYS, MEQN>(w1.q, w1.zc, NRM, TNG, a.sqrt_grav, bad, c1);
         I fa;
-        riemann(cm2, cm1, a.Z0, a.c0, a.grav, a.efix, fa);
-        riemann(cm1, c0, a.Z0, a.c0, a.grav, a.efix, fb);
-        riemann(c0, c1, a.Z0, a.c0, a.grav, a.efix, fc);
-        if (xin && y0 == 0) sm = rmax(sm, iface_smax(fb));
+        riemann(cm2, cm1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fa);
+        riemann(cm1, c0, a.Z0, a.c0, inv2Z, a.grav, a.efix, fb);
+        riemann(c0, c1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fc);
+        if (y0 == 0) sm = iface_smax(fb);
         if constexpr (!SPEEDS) {
             Contrib<R> kb;
             limit_contrib(fb, fa, fc, nu, a.limiter, kb);
@@ -305,102 +295,115 @@ __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
         }
     }
 
-    // prefetch ring: pre[k] holds row y + 2 + k at the top of each group
+    // prefetch ring: pre[k] holds row y + 2 + k at the top of each group;
+    // refills past the last needed row (y1 + 1) reload that row instead
+    const int ylast = y1 + 1;
     CC pre[PF];
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
-        if (y0 + 2 + k < y1 + 2)
-            col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, y0 + 2 + k, m, a.stride, a.bc_lo, a.bc_hi, pre[k]);
+        const int r = y0 + 2 + k;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, pre[k]);
     }
 
-    for (int64_t y = y0; y < y1; y += PF) {
+    // one row of the march: cell yy is finished, the window moves down by one
+    auto step = [&](int yy, CC& slot) {
+        CC w2 = slot;
+        const int r = yy + 2 + PF;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, slot);
+        C c2;
+        make_cell<R, SYS, MEQN>(w2.q, w2.zc, NRM, TNG, a.sqrt_grav, bad, c2);
+        I fd;
+        riemann(c1, c2, a.Z0, a.c0, inv2Z, a.grav, a.efix, fd);
+        sm = rmax(sm, iface_smax(fc));
+        if constexpr (!SPEEDS) {
+            Contrib<R> kc;
+            limit_contrib(fc, fb, fd, nu, a.limiter, kc);
+            apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
+            if (xin) {
+                const unsigned off = (unsigned)(colbase + yy * a.stride);
 #pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int64_t yy = y + k;
-            if (yy < y1) {
-                CC w2 = pre[k];
-                if (yy + 2 + PF < y1 + 2)
-                    col_load<R, SYS, MEQN, NRM>(src, a.zc, a.ncell, colbase, yy + 2 + PF, m, a.stride, a.bc_lo, a.bc_hi, pre[k]);
-                C c2;
-                make_cell<R, SYS, MEQN>(w2.q, w2.zc, NRM, TNG, a.grav, bad, c2);
-                I fd;
-                riemann(c1, c2, a.Z0, a.c0, a.grav, a.efix, fd);
-                if (xin) sm = rmax(sm, iface_smax(fc));
-                if constexpr (!SPEEDS) {
-                    Contrib<R> kc;
-                    limit_contrib(fc, fb, fd, nu, a.limiter, kc);
-                    apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
-                    if (xin) {
-                        const int64_t off = colbase + yy * a.stride;
-#pragma unroll
-                        for (int e = 0; e < MEQN; ++e) dst[e * a.ncell + off] = w0.q[e];
-                    }
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) Rb[i] = kc.Rr[i];
-                }
-                fb = fc;
-                fc = fd;
-                w0 = w1;
-                w1 = w2;
-                c1 = c2;
+                for (int e = 0; e < MEQN; ++e) dst[(size_t)e * a.ncell + off] = w0.q[e];
             }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Rb[i] = kc.Rr[i];
         }
+        fb = fc;
+        fc = fd;
+        w0 = w1;
+        w1 = w2;
+        c1 = c2;
+    };
+
+    int y = y0;
+    for (; y + PF <= y1; y += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) step(y + k, pre[k]);
     }
-    if (!active) bad = false;
-    block_publish_smax(ctrl, dir, sm, bad);
+    if (y < y1) {  // ragged end of the last chunk
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (y + k < y1) step(y + k, pre[k]);
+    }
+    if (!xin) {
+        bad = false;
+        sm = R(0);
+    }
+    block_finish(a, dir, sm, bad, KIND == 2);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 template <typename R, int SYS, int MEQN, bool SPEEDS>
 static hipError_t launch_row(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
-    const int64_t P = 62 * CPL;
-    const int64_t waves = a.nrows * ceil_div(a.nx, P);
-    const int64_t blocks = ceil_div(waves, 4);
-    hipLaunchKernelGGL((k_sweep_row<R, SYS, MEQN, CPL, SPEEDS>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const int segs = ceil_div(a.nx, 62 * CPL);
+    const int groups = ceil_div(a.nrows, 4);
+    const int gy = groups < 32768 ? groups : 32768;
+    const int gz = ceil_div(groups, gy);
+    hipLaunchKernelGGL((k_sweep_row<R, SYS, MEQN, CPL, SPEEDS>), dim3(segs, gy, gz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R, int SYS, int MEQN, int NRM, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int NRM, int KIND>
 static hipError_t launch_col(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int PF = 4;
-    const int64_t waves = ceil_div(a.nx, 64) * ceil_div(a.m, a.chunk) * a.nlines_o;
-    const int64_t blocks = ceil_div(waves, 4);
-    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, SPEEDS>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    const dim3 grid(ceil_div(ceil_div(a.nx, 64), 4), ceil_div(a.m, a.chunk), a.nlines_o);
+    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, KIND>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R, int SYS, int MEQN, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int KIND>
 static hipError_t launch_dir(const SweepArgs<R>& a, hipStream_t s) {
-    if (a.dir == 0) return launch_row<R, SYS, MEQN, SPEEDS>(a, s);
-    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, SPEEDS>(a, s);
-    if constexpr (MEQN == 4) return launch_col<R, SYS, MEQN, 3, SPEEDS>(a, s);
+    if (a.dir == 0) {
+        if constexpr (KIND == 2) return hipErrorInvalidValue;  // x never closes a step
+        return launch_row<R, SYS, MEQN, KIND == 1>(a, s);
+    }
+    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, KIND>(a, s);
+    if constexpr (MEQN == 4) return launch_col<R, SYS, MEQN, 3, KIND>(a, s);
     return hipErrorInvalidValue;
+}
+
+template <typename R, int SYS, int MEQN>
+static hipError_t launch_kind(const SweepArgs<R>& a, int kind, hipStream_t s) {
+    if (kind == 1) return launch_dir<R, SYS, MEQN, 1>(a, s);
+    if (kind == 2) return launch_dir<R, SYS, MEQN, 2>(a, s);
+    return launch_dir<R, SYS, MEQN, 0>(a, s);
 }
 
 template <typename R>
-hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds_only, hipStream_t s) {
-    if (sys == SYS_SW) {
-        if (meqn != 3) return hipErrorInvalidValue;
-        return speeds_only ? launch_dir<R, SYS_SW, 3, true>(a, s) : launch_dir<R, SYS_SW, 3, false>(a, s);
-    }
-    if (sys == SYS_AC) {
-        if (meqn == 3) return speeds_only ? launch_dir<R, SYS_AC, 3, true>(a, s) : launch_dir<R, SYS_AC, 3, false>(a, s);
-        if (meqn == 4) return speeds_only ? launch_dir<R, SYS_AC, 4, true>(a, s) : launch_dir<R, SYS_AC, 4, false>(a, s);
-        return hipErrorInvalidValue;
-    }
-    if (sys == SYS_ACV) {
-        if (meqn == 3) return speeds_only ? launch_dir<R, SYS_ACV, 3, true>(a, s) : launch_dir<R, SYS_ACV, 3, false>(a, s);
-        if (meqn == 4) return speeds_only ? launch_dir<R, SYS_ACV, 4, true>(a, s) : launch_dir<R, SYS_ACV, 4, false>(a, s);
-    }
+hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, int kind, hipStream_t s) {
+    if (sys == SYS_SW && meqn == 3) return launch_kind<R, SYS_SW, 3>(a, kind, s);
+    if (sys == SYS_AC && meqn == 3) return launch_kind<R, SYS_AC, 3>(a, kind, s);
+    if (sys == SYS_AC && meqn == 4) return launch_kind<R, SYS_AC, 4>(a, kind, s);
+    if (sys == SYS_ACV && meqn == 3) return launch_kind<R, SYS_ACV, 3>(a, kind, s);
+    if (sys == SYS_ACV && meqn == 4) return launch_kind<R, SYS_ACV, 4>(a, kind, s);
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, bool, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, bool, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, int, hipStream_t);
 
 }  // namespace claw

@@ -265,7 +265,7 @@ def test_graph_path_equals_eager_path_bitwise(claw):
     s1.advance(70)
     s2, q2 = _solver(claw, prob, q0)
     ms, cnt = s2.advance_timed(70)
-    assert cnt[0] == cnt[1] == cnt[3] >= 70
+    assert cnt[0] == cnt[1] >= 70 and cnt[3] == 0
     assert np.array_equal(_host(q1), _host(q2))
 
 
