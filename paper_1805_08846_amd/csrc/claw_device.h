@@ -31,28 +31,41 @@ enum { LIM_MC = 0, LIM_NONE = 1, LIM_FIRST = 2 };
 // per-cell coefficients, shallow water
 enum { SYS_AC = 0, SYS_ACV = 1, SYS_SW = 2 };
 
+// Step state a trial step runs with.  The control block keeps one copy per
+// trial parity: the first sweep of trial k decides trial k-1 from copy
+// (k-1)&1 and the speed maxima of trial k-1, and writes the result to copy k&1
+// for the remaining sweeps of trial k (section 4.1: the CFL number of the
+// previous step decides accept / revert and the next time step).
+struct StepState {
+    double t;          // simulation time of the current state
+    double dt;         // time step of this trial
+    double dt_next;    // min(dt_max, cfl_desired / sigma) of the last decided trial
+    double cfl;        // Courant number of the last decided trial
+    double dtdx[3];    // dt / dx_d
+    float dtdx_f[3];   // the same rounded once to FP32
+    int32_t cur;       // rotation buffer holding the current state
+    int32_t done;      // nonzero: the requested steps are complete (sweeps skip)
+    int32_t err;       // claw_status of a failure that stopped the run
+    int32_t last_accepted;
+    int32_t pending;   // 1: this trial ran and is not decided yet
+    int32_t mode;      // MODE_* of the trial
+    int32_t result_off;  // buffer offset of the trial's result
+    int32_t pad;
+    long long accepted, rejected, target, consecutive, trials;
+};
+
 // Device control block: step-control state that lives on the GPU so that a
 // captured graph can run many steps without the host.
 struct alignas(256) Ctrl {
-    double t;          // simulation time of the current state
-    double dt;         // time step of the trial in flight
-    double dt_next;    // proposal for the next trial
-    double cfl;        // Courant number of the last trial
-    double dtdx[3];    // dt / dx_d of the trial in flight
-    float dtdx_f[3];   // the same rounded once to FP32
-    int32_t mode;      // control mode of the run in flight
-    double dx[3];
-    double cfl_desired, cfl_max, dt_max;
-    unsigned long long smax64[3];  // per-direction max |s| (FP64 bit pattern)
-    unsigned int smax32[3];        // per-direction max |s| (FP32 bit pattern)
-    int32_t cur;       // rotation buffer holding the current state
-    int32_t done;      // nonzero: the requested steps are complete (sweeps skip)
-    int32_t nonphys;   // set by a sweep that met depth <= 0 or NaN
-    int32_t err;       // claw_status of a failure that stopped the run
-    int32_t last_accepted;
+    StepState st[2];
+    unsigned long long smax64[2][4];  // per parity and direction: max |s| (FP64 bits)
+    unsigned int smax32[2][4];        // the same for FP32 kernels
+    int32_t nonphys[2];               // per parity: a sweep met depth <= 0 or NaN
     int32_t ndim;
-    long long accepted, rejected, target, consecutive, trials;
-    unsigned int blocks_done;  // workgroups finished in the sweep that closes a step
+    int32_t pad;
+    double dx[3];
+    double inv_dx[3];   // 1 / dx_d, so a decision costs one division
+    double cfl_desired, cfl_max, dt_max;
 };
 
 // Per-launch arguments of a sweep kernel (passed by value).  Element
@@ -76,8 +89,10 @@ struct SweepArgs {
     int32_t bc_lo, bc_hi;
     int32_t limiter;
     int32_t efix;
-    int32_t result_off; // fused step control: buffer offset of the step's result
-    int32_t ctrl_mode;  // fused step control: MODE_* of the run
+    int32_t parity;     // trial parity: step-state copy and speed slots in use
+    int32_t first;      // this sweep opens a trial (decides the previous one)
+    int32_t last;       // this sweep closes a trial (clears the other parity's slots)
+    int32_t pad;
     R grav;
     R sqrt_grav;
     R Z0, c0;           // constant-coefficient acoustics
@@ -478,54 +493,50 @@ __device__ __forceinline__ R wave_max(R v) {
 // patterns, so an unsigned atomic max is exact and order independent.  A
 // cached read first skips the atomic when a larger value is already known
 // (a stale read only costs an unneeded atomic).
-__device__ __forceinline__ void publish_smax(Ctrl* c, int dir, float v) {
+__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, float v) {
     const unsigned bits = __float_as_uint(v);
-    if (bits > __atomic_load_n(&c->smax32[dir], __ATOMIC_RELAXED)) atomicMax(&c->smax32[dir], bits);
+    unsigned* p = &c->smax32[par][dir];
+    if (bits > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, bits);
 }
-__device__ __forceinline__ void publish_smax(Ctrl* c, int dir, double v) {
+__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, double v) {
     const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    if (bits > __atomic_load_n(&c->smax64[dir], __ATOMIC_RELAXED)) atomicMax(&c->smax64[dir], bits);
+    unsigned long long* p = &c->smax64[par][dir];
+    if (bits > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, bits);
 }
 
 template <typename R>
-__device__ __forceinline__ R ctrl_nu(const Ctrl* c, int dir);
+__device__ __forceinline__ R state_nu(const StepState& s, int dir);
 template <>
-__device__ __forceinline__ float ctrl_nu<float>(const Ctrl* c, int dir) { return c->dtdx_f[dir]; }
+__device__ __forceinline__ float state_nu<float>(const StepState& s, int dir) { return s.dtdx_f[dir]; }
 template <>
-__device__ __forceinline__ double ctrl_nu<double>(const Ctrl* c, int dir) { return c->dtdx[dir]; }
+__device__ __forceinline__ double state_nu<double>(const StepState& s, int dir) { return s.dtdx[dir]; }
 
 enum { MODE_ADAPT = 0, MODE_STEP = 1, MODE_FIXED = 2 };
 
 // ---------------------------------------------------------------------------
 // Step control (section 4.1; equation CFL-condition): Courant number from the
-// per-direction speed maxima, accept or revert, next trial step.  Runs in one
-// thread, either in the last workgroup of the sweep that closes a step or in
-// a one-thread kernel.
+// per-direction speed maxima, accept or revert, next trial step.  decide() is
+// a pure function of the control block, evaluated identically by every
+// wavefront of the sweep that opens the next trial (and by a one-thread
+// commit kernel at the end of a host call).  It multiplies by 1/dx instead of
+// dividing by dx (a last-bit difference in sigma and dt/dx) so that the
+// decision costs one FP64 division.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void set_trial_dt(Ctrl* c, double dt) {
-    c->dt = dt;
+__device__ __forceinline__ void set_trial_dt(const Ctrl* c, StepState& s, double dt) {
+    s.dt = dt;
     for (int d = 0; d < 3; ++d) {
-        double v = d < c->ndim ? dt / c->dx[d] : 0.0;
-        c->dtdx[d] = v;
-        c->dtdx_f[d] = (float)v;
-        c->smax32[d] = 0u;
-        c->smax64[d] = 0ull;
+        const double v = d < c->ndim ? dt * c->inv_dx[d] : 0.0;
+        s.dtdx[d] = v;
+        s.dtdx_f[d] = (float)v;
     }
-    c->nonphys = 0;
 }
 
-// Reads of values other workgroups updated with atomics: coherent atomic
-// reads inside the kernel that produced them, plain loads in a later kernel.
-__device__ __forceinline__ double smax_of(Ctrl* c, int d, bool fp32, bool same_kernel) {
-    if (fp32)
-        return (double)__uint_as_float(same_kernel ? atomicMax(&c->smax32[d], 0u) : c->smax32[d]);
-    return __longlong_as_double((long long)(same_kernel ? atomicMax(&c->smax64[d], 0ull) : c->smax64[d]));
-}
-
-__device__ __forceinline__ double sigma_of(Ctrl* c, bool fp32, bool same_kernel = false) {
+__device__ __forceinline__ double sigma_of(const Ctrl* c, int q, bool fp32) {
     double sigma = 0.0;
     for (int d = 0; d < c->ndim; ++d) {
-        double v = smax_of(c, d, fp32, same_kernel) / c->dx[d];
+        const double sm = fp32 ? (double)__uint_as_float(c->smax32[q][d])
+                               : __longlong_as_double((long long)c->smax64[q][d]);
+        const double v = sm * c->inv_dx[d];
         if (v > sigma) sigma = v;
     }
     return sigma;
@@ -534,7 +545,7 @@ __device__ __forceinline__ double sigma_of(Ctrl* c, bool fp32, bool same_kernel 
 // next trial step min(dt_max, cfl_desired / sigma); false if none exists
 __device__ __forceinline__ bool next_dt(const Ctrl* c, double sigma, double* dt) {
     if (sigma > 0.0) {
-        double v = c->cfl_desired / sigma;
+        const double v = c->cfl_desired / sigma;
         *dt = v < c->dt_max ? v : c->dt_max;
         return true;
     }
@@ -545,53 +556,96 @@ __device__ __forceinline__ bool next_dt(const Ctrl* c, double sigma, double* dt)
     return false;
 }
 
-__device__ __forceinline__ void control_step(Ctrl* c, int result_off, int mode, bool fp32,
-                                             bool same_kernel) {
-    if (c->done) return;
-    const double sigma = sigma_of(c, fp32, same_kernel);
-    const double cfl = c->dt * sigma;
-    c->cfl = cfl;
-    c->trials += 1;
-    if (same_kernel ? atomicOr(&c->nonphys, 0) : c->nonphys) {  // the state stays Q^n
-        c->err = 5;
-        c->done = 1;
-        c->last_accepted = 0;
-        c->rejected += 1;
+// N = state after deciding the trial recorded in copy q (unchanged if none pending).
+__device__ __forceinline__ void decide(const Ctrl* c, int q, bool fp32, StepState& N) {
+    N = c->st[q];
+    if (!N.pending) return;
+    N.pending = 0;
+    if (N.done) return;
+    const double sigma = sigma_of(c, q, fp32);
+    const double cfl = N.dt * sigma;
+    N.cfl = cfl;
+    N.trials += 1;
+    if (c->nonphys[q]) {  // the state stays Q^n
+        N.err = 5;
+        N.done = 1;
+        N.last_accepted = 0;
+        N.rejected += 1;
         return;
     }
-    const bool accept = mode == MODE_FIXED ? true : (cfl <= c->cfl_max);
+    const bool accept = N.mode == MODE_FIXED ? true : (cfl <= c->cfl_max);
     if (accept) {
-        c->cur = (c->cur + result_off) % 3;
-        c->t += c->dt;
-        c->accepted += 1;
-        c->consecutive = 0;
+        N.cur = (N.cur + N.result_off) % 3;
+        N.t += N.dt;
+        N.accepted += 1;
+        N.consecutive = 0;
     } else {
-        c->rejected += 1;
-        c->consecutive += 1;
-        if (c->consecutive > 64) {
-            c->err = 6;
-            c->done = 1;
+        N.rejected += 1;
+        N.consecutive += 1;
+        if (N.consecutive > 64) {
+            N.err = 6;
+            N.done = 1;
         }
     }
-    c->last_accepted = accept ? 1 : 0;
+    N.last_accepted = accept ? 1 : 0;
     double dtn = 0.0;
     if (!next_dt(c, sigma, &dtn)) {
-        c->err = 6;
-        c->done = 1;
+        N.err = 6;
+        N.done = 1;
         return;
     }
-    c->dt_next = dtn;
-    if (mode == MODE_ADAPT) {
-        set_trial_dt(c, dtn);
-        if (c->accepted >= c->target) c->done = 1;
+    N.dt_next = dtn;
+    if (N.mode == MODE_ADAPT) {
+        set_trial_dt(c, N, dtn);
+        if (N.accepted >= N.target) N.done = 1;
     }
 }
 
-// Block-wide max of v published once per workgroup (blockDim.x a multiple of
-// 64); with close_step the last workgroup to finish runs the step control.
+// What a sweep needs of its trial: buffer index, skip flag, dt/dx.
 template <typename R>
-__device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v, bool bad,
-                                             bool close_step) {
+struct Trial {
+    int cur;
+    int done;
+    R nu;
+};
+
+// Buffer index a trial will use if the previous trial is accepted (or the
+// committed one if nothing is pending): readable before the decision.
+template <typename R>
+__device__ __forceinline__ int predicted_cur(const SweepArgs<R>& a) {
+    if (!a.first) return a.ctrl->st[a.parity].cur;
+    const StepState& P = a.ctrl->st[a.parity ^ 1];
+    return (P.pending && !P.done) ? (P.cur + P.result_off) % 3 : P.cur;
+}
+
+template <typename R>
+__device__ __forceinline__ Trial<R> open_trial(const SweepArgs<R>& a, int dir) {
+    Ctrl* c = a.ctrl;
+    Trial<R> t;
+    if (a.first) {
+        StepState S;
+        decide(c, a.parity ^ 1, sizeof(R) == 4, S);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+            S.pending = S.done ? 0 : 1;
+            c->st[a.parity] = S;
+        }
+        t.cur = S.cur;
+        t.done = S.done;
+        t.nu = state_nu<R>(S, dir);
+    } else {
+        const StepState& S = c->st[a.parity];
+        t.cur = S.cur;
+        t.done = S.done;
+        t.nu = state_nu<R>(S, dir);
+    }
+    return t;
+}
+
+// Block-wide max of v published once per workgroup (blockDim.x a multiple of
+// 64) into the trial's speed slot; the sweep that closes a trial also clears
+// the other parity's slots for the trial after next.
+template <typename R>
+__device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v, bool bad) {
     __shared__ R red[16];
     __shared__ int redbad[16];
     Ctrl* c = a.ctrl;
@@ -610,20 +664,15 @@ __device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v
             m = rmax(m, red[i]);
             b |= redbad[i];
         }
-        publish_smax(c, dir, m);
-        if (b) atomicOr(&c->nonphys, 1);
-        if (close_step) {
-            // The counter increment must not be performed before this
-            // workgroup's maximum and flag: wait for the atomics above to
-            // complete.  All three are device-coherent atomics, so no cache
-            // flush is needed; the state itself is published by the kernel
-            // boundary.
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            const unsigned total = gridDim.x * gridDim.y * gridDim.z;
-            if (atomicAdd(&c->blocks_done, 1u) == total - 1) {
-                c->blocks_done = 0u;
-                control_step(c, a.result_off, a.ctrl_mode, sizeof(R) == 4, true);
+        publish_smax(c, a.parity, dir, m);
+        if (b) atomicOr(&c->nonphys[a.parity], 1);
+        if (a.last && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+            const int o = a.parity ^ 1;
+            for (int d = 0; d < 4; ++d) {
+                c->smax32[o][d] = 0u;
+                c->smax64[o][d] = 0ull;
             }
+            c->nonphys[o] = 0;
         }
     }
 }

@@ -1,8 +1,9 @@
-// control.hip -- one-thread kernels that set up the device control block
-// (trial step, first step from a speed pass, step target) and the small
-// element-wise set-up kernels (derived acoustic coefficients, copy of the
-// state back into q).  The per-step CFL decision itself (section 4.1) runs
-// in the last workgroup of the sweep that closes a step (control_step).
+// control.hip -- one-thread kernels that set up and close the step state of
+// the device control block (trial step, first step from a speed pass, step
+// target, committing the last trial's decision) and the small element-wise
+// set-up kernels (derived acoustic coefficients, copy of the state back into
+// q).  The per-step CFL decision itself (section 4.1) is decide(), evaluated by
+// the sweep that opens the next trial.
 //
 // All step-control scalars stay in the device control block, so a captured
 // graph of many steps runs without any host round trip.
@@ -14,80 +15,98 @@ namespace claw {
 
 __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndim, double cfl_desired,
                             double cfl_max, double dt_max) {
-    c->t = 0.0;
-    c->dt = 0.0;
-    c->dt_next = 0.0;
-    c->cfl = 0.0;
+    for (int q = 0; q < 2; ++q) {
+        StepState& s = c->st[q];
+        s.t = s.dt = s.dt_next = s.cfl = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            s.dtdx[d] = 0.0;
+            s.dtdx_f[d] = 0.0f;
+        }
+        s.cur = s.done = s.err = s.last_accepted = s.pending = s.mode = s.pad = 0;
+        s.result_off = ndim == 2 ? 2 : 1;
+        s.accepted = s.rejected = s.target = s.consecutive = s.trials = 0;
+        for (int d = 0; d < 4; ++d) {
+            c->smax32[q][d] = 0u;
+            c->smax64[q][d] = 0ull;
+        }
+        c->nonphys[q] = 0;
+    }
+    c->ndim = ndim;
     c->dx[0] = dx0;
     c->dx[1] = dx1;
     c->dx[2] = dx2;
-    c->ndim = ndim;
+    c->inv_dx[0] = 1.0 / dx0;
+    c->inv_dx[1] = 1.0 / dx1;
+    c->inv_dx[2] = 1.0 / dx2;
     c->cfl_desired = cfl_desired;
     c->cfl_max = cfl_max;
     c->dt_max = dt_max;
-    c->mode = 0;
-    c->cur = 0;
-    c->done = 0;
-    c->err = 0;
-    c->last_accepted = 0;
-    c->accepted = 0;
-    c->rejected = 0;
-    c->target = 0;
-    c->consecutive = 0;
-    c->trials = 0;
-    c->blocks_done = 0u;
-    set_trial_dt(c, 0.0);
 }
 
-__global__ void k_begin(Ctrl* c, double dt) {
-    set_trial_dt(c, dt);
-    c->done = 0;
-    c->err = 0;
+// Applies a pending decision to copy q and clears the speed slots of the
+// other parity (those the next trial will fill).
+__global__ void k_commit(Ctrl* c, int q, int fp32) {
+    StepState N;
+    decide(c, q, fp32 != 0, N);
+    c->st[q] = N;
+    const int o = q ^ 1;
+    for (int d = 0; d < 4; ++d) {
+        c->smax32[o][d] = 0u;
+        c->smax64[o][d] = 0ull;
+    }
+    c->nonphys[o] = 0;
 }
 
-__global__ void k_begin_speeds(Ctrl* c) {
-    set_trial_dt(c, c->dt);
-    c->done = 0;
-    c->err = 0;
+__global__ void k_begin(Ctrl* c, int q, double dt, int mode, int result_off) {
+    StepState& s = c->st[q];
+    set_trial_dt(c, s, dt);
+    s.mode = mode;
+    s.result_off = result_off;
+    s.done = 0;
+    s.err = 0;
+    s.pending = 0;
 }
 
-// First trial step from the speed-only pass that ran just before.
-__global__ void k_init_dt(Ctrl* c, int fp32) {
+__global__ void k_zero_speeds(Ctrl* c, int q) {
+    for (int d = 0; d < 4; ++d) {
+        c->smax32[q][d] = 0u;
+        c->smax64[q][d] = 0ull;
+    }
+    c->nonphys[q] = 0;
+}
+
+// First trial step from the speed-only pass that filled slot q.
+__global__ void k_init_dt(Ctrl* c, int q, int fp32, int mode, int result_off) {
+    StepState& s = c->st[q];
+    s.mode = mode;
+    s.result_off = result_off;
+    s.pending = 0;
+    s.done = 0;
+    s.err = 0;
+    if (c->nonphys[q]) {
+        s.err = 5;
+        s.done = 1;
+        return;
+    }
     double dt = 0.0;
-    if (c->nonphys) {
-        c->err = 5;
-        c->done = 1;
+    if (!next_dt(c, sigma_of(c, q, fp32 != 0), &dt)) {
+        s.err = 6;
+        s.done = 1;
         return;
     }
-    if (!next_dt(c, sigma_of(c, fp32 != 0), &dt)) {
-        c->err = 6;
-        c->done = 1;
-        return;
-    }
-    set_trial_dt(c, dt);
+    set_trial_dt(c, s, dt);
 }
 
-__global__ void k_set_target(Ctrl* c, long long nsteps) {
-    c->target = c->accepted + nsteps;
-    c->done = nsteps <= 0 ? 1 : 0;
-    c->consecutive = 0;
-    c->err = 0;
+__global__ void k_set_target(Ctrl* c, int q, long long nsteps) {
+    StepState& s = c->st[q];
+    s.target = s.accepted + nsteps;
+    s.done = nsteps <= 0 ? 1 : 0;
+    s.consecutive = 0;
 }
 
-// Step control as its own one-thread kernel (used when the control is not
-// fused into the last sweep).
-__global__ void k_control(Ctrl* c, int result_off, int mode, int fp32) {
-    control_step(c, result_off, mode, fp32 != 0, false);
-}
-
-__global__ void k_accept_sweep(Ctrl* c, int result_off) {
-    if (c->done) return;
-    c->cur = (c->cur + result_off) % 3;
-}
-
-__global__ void k_set_control(Ctrl* c, double t, double dt_next) {
-    c->t = t;
-    c->dt_next = dt_next;
+__global__ void k_set_control(Ctrl* c, int q, double t, double dt_next) {
+    c->st[q].t = t;
+    c->st[q].dt_next = dt_next;
 }
 
 template <typename R>
@@ -101,10 +120,10 @@ __global__ void k_derive_zc(const R* __restrict__ aux, R* __restrict__ zc, int64
     zc[n + i] = sqrt(K / rho);
 }
 
-// Copies the current buffer into buf[0] (the caller's q) when it is elsewhere.
+// Copies the current buffer of copy q into buf[0] (the caller's q) when it is elsewhere.
 template <typename R>
-__global__ void k_sync_state(const Ctrl* c, R* b0, const R* b1, const R* b2, int64_t n) {
-    const int cur = c->cur;
+__global__ void k_sync_state(const Ctrl* c, int q, R* b0, const R* b1, const R* b2, int64_t n) {
+    const int cur = c->st[q].cur;
     if (cur == 0) return;
     const R* src = cur == 1 ? b1 : b2;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -112,7 +131,7 @@ __global__ void k_sync_state(const Ctrl* c, R* b0, const R* b1, const R* b2, int
         b0[i] = src[i];
 }
 
-__global__ void k_reset_cur(Ctrl* c) { c->cur = 0; }
+__global__ void k_reset_cur(Ctrl* c, int q) { c->st[q].cur = 0; }
 
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired, double cfl_max,
                             double dt_max, hipStream_t s) {
@@ -120,32 +139,28 @@ hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desi
                        cfl_max, dt_max);
     return hipGetLastError();
 }
-hipError_t launch_begin(Ctrl* c, double dt, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, c, dt);
+hipError_t launch_commit(Ctrl* c, int q, bool fp32, hipStream_t s) {
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(1), 0, s, c, q, fp32 ? 1 : 0);
     return hipGetLastError();
 }
-hipError_t launch_begin_speeds(Ctrl* c, hipStream_t s) {
-    hipLaunchKernelGGL(k_begin_speeds, dim3(1), dim3(1), 0, s, c);
+hipError_t launch_begin(Ctrl* c, int q, double dt, int mode, int result_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, c, q, dt, mode, result_off);
     return hipGetLastError();
 }
-hipError_t launch_init_dt(Ctrl* c, bool fp32, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, s, c, fp32 ? 1 : 0);
+hipError_t launch_zero_speeds(Ctrl* c, int q, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_speeds, dim3(1), dim3(1), 0, s, c, q);
     return hipGetLastError();
 }
-hipError_t launch_set_target(Ctrl* c, long long nsteps, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, s, c, nsteps);
+hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, s, c, q, fp32 ? 1 : 0, mode, result_off);
     return hipGetLastError();
 }
-hipError_t launch_control(Ctrl* c, int result_off, int mode, bool fp32, hipStream_t s) {
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, s, c, result_off, mode, fp32 ? 1 : 0);
+hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_target, dim3(1), dim3(1), 0, s, c, q, nsteps);
     return hipGetLastError();
 }
-hipError_t launch_accept_sweep(Ctrl* c, int result_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_accept_sweep, dim3(1), dim3(1), 0, s, c, result_off);
-    return hipGetLastError();
-}
-hipError_t launch_set_control(Ctrl* c, double t, double dt_next, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_control, dim3(1), dim3(1), 0, s, c, t, dt_next);
+hipError_t launch_set_control(Ctrl* c, int q, double t, double dt_next, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_control, dim3(1), dim3(1), 0, s, c, q, t, dt_next);
     return hipGetLastError();
 }
 
@@ -158,20 +173,20 @@ hipError_t launch_derive_zc(const R* aux, R* zc, int64_t ncell, hipStream_t s) {
 }
 
 template <typename R>
-hipError_t launch_sync_state(Ctrl* c, R* b0, R* b1, R* b2, int64_t n, hipStream_t s) {
+hipError_t launch_sync_state(Ctrl* c, int q, R* b0, R* b1, R* b2, int64_t n, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_sync_state<R>), dim3((unsigned)blocks), dim3(256), 0, s, c, b0, b1, b2, n);
+    hipLaunchKernelGGL((k_sync_state<R>), dim3((unsigned)blocks), dim3(256), 0, s, c, q, b0, b1, b2, n);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_reset_cur, dim3(1), dim3(1), 0, s, c);
+    hipLaunchKernelGGL(k_reset_cur, dim3(1), dim3(1), 0, s, c, q);
     return hipGetLastError();
 }
 
 template hipError_t launch_derive_zc<float>(const float*, float*, int64_t, hipStream_t);
 template hipError_t launch_derive_zc<double>(const double*, double*, int64_t, hipStream_t);
-template hipError_t launch_sync_state<float>(Ctrl*, float*, float*, float*, int64_t, hipStream_t);
-template hipError_t launch_sync_state<double>(Ctrl*, double*, double*, double*, int64_t, hipStream_t);
+template hipError_t launch_sync_state<float>(Ctrl*, int, float*, float*, float*, int64_t, hipStream_t);
+template hipError_t launch_sync_state<double>(Ctrl*, int, double*, double*, double*, int64_t, hipStream_t);
 
 }  // namespace claw

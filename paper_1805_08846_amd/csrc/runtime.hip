@@ -113,8 +113,9 @@ struct claw_solver {
     void* zc;
     Ctrl* ctrl;
     double dx[3];
-    hipGraphExec_t gexec;
-    hipGraph_t graph;
+    int parity;               // parity of the next trial; copy parity ^ 1 is the committed state
+    hipGraphExec_t gexec[2];  // captured trial sequences, by starting parity
+    hipGraph_t graph[2];
     std::vector<hipEvent_t> events;
 };
 
@@ -172,8 +173,6 @@ SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off)
     a.efix = h->d.efix;
     a.grav = (R)h->d.grav;
     a.sqrt_grav = (R)sqrt(h->d.grav);
-    a.result_off = result_offset(h->d.ndim);
-    a.ctrl_mode = MODE_ADAPT;
     if (h->sys == SYS_AC) {
         a.Z0 = (R)sqrt(h->d.rho * h->d.bulk);
         a.c0 = (R)sqrt(h->d.bulk / h->d.rho);
@@ -192,40 +191,45 @@ SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off)
     return a;
 }
 
-// kind: 0 sweep, 1 speed pass, 2 sweep closing a step with control mode `mode`
-hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, int kind, int mode,
-                         hipStream_t s) {
+// One sweep launch.  speeds: speed-only pass; parity: step-state copy and
+// speed slots; first / last: the sweep opens / closes a trial.
+hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, bool speeds, int parity,
+                         bool first, bool last, hipStream_t s) {
     if (h->fp32) {
         SweepArgs<float> a = sweep_args<float>(h, dir, src_off, dst_off);
-        a.ctrl_mode = mode;
-        return launch_sweep<float>(a, h->sys, h->d.meqn, kind, s);
+        a.parity = parity;
+        a.first = first ? 1 : 0;
+        a.last = last ? 1 : 0;
+        return launch_sweep<float>(a, h->sys, h->d.meqn, speeds, s);
     }
     SweepArgs<double> a = sweep_args<double>(h, dir, src_off, dst_off);
-    a.ctrl_mode = mode;
-    return launch_sweep<double>(a, h->sys, h->d.meqn, kind, s);
+    a.parity = parity;
+    a.first = first ? 1 : 0;
+    a.last = last ? 1 : 0;
+    return launch_sweep<double>(a, h->sys, h->d.meqn, speeds, s);
 }
 
-// One trial step (sweeps + control) on stream s; ev (optional) receives an
-// event before each kernel and one after the last.
-bool fused_control() {
-    static const bool fused = [] {
-        const char* e = getenv("CLAW_FUSED_CONTROL");
-        return e && e[0] == '1';
-    }();
-    return fused;
-}
+int committed(const claw_solver* h) { return h->parity ^ 1; }
 
-claw_status enqueue_trial(claw_solver* h, int mode, hipStream_t s, hipEvent_t* ev) {
-    const bool fused = fused_control();
+// One trial step: the sweeps x, y (, z).  The first decides the previous
+// trial on the device; the trial itself is decided by the next trial's first
+// sweep or by a commit.  ev (optional) receives an event before each sweep and
+// one after the last.
+claw_status enqueue_trial(claw_solver* h, hipStream_t s, hipEvent_t* ev) {
     for (int dir = 0; dir < h->d.ndim; ++dir) {
         int so, dof;
         step_offsets(h->d.ndim, dir, &so, &dof);
-        const bool last = dir == h->d.ndim - 1;
         if (ev) HIP_TRY(hipEventRecord(ev[dir], s));
-        HIP_TRY(enqueue_sweep(h, dir, so, dof, (last && fused) ? 2 : 0, mode, s));
+        HIP_TRY(enqueue_sweep(h, dir, so, dof, false, h->parity, dir == 0, dir == h->d.ndim - 1, s));
     }
     if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim], s));
-    if (!fused) HIP_TRY(launch_control(h->ctrl, result_offset(h->d.ndim), mode, h->fp32, s));
+    h->parity ^= 1;
+    return CLAW_OK;
+}
+
+// Applies the decision of the last trial (if any) to the committed copy.
+claw_status commit(claw_solver* h) {
+    HIP_TRY(launch_commit(h->ctrl, committed(h), h->fp32, h->stream));
     return CLAW_OK;
 }
 
@@ -237,65 +241,87 @@ claw_status read_ctrl(claw_solver* h, Ctrl* out) {
 
 claw_status sync_state(claw_solver* h) {
     if (h->fp32)
-        HIP_TRY(launch_sync_state<float>(h->ctrl, (float*)h->buf[0], (float*)h->buf[1], (float*)h->buf[2],
-                                         h->plan.ncell * h->d.meqn, h->stream));
+        HIP_TRY(launch_sync_state<float>(h->ctrl, committed(h), (float*)h->buf[0], (float*)h->buf[1],
+                                         (float*)h->buf[2], h->plan.ncell * h->d.meqn, h->stream));
     else
-        HIP_TRY(launch_sync_state<double>(h->ctrl, (double*)h->buf[0], (double*)h->buf[1],
+        HIP_TRY(launch_sync_state<double>(h->ctrl, committed(h), (double*)h->buf[0], (double*)h->buf[1],
                                           (double*)h->buf[2], h->plan.ncell * h->d.meqn, h->stream));
     return CLAW_OK;
 }
 
-claw_status speed_pass(claw_solver* h, hipStream_t s) {
-    HIP_TRY(launch_begin_speeds(h->ctrl, s));
-    for (int dir = 0; dir < h->d.ndim; ++dir) HIP_TRY(enqueue_sweep(h, dir, 0, 0, 1, MODE_ADAPT, s));
+// Speed-only pass on the committed state into the committed copy's slots
+// (call after commit()).
+claw_status speed_pass(claw_solver* h) {
+    const int q = committed(h);
+    HIP_TRY(launch_zero_speeds(h->ctrl, q, h->stream));
+    for (int dir = 0; dir < h->d.ndim; ++dir)
+        HIP_TRY(enqueue_sweep(h, dir, 0, 0, true, q, false, false, h->stream));
     return CLAW_OK;
 }
 
-// First trial step of an adaptive run: dt0, else dt_next, else from speeds.
+double smax_value(const claw_solver* h, const Ctrl& c, int q, int dir) {
+    if (h->fp32) {
+        float f;
+        memcpy(&f, &c.smax32[q][dir], 4);
+        return f;
+    }
+    double v;
+    memcpy(&v, &c.smax64[q][dir], 8);
+    return v;
+}
+
+// First trial step of an adaptive run (call after commit()): dt0, else the
+// dt_next of a previous run, else cfl_desired / sigma of a speed pass.
 claw_status begin_adaptive(claw_solver* h, double dt0) {
+    const int q = committed(h);
+    const int roff = result_offset(h->d.ndim);
     if (dt0 > 0) {
-        HIP_TRY(launch_begin(h->ctrl, dt0, h->stream));
+        HIP_TRY(launch_begin(h->ctrl, q, dt0, MODE_ADAPT, roff, h->stream));
         return CLAW_OK;
     }
     Ctrl c;
     claw_status st = read_ctrl(h, &c);
     if (st) return st;
-    if (c.dt_next > 0) {
-        HIP_TRY(launch_begin(h->ctrl, c.dt_next, h->stream));
+    if (c.st[q].dt_next > 0) {
+        HIP_TRY(launch_begin(h->ctrl, q, c.st[q].dt_next, MODE_ADAPT, roff, h->stream));
         return CLAW_OK;
     }
-    st = speed_pass(h, h->stream);
+    st = speed_pass(h);
     if (st) return st;
-    HIP_TRY(launch_init_dt(h->ctrl, h->fp32, h->stream));
+    HIP_TRY(launch_init_dt(h->ctrl, q, h->fp32, MODE_ADAPT, roff, h->stream));
     return CLAW_OK;
 }
 
-claw_status ctrl_status(const Ctrl& c) {
+claw_status ctrl_status(const StepState& c) {
     if (c.err == 5) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
     if (c.err == 6) return fail(CLAW_E_STATE, "step control failed (no usable time step)");
     if (c.err) return fail(CLAW_E_STATE, "step control error %d", c.err);
     return CLAW_OK;
 }
 
+// Graph of kGraphSteps trials starting at the current parity (an even count,
+// so the parity after a replay is the parity before it).
 claw_status ensure_graph(claw_solver* h) {
-    if (h->gexec) return CLAW_OK;
+    const int p = h->parity;
+    if (h->gexec[p]) return CLAW_OK;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     claw_status st = CLAW_OK;
-    for (int k = 0; k < kGraphSteps && st == CLAW_OK; ++k) st = enqueue_trial(h, MODE_ADAPT, h->cap_stream, nullptr);
+    for (int k = 0; k < kGraphSteps && st == CLAW_OK; ++k) st = enqueue_trial(h, h->cap_stream, nullptr);
+    h->parity = p;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
     if (st) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return st;
     }
     if (e != hipSuccess) return fail(CLAW_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
-        h->gexec = nullptr;
+        (void)hipGraphDestroy(g);
+        h->gexec[p] = nullptr;
         return fail(CLAW_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    h->graph = g;
+    h->graph[p] = g;
     return CLAW_OK;
 }
 
@@ -355,6 +381,7 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
     h->buf[2] = ws + p.off_b2;
     h->zc = d->maux ? (void*)(ws + p.off_zc) : nullptr;
     for (int k = 0; k < 3; ++k) h->dx[k] = k < d->ndim ? (d->upper[k] - d->lower[k]) / (double)d->n[k] : 1.0;
+    h->parity = 0;
     hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete h;
@@ -366,7 +393,7 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
         else e = launch_derive_zc<double>((const double*)aux, (double*)h->zc, p.ncell, h->stream);
     }
     if (e != hipSuccess) {
-        hipStreamDestroy(h->cap_stream);
+        (void)hipStreamDestroy(h->cap_stream);
         delete h;
         return fail(CLAW_E_HIP, "set-up kernels failed: %s", hipGetErrorString(e));
     }
@@ -376,23 +403,19 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
 
 claw_status claw_cfl(claw_solver* h, double* sigma, double* smax) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
-    claw_status st = speed_pass(h, h->stream);
+    claw_status st = commit(h);
+    if (!st) st = speed_pass(h);
     if (st) return st;
     Ctrl c;
     st = read_ctrl(h, &c);
     if (st) return st;
-    if (c.nonphys) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
+    const int q = committed(h);
+    if (c.nonphys[q]) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
     double sg = 0;
     for (int k = 0; k < 3; ++k) {
         double v = 0;
         if (k < h->d.ndim) {
-            if (h->fp32) {
-                float f;
-                memcpy(&f, &c.smax32[k], 4);
-                v = f;
-            } else {
-                memcpy(&v, &c.smax64[k], 8);
-            }
+            v = smax_value(h, c, q, k);
             if (v / h->dx[k] > sg) sg = v / h->dx[k];
         }
         if (smax) smax[k] = v;
@@ -404,17 +427,20 @@ claw_status claw_cfl(claw_solver* h, double* sigma, double* smax) {
 claw_status claw_step(claw_solver* h, double dt, double* cfl) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (!(dt > 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be positive and finite");
-    HIP_TRY(launch_begin(h->ctrl, dt, h->stream));
-    claw_status st = enqueue_trial(h, MODE_STEP, h->stream, nullptr);
+    claw_status st = commit(h);
     if (st) return st;
-    if (!cfl) return CLAW_OK;
+    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_STEP, result_offset(h->d.ndim), h->stream));
+    st = enqueue_trial(h, h->stream, nullptr);
+    if (!st) st = commit(h);
+    if (st || !cfl) return st;
     Ctrl c;
     st = read_ctrl(h, &c);
     if (st) return st;
-    *cfl = c.cfl;
-    st = ctrl_status(c);
+    const StepState& S = c.st[committed(h)];
+    *cfl = S.cfl;
+    st = ctrl_status(S);
     if (st) return st;
-    if (!c.last_accepted) return fail(CLAW_E_CFL, "step rejected: Courant number %.6g > %.6g", c.cfl, h->d.cfl_max);
+    if (!S.last_accepted) return fail(CLAW_E_CFL, "step rejected: Courant number %.6g > %.6g", S.cfl, h->d.cfl_max);
     return CLAW_OK;
 }
 
@@ -422,46 +448,50 @@ claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (dir < 0 || dir >= h->d.ndim) return fail(CLAW_E_INVALID, "direction %d out of range", dir);
     if (!(dt >= 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be finite and >= 0");
-    HIP_TRY(launch_begin(h->ctrl, dt, h->stream));
-    HIP_TRY(enqueue_sweep(h, dir, 0, 1, 0, MODE_ADAPT, h->stream));
-    HIP_TRY(launch_accept_sweep(h->ctrl, 1, h->stream));
-    if (!smax) return CLAW_OK;
-    Ctrl c;
-    claw_status st = read_ctrl(h, &c);
+    claw_status st = commit(h);
     if (st) return st;
-    if (c.nonphys) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
-    if (h->fp32) {
-        float f;
-        memcpy(&f, &c.smax32[dir], 4);
-        *smax = f;
-    } else {
-        memcpy(smax, &c.smax64[dir], 8);
-    }
+    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, 1, h->stream));
+    HIP_TRY(enqueue_sweep(h, dir, 0, 1, false, h->parity, true, true, h->stream));
+    h->parity ^= 1;
+    st = commit(h);
+    if (st || !smax) return st;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    const int q = committed(h);
+    if (c.nonphys[q]) return fail(CLAW_E_NONPHYSICAL, "non-physical state (depth <= 0 or not finite)");
+    *smax = smax_value(h, c, q, dir);
     return CLAW_OK;
 }
 
 claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t, int64_t* nreject) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
-    Ctrl c0;
-    claw_status st = read_ctrl(h, &c0);
+    claw_status st = commit(h);
     if (st) return st;
+    Ctrl c0;
+    st = read_ctrl(h, &c0);
+    if (st) return st;
+    const long long rej0 = c0.st[committed(h)].rejected, acc0 = c0.st[committed(h)].accepted;
     if (nsteps > 0) {
         st = begin_adaptive(h, dt0);
         if (st) return st;
-        HIP_TRY(launch_set_target(h->ctrl, nsteps, h->stream));
+        HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
         st = ensure_graph(h);
         if (st) return st;
         int64_t remaining = nsteps;
         for (int round = 0; round < 1000; ++round) {
             const int64_t reps = (remaining + kGraphSteps - 1) / kGraphSteps;
-            for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec, h->stream));
+            for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec[h->parity], h->stream));
+            st = commit(h);
+            if (st) return st;
             Ctrl c;
             st = read_ctrl(h, &c);
             if (st) return st;
-            if (c.err) return ctrl_status(c);
-            if (c.done) break;
-            remaining = c.target - c.accepted;
+            const StepState& S = c.st[committed(h)];
+            if (S.err) return ctrl_status(S);
+            if (S.done) break;
+            remaining = S.target - S.accepted;
             if (remaining <= 0) break;
         }
     }
@@ -470,28 +500,36 @@ claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t, 
     Ctrl c;
     st = read_ctrl(h, &c);
     if (st) return st;
-    if (t) *t = c.t;
-    if (nreject) *nreject = c.rejected - c0.rejected;
-    if (c.accepted - c0.accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
+    const StepState& S = c.st[committed(h)];
+    if (t) *t = S.t;
+    if (nreject) *nreject = S.rejected - rej0;
+    if (S.accepted - acc0 != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
     return CLAW_OK;
 }
 
 claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts, double* cfl_log) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (nsteps < 0 || (nsteps > 0 && !dts)) return fail(CLAW_E_INVALID, "bad step list");
-    for (int64_t k = 0; k < nsteps; ++k) {
+    for (int64_t k = 0; k < nsteps; ++k)
         if (!(dts[k] > 0) || !isfinite(dts[k])) return fail(CLAW_E_INVALID, "dts[%lld] not positive", (long long)k);
-        HIP_TRY(launch_begin(h->ctrl, dts[k], h->stream));
-        claw_status st = enqueue_trial(h, MODE_FIXED, h->stream, nullptr);
+    claw_status st = CLAW_OK;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        st = commit(h);
         if (st) return st;
-        if (cfl_log) HIP_TRY(hipMemcpyAsync(&cfl_log[k], &h->ctrl->cfl, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[k], MODE_FIXED, result_offset(h->d.ndim), h->stream));
+        st = enqueue_trial(h, h->stream, nullptr);
+        if (!st) st = commit(h);
+        if (st) return st;
+        if (cfl_log)
+            HIP_TRY(hipMemcpyAsync(&cfl_log[k], &h->ctrl->st[committed(h)].cfl, sizeof(double),
+                                   hipMemcpyDeviceToHost, h->stream));
     }
-    claw_status st = sync_state(h);
+    st = sync_state(h);
     if (st) return st;
     Ctrl c;
     st = read_ctrl(h, &c);
     if (st) return st;
-    return ctrl_status(c);
+    return ctrl_status(c.st[committed(h)]);
 }
 
 claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms, int64_t* launches) {
@@ -501,25 +539,26 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
     int64_t cnt[4] = {0, 0, 0, 0};
     const int per = h->d.ndim + 1;
     const int batch = 64;
-    if ((int)h->events.size() < batch * per) {
-        for (int i = (int)h->events.size(); i < batch * per; ++i) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
-            h->events.push_back(e);
-        }
+    while ((int)h->events.size() < batch * per) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->events.push_back(e);
     }
-    claw_status st;
+    claw_status st = commit(h);
+    if (st) return st;
     if (nsteps > 0) {
         st = begin_adaptive(h, 0.0);
         if (st) return st;
-        HIP_TRY(launch_set_target(h->ctrl, nsteps, h->stream));
+        HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
         int64_t remaining = nsteps;
         while (remaining > 0) {
             const int64_t n = remaining < batch ? remaining : batch;
             for (int64_t k = 0; k < n; ++k) {
-                st = enqueue_trial(h, MODE_ADAPT, h->stream, &h->events[k * per]);
+                st = enqueue_trial(h, h->stream, &h->events[k * per]);
                 if (st) return st;
             }
+            st = commit(h);
+            if (st) return st;
             HIP_TRY(hipStreamSynchronize(h->stream));
             for (int64_t k = 0; k < n; ++k) {
                 hipEvent_t* ev = &h->events[k * per];
@@ -533,9 +572,10 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
             Ctrl c;
             st = read_ctrl(h, &c);
             if (st) return st;
-            if (c.err) return ctrl_status(c);
-            if (c.done) break;
-            remaining = c.target - c.accepted;
+            const StepState& S = c.st[committed(h)];
+            if (S.err) return ctrl_status(S);
+            if (S.done) break;
+            remaining = S.target - S.accepted;
         }
     }
     st = sync_state(h);
@@ -550,35 +590,44 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
 
 claw_status claw_sync_state(claw_solver* h) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    claw_status st = commit(h);
+    if (st) return st;
     return sync_state(h);
 }
 
 claw_status claw_get_control(claw_solver* h, double* t, double* dt_next, int64_t* accepted, int64_t* rejected) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
-    Ctrl c;
-    claw_status st = read_ctrl(h, &c);
+    claw_status st = commit(h);
     if (st) return st;
-    if (t) *t = c.t;
-    if (dt_next) *dt_next = c.dt_next;
-    if (accepted) *accepted = c.accepted;
-    if (rejected) *rejected = c.rejected;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    const StepState& S = c.st[committed(h)];
+    if (t) *t = S.t;
+    if (dt_next) *dt_next = S.dt_next;
+    if (accepted) *accepted = S.accepted;
+    if (rejected) *rejected = S.rejected;
     return CLAW_OK;
 }
 
 claw_status claw_set_control(claw_solver* h, double t, double dt_next) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (!isfinite(t) || !(dt_next >= 0)) return fail(CLAW_E_INVALID, "bad control values");
-    HIP_TRY(launch_set_control(h->ctrl, t, dt_next, h->stream));
+    claw_status st = commit(h);
+    if (st) return st;
+    HIP_TRY(launch_set_control(h->ctrl, committed(h), t, dt_next, h->stream));
     return CLAW_OK;
 }
 
 claw_status claw_destroy(claw_solver* h) {
     if (!h) return CLAW_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (h->gexec) hipGraphExecDestroy(h->gexec);
-    if (h->graph) hipGraphDestroy(h->graph);
-    for (hipEvent_t ev : h->events) hipEventDestroy(ev);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
+    for (int p = 0; p < 2; ++p) {
+        if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
+        if (h->graph[p]) (void)hipGraphDestroy(h->graph[p]);
+    }
+    for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     if (e != hipSuccess) return fail(CLAW_E_HIP, "stream sync failed: %s", hipGetErrorString(e));
     return CLAW_OK;

@@ -14,8 +14,11 @@
 // Column kernel (y and z sweeps).  A wavefront owns 64 adjacent columns (one
 // per lane, coalesced rows) and marches along the sweep direction over a
 // chunk of cells with a rolling register window, so each interface is solved
-// once per chunk; rows are prefetched PF rows ahead.  The column kernel that
-// closes a step also runs the CFL control in its last workgroup.
+// once per chunk; rows are prefetched PF rows ahead.
+//
+// Step control needs no kernel of its own: the first sweep of every trial
+// decides the previous trial from its speed maxima (open_trial / decide) and
+// the last sweep clears the speed slots of the other parity.
 //
 // Ghost cells are never stored: a cell index outside the grid is mapped to its
 // source cell by the boundary rule (section 4.1) when it is loaded.
@@ -92,12 +95,10 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
     typedef typename VecOf<R, CPL>::type V;
-    Ctrl* ctrl = a.ctrl;
-    if (ctrl->done) return;
-    const int cur = ctrl->cur;
-    const R* __restrict__ src = a.buf[(cur + a.src_off) % 3];
-    R* __restrict__ dst = a.buf[(cur + a.dst_off) % 3];
-    const R nu = ctrl_nu<R>(ctrl, 0);
+    // The buffer of this trial is known before the previous trial is decided
+    // unless that trial gets reverted: load from the predicted buffer first so
+    // the decision's latency overlaps the loads, and reload on a mismatch.
+    const int cur_guess = predicted_cur(a);
     const int lane = threadIdx.x & 63;
     const int nx = a.nx;
     const int row = (int)(blockIdx.y + blockIdx.z * gridDim.y) * 4 + (int)(threadIdx.x >> 6);
@@ -113,35 +114,44 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
     // load the lane's cells (ghost cells synthesised at the row ends)
     R q[CPL][MEQN];
     R zc[CPL][2];
-    if (interior) {
+    auto load_cells = [&](const R* __restrict__ src) {
+        if (interior) {
 #pragma unroll
-        for (int e = 0; e < MEQN; ++e) {
-            V v = *reinterpret_cast<const V*>(src + (size_t)e * a.ncell + base + (unsigned)xl);
+            for (int e = 0; e < MEQN; ++e) {
+                V v = *reinterpret_cast<const V*>(src + (size_t)e * a.ncell + base + (unsigned)xl);
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
-        }
-        if constexpr (SYS == SYS_ACV) {
-#pragma unroll
-            for (int f = 0; f < 2; ++f) {
-                V v = *reinterpret_cast<const V*>(a.zc + (size_t)f * a.ncell + base + (unsigned)xl);
-#pragma unroll
-                for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
+                for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
             }
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            bool flip;
-            const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
-#pragma unroll
-            for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
-            if (flip) q[c][nrm] = -q[c][nrm];
             if constexpr (SYS == SYS_ACV) {
-                zc[c][0] = a.zc[sidx];
-                zc[c][1] = a.zc[(size_t)a.ncell + sidx];
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    V v = *reinterpret_cast<const V*>(a.zc + (size_t)f * a.ncell + base + (unsigned)xl);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                bool flip;
+                const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
+#pragma unroll
+                for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
+                if (flip) q[c][nrm] = -q[c][nrm];
+                if constexpr (SYS == SYS_ACV) {
+                    zc[c][0] = a.zc[sidx];
+                    zc[c][1] = a.zc[(size_t)a.ncell + sidx];
+                }
             }
         }
-    }
+    };
+    load_cells(a.buf[(cur_guess + a.src_off) % 3]);
+
+    const Trial<R> tr = open_trial(a, 0);
+    if (tr.done && !SPEEDS) return;
+    if (tr.cur != cur_guess) load_cells(a.buf[(tr.cur + a.src_off) % 3]);
+    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    const R nu = tr.nu;
 
     bool bad = false;
     C cell[CPL];
@@ -210,7 +220,7 @@ __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
             }
         }
     }
-    block_finish(a, 0, sm, bad, false);
+    block_finish(a, 0, sm, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -237,22 +247,18 @@ __device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __r
     }
 }
 
-// KIND: 0 sweep, 1 speed-only pass, 2 sweep that closes a step (runs the
-// step control in its last workgroup)
-template <typename R, int SYS, int MEQN, int NRM, int PF, int KIND>
+template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
 __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
     using CC = ColCell<R, SYS, MEQN>;
-    constexpr bool SPEEDS = KIND == 1;
     constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
-    Ctrl* ctrl = a.ctrl;
-    if (ctrl->done) return;
-    const int cur = ctrl->cur;
-    const R* __restrict__ src = a.buf[(cur + a.src_off) % 3];
-    R* __restrict__ dst = a.buf[(cur + a.dst_off) % 3];
     const int dir = a.dir;
-    const R nu = ctrl_nu<R>(ctrl, dir);
+    const Trial<R> tr = open_trial(a, dir);
+    if (tr.done && !SPEEDS) return;
+    const R* __restrict__ src = a.buf[(tr.cur + a.src_off) % 3];
+    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    const R nu = tr.nu;
     const R inv2Z = ac_inv2Z<R, SYS>(a);
     const int lane = threadIdx.x & 63;
     const int nx = a.nx, m = a.m;
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
         bad = false;
         sm = R(0);
     }
-    block_finish(a, dir, sm, bad, KIND == 2);
+    block_finish(a, dir, sm, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,43 +373,38 @@ static hipError_t launch_row(const SweepArgs<R>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename R, int SYS, int MEQN, int NRM, int KIND>
+template <typename R, int SYS, int MEQN, int NRM, bool SPEEDS>
 static hipError_t launch_col(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int PF = 4;
     const dim3 grid(ceil_div(ceil_div(a.nx, 64), 4), ceil_div(a.m, a.chunk), a.nlines_o);
-    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, KIND>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, SPEEDS>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R, int SYS, int MEQN, int KIND>
+template <typename R, int SYS, int MEQN, bool SPEEDS>
 static hipError_t launch_dir(const SweepArgs<R>& a, hipStream_t s) {
-    if (a.dir == 0) {
-        if constexpr (KIND == 2) return hipErrorInvalidValue;  // x never closes a step
-        return launch_row<R, SYS, MEQN, KIND == 1>(a, s);
-    }
-    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, KIND>(a, s);
-    if constexpr (MEQN == 4) return launch_col<R, SYS, MEQN, 3, KIND>(a, s);
+    if (a.dir == 0) return launch_row<R, SYS, MEQN, SPEEDS>(a, s);
+    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, SPEEDS>(a, s);
+    if constexpr (MEQN == 4) return launch_col<R, SYS, MEQN, 3, SPEEDS>(a, s);
     return hipErrorInvalidValue;
 }
 
 template <typename R, int SYS, int MEQN>
-static hipError_t launch_kind(const SweepArgs<R>& a, int kind, hipStream_t s) {
-    if (kind == 1) return launch_dir<R, SYS, MEQN, 1>(a, s);
-    if (kind == 2) return launch_dir<R, SYS, MEQN, 2>(a, s);
-    return launch_dir<R, SYS, MEQN, 0>(a, s);
+static hipError_t launch_kind(const SweepArgs<R>& a, bool speeds, hipStream_t s) {
+    return speeds ? launch_dir<R, SYS, MEQN, true>(a, s) : launch_dir<R, SYS, MEQN, false>(a, s);
 }
 
 template <typename R>
-hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, int kind, hipStream_t s) {
-    if (sys == SYS_SW && meqn == 3) return launch_kind<R, SYS_SW, 3>(a, kind, s);
-    if (sys == SYS_AC && meqn == 3) return launch_kind<R, SYS_AC, 3>(a, kind, s);
-    if (sys == SYS_AC && meqn == 4) return launch_kind<R, SYS_AC, 4>(a, kind, s);
-    if (sys == SYS_ACV && meqn == 3) return launch_kind<R, SYS_ACV, 3>(a, kind, s);
-    if (sys == SYS_ACV && meqn == 4) return launch_kind<R, SYS_ACV, 4>(a, kind, s);
+hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds, hipStream_t s) {
+    if (sys == SYS_SW && meqn == 3) return launch_kind<R, SYS_SW, 3>(a, speeds, s);
+    if (sys == SYS_AC && meqn == 3) return launch_kind<R, SYS_AC, 3>(a, speeds, s);
+    if (sys == SYS_AC && meqn == 4) return launch_kind<R, SYS_AC, 4>(a, speeds, s);
+    if (sys == SYS_ACV && meqn == 3) return launch_kind<R, SYS_ACV, 3>(a, speeds, s);
+    if (sys == SYS_ACV && meqn == 4) return launch_kind<R, SYS_ACV, 4>(a, speeds, s);
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, int, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, int, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int, int, bool, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int, int, bool, hipStream_t);
 
 }  // namespace claw
