@@ -97,7 +97,8 @@ def main():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--timed-steps", type=int, default=200,
                     help="steps of the per-kernel event timing run")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=150,
+                    help="oracle steps of the CPU baseline sample (about 10 s on 16 threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
