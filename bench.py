@@ -87,6 +87,65 @@ def achievable_bandwidth(torch, claw, nbytes=1 << 30, reps=10):
     return res
 
 
+def bench_ensemble(args, torch, claw, inputs):
+    """Batched ensemble of 256 shallow-water instances (sides U{128..1024},
+    Gaussian humps, walls, FP32) for `steps` accepted steps each, against the
+    same instances advanced one after another through the single-grid path.
+    Results are bitwise identical between the two (tested), so the L1 error is
+    equal by construction and the speedup is T_single / T_batch."""
+    steps = args.steps if args.steps_given else 500
+    members = inputs.sw_ensemble(count=args.count, seed=0, dtype="f32", nsteps=steps)
+    cells = sum(p["n"][0] * p["n"][1] for p, _ in members)
+    qs = [torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous() for _, q0 in members]
+    b = claw.BatchSolver([p for p, _ in members], qs)
+    tuned = b.tune(os.environ.get("CLAW_AUTOTUNE_CACHE"))
+    print(f"# ensemble: {len(members)} instances, {cells} cells; tuned {tuned}", file=sys.stderr, flush=True)
+    b.advance(args.warmup if args.warmup_given else 50)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rej = b.advance(steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    b.close()
+    del qs
+    # the same instances one after another through the single-grid path
+    t_single = 0.0
+    for p, q0 in members:
+        q = torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous()
+        s = claw.Solver(p, q)
+        s.advance(1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.advance(steps)
+        torch.cuda.synchronize()
+        t_single += time.perf_counter() - t1
+        s.close()
+    value = cells * steps / t_batch / 1e9
+    return {
+        "metric": "ensemble Gcell-updates/s",
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup if args.warmup_given else 50,
+        "ms_per_step": t_batch / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian humps, sides U{128..1024})",
+        "config": {"workload": "batched 2D shallow-water ensemble, walls, MC, CFL 0.9, adaptive dt per "
+                               "instance", "instances": len(members), "cells": cells,
+                   "parallelism": "single GPU"},
+        "tuned": tuned,
+        "rejected_trials": int(sum(rej)),
+        "single_grid_seconds": t_single,
+        "batch_seconds": t_batch,
+        "speedup_vs_single_grid": t_single / t_batch,
+        "single_grid_value": cells * steps / t_single / 1e9,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,7 +161,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble"])
+    ap.add_argument("--count", type=int, default=256, help="ensemble instances")
     args = ap.parse_args()
+    args.steps_given = "--steps" in sys.argv
+    args.warmup_given = "--warmup" in sys.argv
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -115,6 +178,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload == "ensemble":
+        print(json.dumps(bench_ensemble(args, torch, claw, inputs)), flush=True)
+        return
 
     prob, q0, _ = inputs.sw_radial_dam(n=args.n, dtype=args.dtype, nsteps=args.steps)
     ncell = prob["n"][0] * prob["n"][1]

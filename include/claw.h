@@ -163,6 +163,39 @@ claw_status claw_set_control(claw_solver* h, double t, double dt_next);
  * caller's. */
 claw_status claw_destroy(claw_solver* h);
 
+/* ---------------------------------------------------------------------------
+ * Batched ensembles: many independent 2D shallow-water grids of different
+ * sizes advanced together (each with its own adaptive dt, accept / revert and
+ * step count).  Every sweep of every instance runs in one launch per sweep
+ * direction; a table maps each workgroup to (instance, block), and the
+ * whole multi-step run replays a captured HIP graph.  Each instance's result is
+ * bitwise the single-grid result.
+ * ------------------------------------------------------------------------- */
+typedef struct claw_batch claw_batch; /* opaque */
+
+/* Workspace bytes for count descriptors (all 2D shallow water, one dtype). */
+claw_status claw_batch_workspace_bytes(const claw_desc* descs, int32_t count, size_t* bytes);
+/* q[i]: device state of instance i (layout as for claw_create, 256-byte
+ * aligned); workspace: device buffer of claw_batch_workspace_bytes() bytes. */
+claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const* q, void* workspace,
+                              size_t workspace_bytes, void* stream, claw_batch** out);
+/* Autotuner: times state-preserving trial steps (dt = 0) for each candidate
+ * column chunk {16, 32, 64, 128} and block schedule (0 largest instances
+ * first, 1 round-robin), keeps the fastest, and records it in the JSON cache
+ * file cache_path (may be NULL) keyed by arch, dtype, system, instance count
+ * and total-cell bucket; a cached key is used without timing.  Outputs may be
+ * NULL.  Synchronises. */
+claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk, int32_t* schedule,
+                            double* us_per_step);
+/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1). */
+claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule);
+/* Advances every instance by nsteps accepted steps (adaptive dt per
+ * instance, first dt from a speed pass); t[i], nreject[i] (host arrays of
+ * count entries, may be NULL) receive each instance's time and rejected
+ * trials of this call.  Synchronises; states end in q[i]. */
+claw_status claw_batch_advance(claw_batch* b, int64_t nsteps, double* t, int64_t* nreject);
+claw_status claw_batch_destroy(claw_batch* b);
+
 /* Achievable-bandwidth microbenchmark (the paper's achievable roof, section
  * 7.1): streams over device buffers a (read, must be zero-filled) and b
  * (written), each of `bytes` bytes, reps times per kernel, on `stream`, and

@@ -1,7 +1,10 @@
 """Builds libclaw.so (HIP, gfx950) in-tree from csrc/.
 
 hipcc compiles each translation unit for gfx950 only; packed FP32 VALU
-instructions are disabled for the whole library.
+instructions are disabled for the whole library.  Floating-point contraction
+is decided per source expression (-ffp-contract=on), so a formula compiles to
+the same operations wherever it is inlined: results do not depend on tile
+shapes or on which kernel computes an interface.
 """
 import os
 import subprocess
@@ -12,8 +15,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libclaw.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["sweeps.hip", "control.hip", "runtime.hip", "stream.hip"]
+SOURCES = ["sweeps.hip", "batch.hip", "control.hip", "runtime.hip", "stream.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
+         "-ffp-contract=on",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(HERE, "..", "include")]
 

@@ -28,6 +28,8 @@ _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDE
 EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
             "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
             "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
+            "claw_batch_workspace_bytes", "claw_batch_create", "claw_batch_tune",
+            "claw_batch_set_tiles", "claw_batch_advance", "claw_batch_destroy",
             "claw_stream_bench", "claw_status_string", "claw_last_error"]
 
 
@@ -86,6 +88,12 @@ def _load():
         "claw_set_control": (i32, [vp, dbl, dbl]),
         "claw_destroy": (i32, [vp]),
         "claw_stream_bench": (i32, [vp, vp, ctypes.c_size_t, i32, vp, P(dbl)]),
+        "claw_batch_workspace_bytes": (i32, [P(claw_desc), i32, P(ctypes.c_size_t)]),
+        "claw_batch_create": (i32, [P(claw_desc), i32, P(vp), vp, ctypes.c_size_t, vp, P(vp)]),
+        "claw_batch_tune": (i32, [vp, ctypes.c_char_p, P(i32), P(i32), P(dbl)]),
+        "claw_batch_set_tiles": (i32, [vp, i32, i32]),
+        "claw_batch_advance": (i32, [vp, i64, P(dbl), P(i64)]),
+        "claw_batch_destroy": (i32, [vp]),
         "claw_status_string": (ctypes.c_char_p, [i32]),
         "claw_last_error": (ctypes.c_char_p, []),
     }
@@ -214,6 +222,82 @@ def claw_stream_bench(a, b, reps, stream_handle):
     _check(_lib.claw_stream_bench(_ptr(a), _ptr(b), nbytes, int(reps),
                                   ctypes.c_void_p(stream_handle), out), "claw_stream_bench")
     return dict(zip(["copy", "copy_nt", "read", "write", "write_nt"], list(out)))
+
+
+def claw_batch_workspace_bytes(descs):
+    arr = (claw_desc * len(descs))(*descs)
+    n = ctypes.c_size_t(0)
+    _check(_lib.claw_batch_workspace_bytes(arr, len(descs), ctypes.byref(n)),
+           "claw_batch_workspace_bytes")
+    return n.value
+
+
+def claw_batch_create(descs, qs, workspace, stream_handle):
+    arr = (claw_desc * len(descs))(*descs)
+    ptrs = (ctypes.c_void_p * len(qs))(*[q.data_ptr() for q in qs])
+    h = ctypes.c_void_p(None)
+    _check(_lib.claw_batch_create(arr, len(descs), ptrs, _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(),
+                                  ctypes.c_void_p(stream_handle), ctypes.byref(h)), "claw_batch_create")
+    return h
+
+
+def claw_batch_tune(h, cache_path=None):
+    c, s, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+    _check(_lib.claw_batch_tune(h, cache_path.encode() if cache_path else None, ctypes.byref(c),
+                                ctypes.byref(s), ctypes.byref(us)), "claw_batch_tune")
+    return {"chunk": c.value, "schedule": s.value, "us_per_step": us.value}
+
+
+def claw_batch_set_tiles(h, chunk, schedule):
+    _check(_lib.claw_batch_set_tiles(h, int(chunk), int(schedule)), "claw_batch_set_tiles")
+
+
+def claw_batch_advance(h, count, nsteps):
+    t = (ctypes.c_double * count)()
+    rej = (ctypes.c_int64 * count)()
+    _check(_lib.claw_batch_advance(h, int(nsteps), t, rej), "claw_batch_advance")
+    return list(t), list(rej)
+
+
+def claw_batch_destroy(h):
+    _check(_lib.claw_batch_destroy(h), "claw_batch_destroy")
+
+
+class BatchSolver:
+    """An ensemble of 2D shallow-water problems advanced together; qs are torch
+    device tensors, one per problem (same dtype)."""
+
+    def __init__(self, probs, qs, stream=None):
+        import torch
+        self.probs = probs
+        self.descs = [desc_from_problem(p) for p in probs]
+        self.qs = qs
+        dev = qs[0].device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        nbytes = claw_batch_workspace_bytes(self.descs)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.h = claw_batch_create(self.descs, qs, self.workspace, self.stream.cuda_stream)
+
+    def tune(self, cache_path=None):
+        return claw_batch_tune(self.h, cache_path)
+
+    def set_tiles(self, chunk, schedule):
+        claw_batch_set_tiles(self.h, chunk, schedule)
+
+    def advance(self, nsteps):
+        return claw_batch_advance(self.h, len(self.qs), nsteps)
+
+    def close(self):
+        if self.h is not None:
+            claw_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def claw_status_string(status):

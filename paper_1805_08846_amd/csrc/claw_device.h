@@ -618,14 +618,15 @@ __device__ __forceinline__ int predicted_cur(const SweepArgs<R>& a) {
     return (P.pending && !P.done) ? (P.cur + P.result_off) % 3 : P.cur;
 }
 
+// lead: this workgroup is block (0, 0, 0) of its grid (it records the state).
 template <typename R>
-__device__ __forceinline__ Trial<R> open_trial(const SweepArgs<R>& a, int dir) {
+__device__ __forceinline__ Trial<R> open_trial(const SweepArgs<R>& a, int dir, bool lead) {
     Ctrl* c = a.ctrl;
     Trial<R> t;
     if (a.first) {
         StepState S;
         decide(c, a.parity ^ 1, sizeof(R) == 4, S);
-        if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+        if (lead && threadIdx.x == 0) {
             S.pending = S.done ? 0 : 1;
             c->st[a.parity] = S;
         }
@@ -645,7 +646,7 @@ __device__ __forceinline__ Trial<R> open_trial(const SweepArgs<R>& a, int dir) {
 // 64) into the trial's speed slot; the sweep that closes a trial also clears
 // the other parity's slots for the trial after next.
 template <typename R>
-__device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v, bool bad) {
+__device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v, bool bad, bool lead) {
     __shared__ R red[16];
     __shared__ int redbad[16];
     Ctrl* c = a.ctrl;
@@ -666,7 +667,7 @@ __device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v
         }
         publish_smax(c, a.parity, dir, m);
         if (b) atomicOr(&c->nonphys[a.parity], 1);
-        if (a.last && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+        if (a.last && lead) {
             const int o = a.parity ^ 1;
             for (int d = 0; d < 4; ++d) {
                 c->smax32[o][d] = 0u;

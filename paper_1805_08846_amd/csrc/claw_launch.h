@@ -22,6 +22,25 @@ hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, h
 hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s);
 hipError_t launch_set_control(Ctrl* c, int q, double t, double dt_next, hipStream_t s);
 
+// Batched ensemble launches (batch.hip): blocks[i] maps workgroup i of a
+// launch to an instance and its logical block; args holds two SweepArgs per
+// instance (x, y).
+struct BatchBlock {
+    int inst, x, y, z;
+};
+template <typename R>
+struct BatchLaunch {
+    const BatchBlock* blocks;
+    const SweepArgs<R>* args;
+    int parity, first, last, pad;
+};
+enum { BOP_COMMIT = 0, BOP_ZERO_SPEEDS = 1, BOP_BEGIN_FIXED = 2, BOP_BEGIN_ADAPT = 3 };
+template <typename R>
+hipError_t launch_batch_sweep(const BatchLaunch<R>& L, int sys, int dir, int nblocks, bool speeds,
+                              hipStream_t s);
+hipError_t launch_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, double dt, int mode,
+                             int result_off, long long nsteps, bool fp32, hipStream_t s);
+
 // Element-wise set-up kernels.
 template <typename R>
 hipError_t launch_derive_zc(const R* aux, R* zc, int64_t ncell, hipStream_t s);

@@ -8,7 +8,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <array>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/claw.h"
@@ -154,28 +157,31 @@ int col_chunk(int64_t m, int64_t nx, int64_t nlines_o) {
     return (int)chunk;
 }
 
+// Sweep arguments of one grid.  chunk <= 0 picks the column chunk from the
+// grid size (col_chunk).
 template <typename R>
-SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off) {
+SweepArgs<R> grid_args(const claw_desc& d, int sys, int64_t ncell, void* const* buf, const void* zc,
+                       Ctrl* ctrl, int dir, int src_off, int dst_off, int chunk) {
     SweepArgs<R> a;
     memset(&a, 0, sizeof a);
-    for (int i = 0; i < 3; ++i) a.buf[i] = (R*)h->buf[i];
-    a.zc = (const R*)h->zc;
-    a.ctrl = h->ctrl;
-    a.ncell = (int32_t)h->plan.ncell;
-    const int64_t nx = h->d.n[0], ny = h->d.n[1], nz = h->d.n[2];
+    for (int i = 0; i < 3; ++i) a.buf[i] = (R*)buf[i];
+    a.zc = (const R*)zc;
+    a.ctrl = ctrl;
+    a.ncell = (int32_t)ncell;
+    const int64_t nx = d.n[0], ny = d.n[1], nz = d.n[2];
     a.nx = (int32_t)nx;
     a.dir = dir;
     a.src_off = src_off;
     a.dst_off = dst_off;
-    a.bc_lo = h->d.bc_lo[dir];
-    a.bc_hi = h->d.bc_hi[dir];
-    a.limiter = h->d.limiter;
-    a.efix = h->d.efix;
-    a.grav = (R)h->d.grav;
-    a.sqrt_grav = (R)sqrt(h->d.grav);
-    if (h->sys == SYS_AC) {
-        a.Z0 = (R)sqrt(h->d.rho * h->d.bulk);
-        a.c0 = (R)sqrt(h->d.bulk / h->d.rho);
+    a.bc_lo = d.bc_lo[dir];
+    a.bc_hi = d.bc_hi[dir];
+    a.limiter = d.limiter;
+    a.efix = d.efix;
+    a.grav = (R)d.grav;
+    a.sqrt_grav = (R)sqrt(d.grav);
+    if (sys == SYS_AC) {
+        a.Z0 = (R)sqrt(d.rho * d.bulk);
+        a.c0 = (R)sqrt(d.bulk / d.rho);
     }
     if (dir == 0) {
         a.m = (int32_t)nx;
@@ -186,9 +192,14 @@ SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off)
         a.stride = (int32_t)(dir == 1 ? nx : nx * ny);
         a.nlines_o = (int32_t)(dir == 1 ? nz : ny);
         a.ostride = (int32_t)(dir == 1 ? nx * ny : nx);
-        a.chunk = col_chunk(a.m, nx, a.nlines_o);
+        a.chunk = chunk > 0 ? (int32_t)(chunk < a.m ? chunk : a.m) : col_chunk(a.m, nx, a.nlines_o);
     }
     return a;
+}
+
+template <typename R>
+SweepArgs<R> sweep_args(const claw_solver* h, int dir, int src_off, int dst_off) {
+    return grid_args<R>(h->d, h->sys, h->plan.ncell, h->buf, h->zc, h->ctrl, dir, src_off, dst_off, 0);
 }
 
 // One sweep launch.  speeds: speed-only pass; parity: step-state copy and
@@ -647,5 +658,500 @@ const char* claw_status_string(claw_status s) {
 }
 
 const char* claw_last_error(void) { return g_err; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched ensembles of independent shallow-water grids (claw_batch_*)
+// ===========================================================================
+
+struct claw_batch {
+    int count;
+    bool fp32;
+    std::vector<claw_desc> d;
+    std::vector<Plan> plan;
+    hipStream_t stream;
+    hipStream_t cap_stream;
+    char* ws;
+    size_t off_ptrs, off_args, off_rows, off_cols, off_bufs;
+    size_t args_stride;  // bytes per SweepArgs of the dtype
+    Ctrl** ctrl_ptrs;    // device array of the instances' control blocks
+    std::vector<Ctrl*> ctrl;
+    std::vector<std::array<void*, 3>> buf;
+    int n_row_blocks, n_col_blocks, max_col_blocks;
+    int chunk, schedule;
+    double tuned_us;
+    bool have_dt_next;
+    int parity;
+    hipGraphExec_t gexec[2];
+    hipGraph_t graph[2];
+};
+
+namespace {
+
+constexpr int kBatchChunkMin = 8;
+const int kTuneChunks[] = {16, 32, 64, 128};
+
+claw_status batch_validate(const claw_desc* d, int32_t count) {
+    if (!d || count < 1 || count > 65535) return fail(CLAW_E_INVALID, "need 1..65535 descriptors");
+    for (int i = 0; i < count; ++i) {
+        claw_status st = validate(&d[i]);
+        if (st) return st;
+        if (d[i].riemann != CLAW_RP_SHALLOW_WATER || d[i].ndim != 2)
+            return fail(CLAW_E_UNSUPPORTED, "batches hold 2D shallow-water instances (instance %d)", i);
+        if (d[i].dtype != d[0].dtype) return fail(CLAW_E_INVALID, "all instances need the same dtype");
+    }
+    return CLAW_OK;
+}
+
+struct BatchPlan {
+    size_t ctrl_stride, off_ptrs, off_args, off_rows, off_cols, off_bufs, total, args_stride;
+    int max_row_blocks, max_col_blocks;
+};
+
+int row_cpl(bool fp32) { return fp32 ? 4 : 2; }
+
+int inst_row_blocks(const claw_desc& d, bool fp32) {
+    const int P = 62 * row_cpl(fp32);
+    return (int)(((d.n[0] + P - 1) / P) * ((d.n[1] + 3) / 4));
+}
+int inst_col_blocks(const claw_desc& d, int chunk) {
+    const int64_t sg = ((d.n[0] + 63) / 64 + 3) / 4;
+    const int64_t c = chunk < d.n[1] ? chunk : d.n[1];
+    return (int)(sg * ((d.n[1] + c - 1) / c));
+}
+
+BatchPlan batch_plan(const claw_desc* d, int count) {
+    BatchPlan p;
+    const bool fp32 = d[0].dtype == CLAW_FP32;
+    p.ctrl_stride = (sizeof(Ctrl) + 255) / 256 * 256;
+    p.args_stride = fp32 ? sizeof(SweepArgs<float>) : sizeof(SweepArgs<double>);
+    p.off_ptrs = round_up(p.ctrl_stride * count);
+    p.off_args = p.off_ptrs + round_up(sizeof(Ctrl*) * count);
+    p.off_rows = p.off_args + round_up(p.args_stride * 2 * count);
+    p.max_row_blocks = 0;
+    p.max_col_blocks = 0;
+    for (int i = 0; i < count; ++i) {
+        p.max_row_blocks += inst_row_blocks(d[i], fp32);
+        p.max_col_blocks += inst_col_blocks(d[i], kBatchChunkMin);
+    }
+    p.off_cols = p.off_rows + round_up(sizeof(BatchBlock) * p.max_row_blocks);
+    p.off_bufs = p.off_cols + round_up(sizeof(BatchBlock) * p.max_col_blocks);
+    p.total = p.off_bufs;
+    for (int i = 0; i < count; ++i) p.total += 2 * round_up(make_plan(&d[i]).state_bytes);
+    return p;
+}
+
+// Block tables and per-instance sweep arguments for column chunk `chunk` and
+// schedule 0 (largest instances first) or 1 (round-robin over instances).
+claw_status batch_tables(claw_batch* b, int chunk, int schedule) {
+    const int n = b->count;
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return b->plan[x].ncell > b->plan[y].ncell;
+    });
+    std::vector<std::vector<BatchBlock>> rows(n), cols(n);
+    const int P = 62 * row_cpl(b->fp32);
+    for (int i = 0; i < n; ++i) {
+        const claw_desc& d = b->d[i];
+        const int segs = (int)((d.n[0] + P - 1) / P), groups = (int)((d.n[1] + 3) / 4);
+        for (int y = 0; y < groups; ++y)
+            for (int x = 0; x < segs; ++x) rows[i].push_back({i, x, y, 0});
+        const int sg = (int)(((d.n[0] + 63) / 64 + 3) / 4);
+        const int c = chunk < d.n[1] ? chunk : (int)d.n[1];
+        const int nch = (int)((d.n[1] + c - 1) / c);
+        for (int y = 0; y < nch; ++y)
+            for (int x = 0; x < sg; ++x) cols[i].push_back({i, x, y, 0});
+    }
+    auto flatten = [&](std::vector<std::vector<BatchBlock>>& per) {
+        std::vector<BatchBlock> out;
+        if (schedule == 0) {
+            for (int i : order) out.insert(out.end(), per[i].begin(), per[i].end());
+        } else {
+            size_t k = 0;
+            bool any = true;
+            while (any) {
+                any = false;
+                for (int i : order)
+                    if (k < per[i].size()) {
+                        out.push_back(per[i][k]);
+                        any = true;
+                    }
+                ++k;
+            }
+        }
+        return out;
+    };
+    std::vector<BatchBlock> rt = flatten(rows), ct = flatten(cols);
+    if ((int)ct.size() > b->max_col_blocks) return fail(CLAW_E_INVALID, "column chunk too small");
+    // per-instance arguments (x: cur -> cur+1, y: cur+1 -> cur+2)
+    std::vector<char> args(b->args_stride * 2 * n);
+    for (int i = 0; i < n; ++i) {
+        void* bufs[3] = {b->buf[i][0], b->buf[i][1], b->buf[i][2]};
+        for (int dir = 0; dir < 2; ++dir) {
+            char* dst = args.data() + b->args_stride * (2 * i + dir);
+            if (b->fp32) {
+                SweepArgs<float> a = grid_args<float>(b->d[i], SYS_SW, b->plan[i].ncell, bufs, nullptr,
+                                                      b->ctrl[i], dir, dir, dir + 1, chunk);
+                memcpy(dst, &a, sizeof a);
+            } else {
+                SweepArgs<double> a = grid_args<double>(b->d[i], SYS_SW, b->plan[i].ncell, bufs, nullptr,
+                                                        b->ctrl[i], dir, dir, dir + 1, chunk);
+                memcpy(dst, &a, sizeof a);
+            }
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_args, args.data(), args.size(), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_rows, rt.data(), rt.size() * sizeof(BatchBlock), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipMemcpyAsync(b->ws + b->off_cols, ct.data(), ct.size() * sizeof(BatchBlock), hipMemcpyHostToDevice,
+                           b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    b->n_row_blocks = (int)rt.size();
+    b->n_col_blocks = (int)ct.size();
+    b->chunk = chunk;
+    b->schedule = schedule;
+    for (int p = 0; p < 2; ++p) {  // launch sizes changed: recapture
+        if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+        if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
+        b->gexec[p] = nullptr;
+        b->graph[p] = nullptr;
+    }
+    return CLAW_OK;
+}
+
+template <typename R>
+hipError_t batch_sweep(claw_batch* b, int dir, bool speeds, int parity, bool first, bool last, hipStream_t s) {
+    BatchLaunch<R> L;
+    L.blocks = (const BatchBlock*)(b->ws + (dir == 0 ? b->off_rows : b->off_cols));
+    L.args = (const SweepArgs<R>*)(b->ws + b->off_args);
+    L.parity = parity;
+    L.first = first ? 1 : 0;
+    L.last = last ? 1 : 0;
+    L.pad = 0;
+    return launch_batch_sweep<R>(L, SYS_SW, dir, dir == 0 ? b->n_row_blocks : b->n_col_blocks, speeds, s);
+}
+
+hipError_t batch_sweep_any(claw_batch* b, int dir, bool speeds, int parity, bool first, bool last, hipStream_t s) {
+    return b->fp32 ? batch_sweep<float>(b, dir, speeds, parity, first, last, s)
+                   : batch_sweep<double>(b, dir, speeds, parity, first, last, s);
+}
+
+claw_status batch_trial(claw_batch* b, hipStream_t s) {
+    HIP_TRY(batch_sweep_any(b, 0, false, b->parity, true, false, s));
+    HIP_TRY(batch_sweep_any(b, 1, false, b->parity, false, true, s));
+    b->parity ^= 1;
+    return CLAW_OK;
+}
+
+claw_status batch_ctrl(claw_batch* b, int op, double dt = 0, int mode = 0, long long nsteps = 0) {
+    HIP_TRY(launch_batch_ctrl(b->ctrl_ptrs, b->count, op, b->parity ^ 1, dt, mode, 2, nsteps, b->fp32,
+                              b->stream));
+    return CLAW_OK;
+}
+
+claw_status batch_read(claw_batch* b, std::vector<Ctrl>& out) {
+    out.resize(b->count);
+    for (int i = 0; i < b->count; ++i)
+        HIP_TRY(hipMemcpyAsync(&out[i], b->ctrl[i], sizeof(Ctrl), hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return CLAW_OK;
+}
+
+claw_status batch_graph(claw_batch* b) {
+    const int p = b->parity;
+    if (b->gexec[p]) return CLAW_OK;
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    claw_status st = CLAW_OK;
+    for (int k = 0; k < kGraphSteps && st == CLAW_OK; ++k) st = batch_trial(b, b->cap_stream);
+    b->parity = p;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(CLAW_E_HIP, "batch graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec[p], g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        b->gexec[p] = nullptr;
+        return fail(CLAW_E_HIP, "batch graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    b->graph[p] = g;
+    return CLAW_OK;
+}
+
+std::string tune_key(const claw_batch* b) {
+    int64_t cells = 0;
+    for (int i = 0; i < b->count; ++i) cells += b->plan[i].ncell;
+    int lg = 0;
+    while ((int64_t(1) << (lg + 1)) <= cells) ++lg;
+    char key[128];
+    snprintf(key, sizeof key, "gfx950/%s/sw/n%d/cells2^%d", b->fp32 ? "f32" : "f64", b->count, lg);
+    return key;
+}
+
+bool cache_lookup(const char* path, const std::string& key, int* chunk, int* schedule, double* us) {
+    FILE* f = path ? fopen(path, "r") : nullptr;
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const std::string pat = "\"" + key + "\"";
+    while (fgets(line, sizeof line, f)) {
+        const char* p = strstr(line, pat.c_str());
+        if (!p) continue;
+        const char* c = strstr(p, "\"chunk\":");
+        const char* s = strstr(p, "\"schedule\":");
+        const char* u = strstr(p, "\"us_per_step\":");
+        if (c && s && u && sscanf(c + 8, "%d", chunk) == 1 && sscanf(s + 11, "%d", schedule) == 1 &&
+            sscanf(u + 14, "%lf", us) == 1)
+            found = true;
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, const std::string& key, int chunk, int schedule, double us) {
+    if (!path) return;
+    std::vector<std::string> keep;
+    if (FILE* f = fopen(path, "r")) {
+        char line[512];
+        const std::string pat = "\"" + key + "\"";
+        while (fgets(line, sizeof line, f)) {
+            std::string l(line);
+            if (l.find("\"gfx") != std::string::npos && l.find(pat) == std::string::npos) {
+                while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+                keep.push_back(l);
+            }
+        }
+        fclose(f);
+    }
+    char entry[512];
+    snprintf(entry, sizeof entry, "  \"%s\": {\"chunk\": %d, \"schedule\": %d, \"us_per_step\": %.3f}",
+             key.c_str(), chunk, schedule, us);
+    keep.push_back(entry);
+    FILE* f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < keep.size(); ++i) fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+}
+
+}  // namespace
+
+extern "C" {
+
+claw_status claw_batch_workspace_bytes(const claw_desc* descs, int32_t count, size_t* bytes) {
+    claw_status st = batch_validate(descs, count);
+    if (st) return st;
+    if (!bytes) return fail(CLAW_E_INVALID, "bytes is NULL");
+    *bytes = batch_plan(descs, count).total;
+    return CLAW_OK;
+}
+
+claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const* q, void* workspace,
+                              size_t workspace_bytes, void* stream, claw_batch** out) {
+    claw_status st = batch_validate(descs, count);
+    if (st) return st;
+    if (!out || !q || !workspace) return fail(CLAW_E_INVALID, "NULL argument");
+    *out = nullptr;
+    const BatchPlan bp = batch_plan(descs, count);
+    if (workspace_bytes < bp.total)
+        return fail(CLAW_E_INVALID, "workspace too small: %zu < %zu bytes", workspace_bytes, bp.total);
+    if ((uintptr_t)workspace % 256) return fail(CLAW_E_INVALID, "workspace must be 256-byte aligned");
+    for (int i = 0; i < count; ++i)
+        if (!q[i] || (uintptr_t)q[i] % 256) return fail(CLAW_E_INVALID, "q[%d] NULL or not 256-byte aligned", i);
+    claw_batch* b = new (std::nothrow) claw_batch();
+    if (!b) return fail(CLAW_E_HIP, "out of host memory");
+    b->count = count;
+    b->fp32 = descs[0].dtype == CLAW_FP32;
+    b->d.assign(descs, descs + count);
+    b->stream = (hipStream_t)stream;
+    b->ws = (char*)workspace;
+    b->off_ptrs = bp.off_ptrs;
+    b->off_args = bp.off_args;
+    b->off_rows = bp.off_rows;
+    b->off_cols = bp.off_cols;
+    b->off_bufs = bp.off_bufs;
+    b->args_stride = bp.args_stride;
+    b->max_col_blocks = bp.max_col_blocks;
+    b->ctrl_ptrs = (Ctrl**)(b->ws + bp.off_ptrs);
+    size_t off = bp.off_bufs;
+    for (int i = 0; i < count; ++i) {
+        b->plan.push_back(make_plan(&descs[i]));
+        b->ctrl.push_back((Ctrl*)(b->ws + bp.ctrl_stride * i));
+        std::array<void*, 3> bufs;
+        bufs[0] = q[i];
+        bufs[1] = b->ws + off;
+        off += round_up(b->plan[i].state_bytes);
+        bufs[2] = b->ws + off;
+        off += round_up(b->plan[i].state_bytes);
+        b->buf.push_back(bufs);
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(CLAW_E_HIP, "stream create failed: %s", hipGetErrorString(e));
+    }
+    auto bail = [&](claw_status s) {
+        (void)hipStreamDestroy(b->cap_stream);
+        delete b;
+        return s;
+    };
+    for (int i = 0; i < count; ++i) {
+        double dx[3];
+        for (int k = 0; k < 3; ++k) dx[k] = k < 2 ? (descs[i].upper[k] - descs[i].lower[k]) / (double)descs[i].n[k] : 1.0;
+        e = launch_ctrl_init(b->ctrl[i], dx, 2, descs[i].cfl_desired, descs[i].cfl_max, descs[i].dt_max, b->stream);
+        if (e != hipSuccess) return bail(fail(CLAW_E_HIP, "control init failed: %s", hipGetErrorString(e)));
+    }
+    e = hipMemcpyAsync(b->ctrl_ptrs, b->ctrl.data(), sizeof(Ctrl*) * count, hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return bail(fail(CLAW_E_HIP, "upload failed: %s", hipGetErrorString(e)));
+    b->parity = 0;
+    st = batch_tables(b, 32, 0);
+    if (st) return bail(st);
+    *out = b;
+    return CLAW_OK;
+}
+
+claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk_out, int32_t* schedule_out,
+                            double* us_per_step) {
+    if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
+    const std::string key = tune_key(b);
+    int chunk = 0, schedule = 0;
+    double best = 0;
+    bool cached = cache_lookup(cache_path, key, &chunk, &schedule, &best);
+    if (!cached) {
+        // time a few state-preserving trials (dt = 0, always accepted) per candidate
+        claw_status st = batch_ctrl(b, BOP_COMMIT);
+        if (st) return st;
+        std::vector<Ctrl> saved;
+        st = batch_read(b, saved);
+        if (st) return st;
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        best = 1e300;
+        for (int sched = 0; sched < 2; ++sched) {
+            for (int c : kTuneChunks) {
+                st = batch_tables(b, c, sched);
+                if (st) break;
+                const int reps = 6;
+                for (int k = 0; k < 2 + reps && st == CLAW_OK; ++k) {
+                    if (k == 2) HIP_TRY(hipEventRecord(e0, b->stream));
+                    st = batch_ctrl(b, BOP_BEGIN_FIXED, 0.0, MODE_FIXED);
+                    if (!st) st = batch_trial(b, b->stream);
+                    if (!st) st = batch_ctrl(b, BOP_COMMIT);
+                }
+                if (st) break;
+                HIP_TRY(hipEventRecord(e1, b->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                const double us = ms * 1e3 / reps;
+                if (us < best) {
+                    best = us;
+                    chunk = c;
+                    schedule = sched;
+                }
+            }
+            if (st) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st) return st;
+        for (int i = 0; i < b->count; ++i)  // restore the control state the trials advanced
+            HIP_TRY(hipMemcpyAsync(b->ctrl[i], &saved[i], sizeof(Ctrl), hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        cache_store(cache_path, key, chunk, schedule, best);
+    }
+    claw_status st = batch_tables(b, chunk, schedule);
+    if (st) return st;
+    b->tuned_us = best;
+    if (chunk_out) *chunk_out = chunk;
+    if (schedule_out) *schedule_out = schedule;
+    if (us_per_step) *us_per_step = best;
+    return CLAW_OK;
+}
+
+claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule) {
+    if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
+    if (chunk < kBatchChunkMin || (schedule != 0 && schedule != 1)) return fail(CLAW_E_INVALID, "bad tile choice");
+    return batch_tables(b, chunk, schedule);
+}
+
+claw_status claw_batch_advance(claw_batch* b, int64_t nsteps, double* t, int64_t* nreject) {
+    if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
+    if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
+    claw_status st = batch_ctrl(b, BOP_COMMIT);
+    if (st) return st;
+    std::vector<Ctrl> c0;
+    st = batch_read(b, c0);
+    if (st) return st;
+    if (nsteps > 0) {
+        if (!b->have_dt_next) {  // first trial steps from a speed pass of every instance
+            st = batch_ctrl(b, BOP_ZERO_SPEEDS);
+            if (st) return st;
+            for (int dir = 0; dir < 2; ++dir)
+                HIP_TRY(batch_sweep_any(b, dir, true, b->parity ^ 1, false, false, b->stream));
+        }
+        st = batch_ctrl(b, BOP_BEGIN_ADAPT, 0.0, MODE_ADAPT, nsteps);
+        if (st) return st;
+        st = batch_graph(b);
+        if (st) return st;
+        int64_t remaining = nsteps;
+        for (int round = 0; round < 1000 && remaining > 0; ++round) {
+            const int64_t reps = (remaining + kGraphSteps - 1) / kGraphSteps;
+            for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(b->gexec[b->parity], b->stream));
+            st = batch_ctrl(b, BOP_COMMIT);
+            if (st) return st;
+            std::vector<Ctrl> c;
+            st = batch_read(b, c);
+            if (st) return st;
+            remaining = 0;
+            for (int i = 0; i < b->count; ++i) {
+                const StepState& S = c[i].st[b->parity ^ 1];
+                if (S.err) return ctrl_status(S);
+                if (!S.done && S.target - S.accepted > remaining) remaining = S.target - S.accepted;
+            }
+        }
+        b->have_dt_next = true;
+    }
+    for (int i = 0; i < b->count; ++i) {
+        hipError_t e = b->fp32 ? launch_sync_state<float>(b->ctrl[i], b->parity ^ 1, (float*)b->buf[i][0],
+                                                          (float*)b->buf[i][1], (float*)b->buf[i][2],
+                                                          b->plan[i].ncell * 3, b->stream)
+                               : launch_sync_state<double>(b->ctrl[i], b->parity ^ 1, (double*)b->buf[i][0],
+                                                           (double*)b->buf[i][1], (double*)b->buf[i][2],
+                                                           b->plan[i].ncell * 3, b->stream);
+        HIP_TRY(e);
+    }
+    std::vector<Ctrl> c;
+    st = batch_read(b, c);
+    if (st) return st;
+    for (int i = 0; i < b->count; ++i) {
+        const StepState& S = c[i].st[b->parity ^ 1];
+        const StepState& S0 = c0[i].st[b->parity ^ 1];
+        if (t) t[i] = S.t;
+        if (nreject) nreject[i] = S.rejected - S0.rejected;
+        if (S.accepted - S0.accepted != nsteps) return fail(CLAW_E_STATE, "instance %d stopped early", i);
+    }
+    return CLAW_OK;
+}
+
+claw_status claw_batch_destroy(claw_batch* b) {
+    if (!b) return CLAW_OK;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (int p = 0; p < 2; ++p) {
+        if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+        if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
+    }
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    if (e != hipSuccess) return fail(CLAW_E_HIP, "stream sync failed: %s", hipGetErrorString(e));
+    return CLAW_OK;
+}
 
 }  // extern "C"

@@ -1,0 +1,369 @@
+// sweep_body.h -- bodies of the directional sweep kernels (equation
+// LW-update), shared by the single-grid kernels (sweeps.hip) and the batched
+// ensemble kernels (batch.hip).  A body works on one workgroup's share of a
+// grid given its logical block coordinates.
+//
+// The directional sweeps of the split wave-propagation
+// step (equation LW-update): Riemann solve at every interface, wave limiter,
+// correction flux, single-stage cell update and the fused wave-speed maximum.
+//
+// Row kernel (x sweep, the contiguous direction).  A wavefront owns a row
+// segment: every lane holds CPL consecutive cells loaded with one 16-byte
+// vector load per field, solves the CPL interfaces at the left faces of its
+// cells and takes what it misses (left neighbour cell, neighbouring waves,
+// the next lane's left-cell contribution) from the adjacent lanes with DPP
+// wave shifts, so each interface is solved once.  The first and last lane
+// of a wave only supply halo interfaces; neighbouring waves overlap by
+// 2 * CPL cells.  The four wavefronts of a workgroup take four rows.
+//
+// Column kernel (y and z sweeps).  A wavefront owns 64 adjacent columns (one
+// per lane, coalesced rows) and marches along the sweep direction over a
+// chunk of cells with a rolling register window, so each interface is solved
+// once per chunk; rows are prefetched PF rows ahead.
+//
+// Step control needs no kernel of its own: the first sweep of every trial
+// decides the previous trial from its speed maxima (open_trial / decide) and
+// the last sweep clears the speed slots of the other parity.
+//
+// Ghost cells are never stored: a cell index outside the grid is mapped to its
+// source cell by the boundary rule (section 4.1) when it is loaded.
+#pragma once
+
+#include "claw_device.h"
+
+namespace claw {
+
+template <typename R, int CPL>
+struct VecOf {
+    typedef R type __attribute__((ext_vector_type(CPL)));
+};
+
+template <typename R, int SYS, int MEQN>
+__device__ __forceinline__ void make_cell(const R (&q)[MEQN], const R (&zc)[2], int nrm, int tng,
+                                          R sg, bool& bad, Cell<R, SYS>& c) {
+    if constexpr (SYS == SYS_SW) {
+        c.h = q[0];
+        c.mn = q[nrm];
+        c.mt = q[tng];
+        c.derive(sg, bad);
+    } else if constexpr (SYS == SYS_ACV) {
+        c.p = q[0];
+        c.un = q[nrm];
+        c.Z = zc[0];
+        c.c = zc[1];
+    } else {
+        c.p = q[0];
+        c.un = q[nrm];
+    }
+}
+
+template <typename R, int SYS>
+__device__ __forceinline__ void cell_prev(const Cell<R, SYS>& in, Cell<R, SYS>& out) {
+    if constexpr (SYS == SYS_SW) {
+        out.h = lane_prev(in.h);
+        out.mn = lane_prev(in.mn);
+        out.mt = lane_prev(in.mt);
+        out.u = lane_prev(in.u);
+        out.v = lane_prev(in.v);
+        out.sqh = lane_prev(in.sqh);
+        out.c = lane_prev(in.c);
+    } else if constexpr (SYS == SYS_ACV) {
+        out.p = lane_prev(in.p);
+        out.un = lane_prev(in.un);
+        out.Z = lane_prev(in.Z);
+        out.c = lane_prev(in.c);
+    } else {
+        out.p = lane_prev(in.p);
+        out.un = lane_prev(in.un);
+    }
+}
+
+// Applies the two contributions to a cell's fields (normal frame -> fields).
+template <typename R, int SYS, int MEQN>
+__device__ __forceinline__ void apply_update(R (&q)[MEQN], const R (&Rl)[3], const R (&Lr)[3],
+                                             R nu, int nrm, int tng) {
+    q[0] = q[0] - nu * (Rl[0] + Lr[0]);
+    q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
+    if constexpr (SYS == SYS_SW) q[tng] = q[tng] - nu * (Rl[2] + Lr[2]);
+}
+
+template <typename R, int SYS>
+__device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
+    if constexpr (SYS == SYS_AC) return frcp(a.Z0 + a.Z0);
+    return R(0);
+}
+
+// ---------------------------------------------------------------------------
+// Row kernel: x sweep
+// ---------------------------------------------------------------------------
+// bx: segment of the row; by: group of four rows; lead: block (0, 0, 0).
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS>
+__device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, bool lead) {
+    using C = Cell<R, SYS>;
+    using I = Iface<R, SYS>;
+    typedef typename VecOf<R, CPL>::type V;
+    // The buffer of this trial is known before the previous trial is decided
+    // unless that trial gets reverted: load from the predicted buffer first so
+    // the decision's latency overlaps the loads, and reload on a mismatch.
+    const int cur_guess = predicted_cur(a);
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx;
+    const int row = by * 4 + (int)(threadIdx.x >> 6);
+    const bool active = row < a.nrows;
+    const int x0 = bx * (62 * CPL);
+    const int xl = x0 - CPL + lane * CPL;
+    const unsigned base = (unsigned)((active ? row : 0) * nx);
+    const bool vec_ok = (nx % CPL) == 0 && (a.ncell % CPL) == 0;
+    const bool interior = vec_ok && xl >= 0 && xl + CPL <= nx;
+    const R inv2Z = ac_inv2Z<R, SYS>(a);
+    constexpr int nrm = 1, tng = 2;
+
+    // load the lane's cells (ghost cells synthesised at the row ends)
+    R q[CPL][MEQN];
+    R zc[CPL][2];
+    auto load_cells = [&](const R* __restrict__ src) {
+        if (interior) {
+#pragma unroll
+            for (int e = 0; e < MEQN; ++e) {
+                V v = *reinterpret_cast<const V*>(src + (size_t)e * a.ncell + base + (unsigned)xl);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
+            }
+            if constexpr (SYS == SYS_ACV) {
+#pragma unroll
+                for (int f = 0; f < 2; ++f) {
+                    V v = *reinterpret_cast<const V*>(a.zc + (size_t)f * a.ncell + base + (unsigned)xl);
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                bool flip;
+                const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
+#pragma unroll
+                for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
+                if (flip) q[c][nrm] = -q[c][nrm];
+                if constexpr (SYS == SYS_ACV) {
+                    zc[c][0] = a.zc[sidx];
+                    zc[c][1] = a.zc[(size_t)a.ncell + sidx];
+                }
+            }
+        }
+    };
+    load_cells(a.buf[(cur_guess + a.src_off) % 3]);
+
+    const Trial<R> tr = open_trial(a, 0, lead);
+    if (tr.done && !SPEEDS) return;
+    if (tr.cur != cur_guess) load_cells(a.buf[(tr.cur + a.src_off) % 3]);
+    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    const R nu = tr.nu;
+
+    bool bad = false;
+    C cell[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.sqrt_grav, bad, cell[c]);
+    if (!active) bad = false;
+
+    // interfaces at the left face of each cell of this lane
+    C left;
+    cell_prev(cell[CPL - 1], left);
+    I f[CPL];
+    riemann(left, cell[0], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[0]);
+#pragma unroll
+    for (int c = 1; c < CPL; ++c) riemann(cell[c - 1], cell[c], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[c]);
+
+    // largest speed over the interfaces j = x, 0 <= j <= nx, owned by lanes 1..62
+    // (and by lane 63 for j = nx when the row ends exactly at its first cell)
+    R sm = R(0);
+    if (active) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int j = xl + c;
+            const bool own = (lane >= 1 && lane <= 62 && j >= 0 && j <= nx) ||
+                             (lane == 63 && c == 0 && j == nx);
+            if (own) sm = rmax(sm, iface_smax(f[c]));
+        }
+    }
+
+    if constexpr (!SPEEDS) {
+        I fprev, fnext;
+        iface_prev(f[CPL - 1], fprev);
+        iface_next(f[0], fnext);
+        Contrib<R> k[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const I& km = c == 0 ? fprev : f[c - 1];
+            const I& kp = c == CPL - 1 ? fnext : f[c + 1];
+            limit_contrib(f[c], km, kp, nu, a.limiter, k[c]);
+        }
+        R Lnext[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Lnext[i] = lane_next(k[0].L[i]);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nu, nrm, tng);
+            else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nu, nrm, tng);
+        }
+        if (active && lane >= 1 && lane <= 62) {
+            if (interior) {
+#pragma unroll
+                for (int e = 0; e < MEQN; ++e) {
+                    V v;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) v[c] = q[c][e];
+                    *reinterpret_cast<V*>(dst + (size_t)e * a.ncell + base + (unsigned)xl) = v;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    if (xl + c < nx) {
+#pragma unroll
+                        for (int e = 0; e < MEQN; ++e)
+                            dst[(size_t)e * a.ncell + base + (unsigned)(xl + c)] = q[c][e];
+                    }
+                }
+            }
+        }
+    }
+    block_finish(a, 0, sm, bad, lead);
+}
+
+// ---------------------------------------------------------------------------
+// Column kernel: y and z sweeps
+// ---------------------------------------------------------------------------
+template <typename R, int SYS, int MEQN>
+struct ColCell {
+    R q[MEQN];
+    R zc[2];
+};
+
+template <typename R, int SYS, int MEQN, int NRM>
+__device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __restrict__ zcg,
+                                         const SweepArgs<R>& a, int colbase, int y,
+                                         ColCell<R, SYS, MEQN>& out) {
+    bool flip;
+    const unsigned off = (unsigned)(colbase + ghost_idx(y, a.m, a.bc_lo, a.bc_hi, flip) * a.stride);
+#pragma unroll
+    for (int e = 0; e < MEQN; ++e) out.q[e] = src[(size_t)e * a.ncell + off];
+    if (flip) out.q[NRM] = -out.q[NRM];
+    if constexpr (SYS == SYS_ACV) {
+        out.zc[0] = zcg[off];
+        out.zc[1] = zcg[(size_t)a.ncell + off];
+    }
+}
+
+// bx: group of four 64-column strips; by: chunk along the sweep; bz: outer
+// plane; lead: block (0, 0, 0).
+template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
+__device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, int bz, bool lead) {
+    using C = Cell<R, SYS>;
+    using I = Iface<R, SYS>;
+    using CC = ColCell<R, SYS, MEQN>;
+    constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
+    const int dir = a.dir;
+    const Trial<R> tr = open_trial(a, dir, lead);
+    if (tr.done && !SPEEDS) return;
+    const R* __restrict__ src = a.buf[(tr.cur + a.src_off) % 3];
+    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    const R nu = tr.nu;
+    const R inv2Z = ac_inv2Z<R, SYS>(a);
+    const int lane = threadIdx.x & 63;
+    const int nx = a.nx, m = a.m;
+    const int nstrip = (nx + 63) >> 6;
+    const int strip = bx * 4 + (int)(threadIdx.x >> 6);
+    const bool sactive = strip < nstrip;
+    const int x = strip * 64 + lane;
+    const bool xin = sactive && x < nx;
+    const int colbase = bz * a.ostride + (x < nx ? x : nx - 1);
+    const int y0 = by * a.chunk;
+    const int y1 = sactive ? (y0 + a.chunk < m ? y0 + a.chunk : m) : y0;
+
+    bool bad = false;
+    R sm = R(0);
+    CC w0, w1;  // cells y and y+1 of the window
+    C c1;
+    I fb, fc;   // interfaces j = y and j = y + 1
+    R Rb[3];    // right-cell contribution of interface j = y
+    {
+        CC wm2, wm1;
+        C cm2, cm1, c0;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 2, wm2);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 1, wm1);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0, w0);
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 + 1, w1);
+        make_cell<R, SYS, MEQN>(wm2.q, wm2.zc, NRM, TNG, a.sqrt_grav, bad, cm2);
+        make_cell<R, SYS, MEQN>(wm1.q, wm1.zc, NRM, TNG, a.sqrt_grav, bad, cm1);
+        make_cell<R, SYS, MEQN>(w0.q, w0.zc, NRM, TNG, a.sqrt_grav, bad, c0);
+        make_cell<R, SYS, MEQN>(w1.q, w1.zc, NRM, TNG, a.sqrt_grav, bad, c1);
+        I fa;
+        riemann(cm2, cm1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fa);
+        riemann(cm1, c0, a.Z0, a.c0, inv2Z, a.grav, a.efix, fb);
+        riemann(c0, c1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fc);
+        if (y0 == 0) sm = iface_smax(fb);
+        if constexpr (!SPEEDS) {
+            Contrib<R> kb;
+            limit_contrib(fb, fa, fc, nu, a.limiter, kb);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Rb[i] = kb.Rr[i];
+        }
+    }
+
+    // prefetch ring: pre[k] holds row y + 2 + k at the top of each group;
+    // refills past the last needed row (y1 + 1) reload that row instead
+    const int ylast = y1 + 1;
+    CC pre[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int r = y0 + 2 + k;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, pre[k]);
+    }
+
+    // one row of the march: cell yy is finished, the window moves down by one
+    auto step = [&](int yy, CC& slot) {
+        CC w2 = slot;
+        const int r = yy + 2 + PF;
+        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, slot);
+        C c2;
+        make_cell<R, SYS, MEQN>(w2.q, w2.zc, NRM, TNG, a.sqrt_grav, bad, c2);
+        I fd;
+        riemann(c1, c2, a.Z0, a.c0, inv2Z, a.grav, a.efix, fd);
+        sm = rmax(sm, iface_smax(fc));
+        if constexpr (!SPEEDS) {
+            Contrib<R> kc;
+            limit_contrib(fc, fb, fd, nu, a.limiter, kc);
+            apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
+            if (xin) {
+                const unsigned off = (unsigned)(colbase + yy * a.stride);
+#pragma unroll
+                for (int e = 0; e < MEQN; ++e) dst[(size_t)e * a.ncell + off] = w0.q[e];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) Rb[i] = kc.Rr[i];
+        }
+        fb = fc;
+        fc = fd;
+        w0 = w1;
+        w1 = w2;
+        c1 = c2;
+    };
+
+    int y = y0;
+    for (; y + PF <= y1; y += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) step(y + k, pre[k]);
+    }
+    if (y < y1) {  // ragged end of the last chunk
+#pragma unroll
+        for (int k = 0; k < PF; ++k)
+            if (y + k < y1) step(y + k, pre[k]);
+    }
+    if (!xin) {
+        bad = false;
+        sm = R(0);
+    }
+    block_finish(a, dir, sm, bad, lead);
+}
+
+}  // namespace claw

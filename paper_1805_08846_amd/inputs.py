@@ -124,6 +124,34 @@ def acoustics3d_layers(n=256, dtype="f32", nsteps=200, seed=0):
     return prob, round_to(q, dtype), round_to(aux, dtype)
 
 
+def sw_ensemble(count=256, seed=0, nmin=128, nmax=1024, dtype="f32", nsteps=500, sides=None):
+    """Ensemble of 2D shallow-water problems on [0,1]^2 (L = 1), reflecting
+    walls, g = 1, MC, CFL 0.9: side n_k ~ U{nmin..nmax}, hump
+    h = 1 + A exp(-r^2 / w^2) with A ~ U[0.1, 0.5], centre ~ U[0.25, 0.75]^2,
+    w ~ U[0.05, 0.2] L, zero momentum; all draws from default_rng(seed) in the
+    order sides, A, centres, widths.  Returns a list of (prob, q0)."""
+    rng = np.random.default_rng(seed)
+    if sides is None:
+        sides = rng.integers(nmin, nmax + 1, size=count)
+    else:
+        sides = np.asarray(sides)
+        count = len(sides)
+    amp = rng.uniform(0.1, 0.5, size=count)
+    centre = rng.uniform(0.25, 0.75, size=(count, 2))
+    width = rng.uniform(0.05, 0.2, size=count)
+    out = []
+    for k in range(count):
+        n = int(sides[k])
+        prob = _base(2, (n, n), (0, 0), (1, 1), "shallow_water", 3, "wall", grav=1.0,
+                     nsteps=nsteps, dtype=dtype, name="sw_ensemble", member=k)
+        x, y, _ = cell_centers(prob)
+        q = np.zeros((3,) + x.shape)
+        r2 = (x - centre[k, 0]) ** 2 + (y - centre[k, 1]) ** 2
+        q[0] = 1.0 + amp[k] * np.exp(-r2 / width[k] ** 2)
+        out.append((prob, round_to(q, dtype)))
+    return out
+
+
 def problem(name, **kw):
     """(prob, q0, aux) for a named workload; keyword arguments override sizes."""
     return CONFIGS[name](**kw)

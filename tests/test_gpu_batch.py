@@ -1,0 +1,104 @@
+"""Batched shallow-water ensembles through the C ABI (claw_batch_*).
+
+Every instance of a batch must equal the single-grid GPU path bitwise (the
+batched kernels run the same sweep bodies), whatever tiles or schedule the
+autotuner picks, and the small instances must match the CPU oracle.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_08846_amd import inputs
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def claw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+SIDES = [37, 64, 129, 100, 256, 300, 128]
+
+
+def _tensors(members, dtype):
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    return [torch.tensor(q0, dtype=tdt, device="cuda").contiguous() for _, q0 in members]
+
+
+def _single(claw, prob, q0, nsteps):
+    tdt = torch.float32 if prob["dtype"] == "f32" else torch.float64
+    q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
+    s = claw.Solver(prob, q)
+    t, nrej = s.advance(nsteps)
+    torch.cuda.synchronize()
+    out = q.double().cpu().numpy()
+    s.close()
+    return out, t, nrej
+
+
+def _batch(claw, members, dtype, nsteps, tiles=None, tune_path=None):
+    qs = _tensors(members, dtype)
+    b = claw.BatchSolver([p for p, _ in members], qs)
+    if tiles:
+        b.set_tiles(*tiles)
+    if tune_path:
+        b.tune(tune_path)
+    t, nrej = b.advance(nsteps)
+    torch.cuda.synchronize()
+    outs = [q.double().cpu().numpy() for q in qs]
+    b.close()
+    return outs, t, nrej
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_equals_single_grid_bitwise(claw, dtype):
+    members = inputs.sw_ensemble(sides=SIDES, seed=3, dtype=dtype, nsteps=60)
+    outs, ts, rejs = _batch(claw, members, dtype, 60)
+    for k, (prob, q0) in enumerate(members):
+        ref, t, nrej = _single(claw, prob, q0, 60)
+        assert np.array_equal(outs[k], ref), f"instance {k} (n={SIDES[k]}) differs"
+        assert ts[k] == t and rejs[k] == nrej
+
+
+def test_tiles_and_schedules_do_not_change_results(claw):
+    members = inputs.sw_ensemble(sides=SIDES, seed=4, dtype="f32", nsteps=40)
+    base, _, _ = _batch(claw, members, "f32", 40, tiles=(32, 0))
+    for tiles in [(16, 1), (128, 0), (64, 1)]:
+        outs, _, _ = _batch(claw, members, "f32", 40, tiles=tiles)
+        for a, b in zip(outs, base):
+            assert np.array_equal(a, b), tiles
+
+
+def test_autotuner_cache_roundtrip(claw, tmp_path):
+    members = inputs.sw_ensemble(sides=SIDES, seed=5, dtype="f32", nsteps=30)
+    base, _, _ = _batch(claw, members, "f32", 30)
+    cache = str(tmp_path / "tune.json")
+    tuned, _, _ = _batch(claw, members, "f32", 30, tune_path=cache)
+    for a, b in zip(tuned, base):
+        assert np.array_equal(a, b)
+    text = open(cache).read()
+    assert "gfx950/f32/sw/n7/" in text and "chunk" in text
+    qs = _tensors(members, "f32")
+    b = claw.BatchSolver([p for p, _ in members], qs)
+    first = b.tune(cache)
+    again = b.tune(cache)
+    b.close()
+    assert first == again and first["chunk"] in (16, 32, 64, 128)
+
+
+def test_batch_matches_oracle(claw):
+    members = inputs.sw_ensemble(sides=[48, 64], seed=6, dtype="f32", nsteps=50)
+    outs, ts, rejs = _batch(claw, members, "f32", 50)
+    for k, (prob, q0) in enumerate(members):
+        ref = oracle.advance(prob, q0, None, 50)
+        err, per = rel_linf(outs[k], ref["q"])
+        assert err <= 1e-5, per
+        assert rejs[k] == ref["nreject"]
