@@ -98,6 +98,14 @@ struct SweepArgs {
     R Z0, c0;           // constant-coefficient acoustics
 };
 
+// Rotation buffer i (0..2) chosen by selects rather than by indexing the
+// array: a dynamic index into a SweepArgs held in registers would force the
+// whole struct into private memory.
+template <typename R>
+__device__ __forceinline__ R* pick_buf(const SweepArgs<R>& a, int i) {
+    return i == 0 ? a.buf[0] : (i == 1 ? a.buf[1] : a.buf[2]);
+}
+
 // ---------------------------------------------------------------------------
 // Precision helpers.  FP64 keeps correctly rounded division and square root;
 // FP32 uses the hardware reciprocal and square root (about 1 ulp).
@@ -507,9 +515,13 @@ __device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, double v
 template <typename R>
 __device__ __forceinline__ R state_nu(const StepState& s, int dir);
 template <>
-__device__ __forceinline__ float state_nu<float>(const StepState& s, int dir) { return s.dtdx_f[dir]; }
+__device__ __forceinline__ float state_nu<float>(const StepState& s, int dir) {
+    return dir == 0 ? s.dtdx_f[0] : (dir == 1 ? s.dtdx_f[1] : s.dtdx_f[2]);
+}
 template <>
-__device__ __forceinline__ double state_nu<double>(const StepState& s, int dir) { return s.dtdx[dir]; }
+__device__ __forceinline__ double state_nu<double>(const StepState& s, int dir) {
+    return dir == 0 ? s.dtdx[0] : (dir == 1 ? s.dtdx[1] : s.dtdx[2]);
+}
 
 enum { MODE_ADAPT = 0, MODE_STEP = 1, MODE_FIXED = 2 };
 

@@ -152,12 +152,12 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
             }
         }
     };
-    load_cells(a.buf[(cur_guess + a.src_off) % 3]);
+    load_cells(pick_buf(a, (cur_guess + a.src_off) % 3));
 
     const Trial<R> tr = open_trial(a, 0, lead);
     if (tr.done && !SPEEDS) return;
-    if (tr.cur != cur_guess) load_cells(a.buf[(tr.cur + a.src_off) % 3]);
-    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    if (tr.cur != cur_guess) load_cells(pick_buf(a, (tr.cur + a.src_off) % 3));
+    R* __restrict__ dst = pick_buf(a, (tr.cur + a.dst_off) % 3);
     const R nu = tr.nu;
 
     bool bad = false;
@@ -262,11 +262,11 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     using I = Iface<R, SYS>;
     using CC = ColCell<R, SYS, MEQN>;
     constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
-    const int dir = a.dir;
+    constexpr int dir = NRM - 1;  // the normal component of direction d is q[d + 1]
     const Trial<R> tr = open_trial(a, dir, lead);
     if (tr.done && !SPEEDS) return;
-    const R* __restrict__ src = a.buf[(tr.cur + a.src_off) % 3];
-    R* __restrict__ dst = a.buf[(tr.cur + a.dst_off) % 3];
+    const R* __restrict__ src = pick_buf(a, (tr.cur + a.src_off) % 3);
+    R* __restrict__ dst = pick_buf(a, (tr.cur + a.dst_off) % 3);
     const R nu = tr.nu;
     const R inv2Z = ac_inv2Z<R, SYS>(a);
     const int lane = threadIdx.x & 63;
