@@ -196,6 +196,92 @@ claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule)
 claw_status claw_batch_advance(claw_batch* b, int64_t nsteps, double* t, int64_t* nreject);
 claw_status claw_batch_destroy(claw_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse-grid flux correction.
+ *
+ * On a shallow-water grid twice as coarse as a reference run, a small network
+ * maps the four-cell stencil around every interior face to a correction of
+ * that face's flux, and the corrected step is the plain split step followed
+ * by the difference of the corrections (the flux-difference form of the
+ * conservative update, section 3, equation LW-update):
+ *   Q^{n+1} = S(Q^n) - nu_x (dF_{i+1/2} - dF_{i-1/2}) - nu_y (dG_{j+1/2} - dG_{j-1/2}),
+ * nu = dt/dx.  Wall faces carry no correction, so every field's sum changes
+ * by rounding only.  The network (12 -> 64 -> 64 -> 3, ReLU) runs on BF16
+ * matrix cores with FP32 accumulation; its parameters are FP32 masters with
+ * BF16 copies of the weights.  Grids are FP32 (3, ny, nx) states (h, hu, hv)
+ * with reflecting walls on all four sides.
+ *
+ * Face frame: faces along x see (h, hu, hv), faces along y (h, hv, hu) =
+ * (depth, normal momentum, tangential momentum); stencil cells k-2 .. k+1
+ * of face k-1/2, mirrored across a wall with the normal momentum negated.
+ * Inputs per channel c with stencil values a, b, e, f:
+ *   (b - a)/sd[c], (e - b)/sd[c], (f - e)/sd[c], ((b + e)/2 - mu_c)/sl[c]
+ * with mu = (mu_h, 0, 0); the outputs are scaled by s_out[c].
+ * ------------------------------------------------------------------------ */
+#define CLAW_LC_NPARAM 5187 /* W1 (64,12), b1 (64), W2 (64,64), b2 (64), W3 (3,64), b3 (3) */
+
+typedef struct {
+    int64_t nx, ny; /* coarse grid, both >= 2, 3 nx ny < 2^31 */
+    float mu_h;     /* input normalisation */
+    float sd[3], sl[3];
+    float s_out[3]; /* output scale per frame channel */
+} claw_lc_desc;
+
+/* Device bytes of the parameter block (masters, Adam moments, BF16 copies;
+ * layout private except that the first CLAW_LC_NPARAM floats are the FP32
+ * masters in the order above) and of the scratch workspace a grid needs. */
+claw_status claw_lc_sizes(const claw_lc_desc* d, size_t* param_bytes, size_t* work_bytes);
+
+/* After the caller has written the masters: zeroes the Adam moments and
+ * emits the BF16 copies.  Enqueued on `stream`. */
+claw_status claw_lc_init(void* params, void* stream);
+
+/* Corrections of every face of state q: dF (3, ny, nx+1) and dG (3, ny+1, nx)
+ * in state component order, zero on wall faces.  Enqueued. */
+claw_status claw_lc_forward(const claw_lc_desc* d, const void* params, const float* q, float* dF, float* dG,
+                            void* stream);
+
+/* Training pass on one sample: state q = Q^n, plain = S(Q^n), target =
+ * reference state at t^{n+1}.  Loss
+ *   L = sum_{cells, f} w[f] (p - r)^2 / (3 nx ny),  r = target - plain,
+ *   p = -nu_x (dF_{i+1/2} - dF_{i-1/2}) - nu_y (dG_{j+1/2} - dG_{j-1/2}).
+ * Writes the parameter gradient to grad (device, CLAW_LC_NPARAM floats) and,
+ * if loss != NULL, loss[0] = L and loss[1..3] = sum r_f^2 (device doubles).
+ * BF16 rounding points: inputs, weights, activations, and the output and
+ * pre-activation gradients entering products; bias gradients sum unrounded
+ * values.  Enqueued; workspace from claw_lc_sizes. */
+claw_status claw_lc_loss_grad(const claw_lc_desc* d, const void* params, const float* q, const float* target,
+                              const float* plain, double nux, double nuy, const double* w, void* work,
+                              float* grad, double* loss, void* stream);
+
+/* One Adam step (step counts from 1) on the masters with gradient grad, then
+ * new BF16 copies.  Enqueued. */
+claw_status claw_lc_adam(void* params, const float* grad, int64_t step, double lr, double beta1, double beta2,
+                         double eps, void* stream);
+
+/* Fallback and application: out = plain - flux difference of the kept
+ * corrections.  A face keeps its correction when |h_R - h_L| <= tau min(h_L,
+ * h_R) (no shock across it) and nu |d_c| <= kappa max(h_L, h_R) for all three
+ * components (h from qn); then faces next to a cell whose corrected depth is
+ * below half its plain depth, or not positive, are dropped (one pass).  FP32
+ * decisions.  out may alias plain.  keep_x (ny, nx+1) and keep_y (ny+1, nx),
+ * optional, receive 1 where a face kept its correction.  Enqueued. */
+claw_status claw_lc_apply(const claw_lc_desc* d, const float* qn, const float* plain, const float* dF,
+                          const float* dG, double nux, double nuy, double tau, double kappa, float* out,
+                          uint8_t* keep_x, uint8_t* keep_y, void* work, void* stream);
+
+/* 2 x 2 cell averages of a fine FP32 state (3, 2ny, 2nx) into coarse (3, ny, nx).
+ * Enqueued. */
+claw_status claw_lc_coarsen(int64_t nx, int64_t ny, const float* fine, float* coarse, void* stream);
+
+/* nsteps learned coarse steps of fixed dt on solver h (FP32 2D shallow water,
+ * walls, grid d->nx x d->ny): each is the plain split step followed by the
+ * corrections computed from Q^n and applied as above, with no host round trip
+ * between steps.  The state is left in the solver's q.  Synchronises at the end;
+ * CLAW_E_NONPHYSICAL as for claw_advance_fixed. */
+claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* params, int64_t nsteps, double dt,
+                            double tau, double kappa, void* work);
+
 /* Achievable-bandwidth microbenchmark (the paper's achievable roof, section
  * 7.1): streams over device buffers a (read, must be zero-filled) and b
  * (written), each of `bytes` bytes, reps times per kernel, on `stream`, and

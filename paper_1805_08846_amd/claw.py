@@ -30,7 +30,11 @@ EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl",
             "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
             "claw_batch_workspace_bytes", "claw_batch_create", "claw_batch_tune",
             "claw_batch_set_tiles", "claw_batch_advance", "claw_batch_destroy",
+            "claw_lc_sizes", "claw_lc_init", "claw_lc_forward", "claw_lc_loss_grad", "claw_lc_adam",
+            "claw_lc_apply", "claw_lc_coarsen", "claw_lc_advance",
             "claw_stream_bench", "claw_status_string", "claw_last_error"]
+
+CLAW_LC_NPARAM = 5187
 
 
 class claw_desc(ctypes.Structure):
@@ -56,6 +60,17 @@ class claw_desc(ctypes.Structure):
         ("cfl_desired", ctypes.c_double),
         ("cfl_max", ctypes.c_double),
         ("dt_max", ctypes.c_double),
+    ]
+
+
+class claw_lc_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int64),
+        ("ny", ctypes.c_int64),
+        ("mu_h", ctypes.c_float),
+        ("sd", ctypes.c_float * 3),
+        ("sl", ctypes.c_float * 3),
+        ("s_out", ctypes.c_float * 3),
     ]
 
 
@@ -94,6 +109,14 @@ def _load():
         "claw_batch_set_tiles": (i32, [vp, i32, i32]),
         "claw_batch_advance": (i32, [vp, i64, P(dbl), P(i64)]),
         "claw_batch_destroy": (i32, [vp]),
+        "claw_lc_sizes": (i32, [P(claw_lc_desc), P(ctypes.c_size_t), P(ctypes.c_size_t)]),
+        "claw_lc_init": (i32, [vp, vp]),
+        "claw_lc_forward": (i32, [P(claw_lc_desc), vp, vp, vp, vp, vp]),
+        "claw_lc_loss_grad": (i32, [P(claw_lc_desc), vp, vp, vp, vp, dbl, dbl, P(dbl), vp, vp, vp, vp]),
+        "claw_lc_adam": (i32, [vp, vp, i64, dbl, dbl, dbl, dbl, vp]),
+        "claw_lc_apply": (i32, [P(claw_lc_desc), vp, vp, vp, vp, dbl, dbl, dbl, dbl, vp, vp, vp, vp, vp]),
+        "claw_lc_coarsen": (i32, [i64, i64, vp, vp, vp]),
+        "claw_lc_advance": (i32, [vp, P(claw_lc_desc), vp, i64, dbl, dbl, dbl, vp]),
         "claw_status_string": (ctypes.c_char_p, [i32]),
         "claw_last_error": (ctypes.c_char_p, []),
     }
@@ -298,6 +321,111 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# Learned coarse-grid flux correction
+# --------------------------------------------------------------------------
+
+def lc_desc(nx, ny, norm):
+    """claw_lc_desc from a grid and a normalisation dict (mu_h, sd, sl, s_out)."""
+    d = claw_lc_desc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.mu_h = float(norm["mu_h"])
+    for c in range(3):
+        d.sd[c] = float(norm["sd"][c])
+        d.sl[c] = float(norm["sl"][c])
+        d.s_out[c] = float(norm["s_out"][c])
+    return d
+
+
+def claw_lc_sizes(desc):
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.claw_lc_sizes(ctypes.byref(desc), ctypes.byref(pb), ctypes.byref(wb)), "claw_lc_sizes")
+    return pb.value, wb.value
+
+
+def claw_lc_init(params, stream_handle):
+    _check(_lib.claw_lc_init(_ptr(params), ctypes.c_void_p(stream_handle)), "claw_lc_init")
+
+
+def claw_lc_forward(desc, params, q, dF, dG, stream_handle):
+    _check(_lib.claw_lc_forward(ctypes.byref(desc), _ptr(params), _ptr(q), _ptr(dF), _ptr(dG),
+                                ctypes.c_void_p(stream_handle)), "claw_lc_forward")
+
+
+def claw_lc_loss_grad(desc, params, q, target, plain, nux, nuy, w, work, grad, loss, stream_handle):
+    wv = (ctypes.c_double * 3)(*[float(v) for v in w])
+    _check(_lib.claw_lc_loss_grad(ctypes.byref(desc), _ptr(params), _ptr(q), _ptr(target), _ptr(plain),
+                                  float(nux), float(nuy), wv, _ptr(work), _ptr(grad), _ptr(loss),
+                                  ctypes.c_void_p(stream_handle)), "claw_lc_loss_grad")
+
+
+def claw_lc_adam(params, grad, step, lr, beta1, beta2, eps, stream_handle):
+    _check(_lib.claw_lc_adam(_ptr(params), _ptr(grad), int(step), float(lr), float(beta1), float(beta2),
+                             float(eps), ctypes.c_void_p(stream_handle)), "claw_lc_adam")
+
+
+def claw_lc_apply(desc, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x, keep_y, work, stream_handle):
+    _check(_lib.claw_lc_apply(ctypes.byref(desc), _ptr(qn), _ptr(plain), _ptr(dF), _ptr(dG), float(nux),
+                              float(nuy), float(tau), float(kappa), _ptr(out), _ptr(keep_x), _ptr(keep_y),
+                              _ptr(work), ctypes.c_void_p(stream_handle)), "claw_lc_apply")
+
+
+def claw_lc_coarsen(nx, ny, fine, coarse, stream_handle):
+    _check(_lib.claw_lc_coarsen(int(nx), int(ny), _ptr(fine), _ptr(coarse), ctypes.c_void_p(stream_handle)),
+           "claw_lc_coarsen")
+
+
+def claw_lc_advance(h, desc, params, nsteps, dt, tau, kappa, work):
+    _check(_lib.claw_lc_advance(h, ctypes.byref(desc), _ptr(params), int(nsteps), float(dt), float(tau),
+                                float(kappa), _ptr(work)), "claw_lc_advance")
+
+
+class LearnedCorrection:
+    """Parameter block and workspace (torch device buffers) of the learned
+    correction on an nx x ny grid; every method forwards to one C call."""
+
+    def __init__(self, nx, ny, norm, theta, device="cuda", stream=None):
+        import torch
+        self.desc = lc_desc(nx, ny, norm)
+        self.nx, self.ny = int(nx), int(ny)
+        pbytes, wbytes = claw_lc_sizes(self.desc)
+        self.params = torch.zeros(pbytes // 4, dtype=torch.float32, device=device)
+        self.work = torch.empty(wbytes, dtype=torch.uint8, device=device)
+        self.grad = torch.zeros(CLAW_LC_NPARAM, dtype=torch.float32, device=device)
+        self.loss = torch.zeros(4, dtype=torch.float64, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.step_count = 0
+        self.set_theta(theta)
+
+    def set_theta(self, theta):
+        import torch
+        t = torch.as_tensor(np.asarray(theta, dtype=np.float32))
+        self.params[:CLAW_LC_NPARAM].copy_(t)
+        claw_lc_init(self.params, self.stream.cuda_stream)
+        self.step_count = 0
+
+    def theta(self):
+        return self.params[:CLAW_LC_NPARAM].double().cpu().numpy()
+
+    def forward(self, q, dF, dG):
+        claw_lc_forward(self.desc, self.params, q, dF, dG, self.stream.cuda_stream)
+
+    def loss_grad(self, q, target, plain, nux, nuy, w):
+        claw_lc_loss_grad(self.desc, self.params, q, target, plain, nux, nuy, w, self.work, self.grad,
+                          self.loss, self.stream.cuda_stream)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_count += 1
+        claw_lc_adam(self.params, self.grad, self.step_count, lr, beta1, beta2, eps, self.stream.cuda_stream)
+
+    def apply(self, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x=None, keep_y=None):
+        claw_lc_apply(self.desc, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x, keep_y, self.work,
+                      self.stream.cuda_stream)
+
+    def advance(self, solver, nsteps, dt, tau, kappa):
+        claw_lc_advance(solver.h, self.desc, self.params, nsteps, dt, tau, kappa, self.work)
 
 
 def claw_status_string(status):

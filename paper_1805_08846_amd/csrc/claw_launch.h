@@ -41,6 +41,78 @@ hipError_t launch_batch_sweep(const BatchLaunch<R>& L, int sys, int dir, int nbl
 hipError_t launch_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, double dt, int mode,
                              int result_off, long long nsteps, bool fp32, hipStream_t s);
 
+// Learned coarse correction (learned.hip).  Parameters of the 12-64-64-3
+// network, flat: W1 (64, 12), b1, W2 (64, 64), b2, W3 (3, 64), b3.
+enum {
+    LC_NPARAM = 5187,
+    LC_OFF_W1 = 0,
+    LC_OFF_B1 = 768,
+    LC_OFF_W2 = 832,
+    LC_OFF_B2 = 4928,
+    LC_OFF_W3 = 4992,
+    LC_OFF_B3 = 5184
+};
+struct LcNorm {
+    float mu_h;
+    float sd[3], sl[3], s_out[3];
+};
+// Network pass over the interior faces of a (ny, nx) grid.  With ctrl set,
+// the state is rotation buffer (cur + qsel) % 3 of step-state copy cq, and the
+// pass does nothing unless that copy's last trial was accepted.
+struct LcNet {
+    const float* q;
+    const Ctrl* ctrl;
+    int cq, qsel;
+    float *buf0, *buf1, *buf2;
+    int nx, ny, ncell;
+    int ntiles_x, tpr_x, tpr_y, ntiles;
+    LcNorm nm;
+    const float* theta;
+    const unsigned short *w1b, *w2b, *w3b;  // BF16 copies, padded [64][16], [64][64], [16][64]
+    float *dF, *dG;
+    const float* g;  // training: cell gradients (3, ny, nx)
+    float nux, nuy;
+    float* partial;  // training: [waves][LC_NPARAM]
+};
+struct LcCell {
+    const float *dF, *dG, *target, *plain;
+    float* g;
+    double* loss_part;
+    int nx, ny, ncell;
+    float nux, nuy;
+    float w[3], gscale[3];
+};
+// Fallback and application; with ctrl set, qn / plain / out are resolved
+// from the rotation buffers (Q^n at (cur + qsel) % 3, plain and out at cur).
+struct LcApply {
+    const float* qn;
+    const float* plain;
+    float* out;
+    const Ctrl* ctrl;
+    int cq, qsel;
+    float *buf0, *buf1, *buf2;
+    const float *dF, *dG;
+    unsigned char *bad, *keep_x, *keep_y;
+    int nx, ny, ncell;
+    float nux, nuy, tau, kappa;
+};
+struct LcParams {
+    float *theta, *m, *v;
+    unsigned short *w1b, *w2b, *w3b;
+};
+int lc_net_waves(const LcNet& a, int cap);
+int lc_cell_blocks(int64_t ncell);
+hipError_t launch_lc_forward(const LcNet& a, hipStream_t s);
+hipError_t launch_lc_backward(const LcNet& a, hipStream_t s);
+hipError_t launch_lc_cellgrad(const LcCell& a, hipStream_t s);
+hipError_t launch_lc_reduce(const float* partial, int nparts, float* grad, const double* loss_part, int nloss,
+                            double inv3n, double* loss, hipStream_t s);
+hipError_t launch_lc_init(const LcParams& a, hipStream_t s);
+hipError_t launch_lc_adam(const LcParams& a, const float* grad, float lr, float beta1, float beta2, float eps,
+                          float c1, float c2, hipStream_t s);
+hipError_t launch_lc_apply(const LcApply& a, hipStream_t s);
+hipError_t launch_lc_coarsen(const float* fine, float* coarse, int nx, int ny, hipStream_t s);
+
 // Element-wise set-up kernels.
 template <typename R>
 hipError_t launch_derive_zc(const R* aux, R* zc, int64_t ncell, hipStream_t s);

@@ -1,0 +1,689 @@
+// learned.hip -- the learned coarse-grid flux correction: a 12-64-64-3 ReLU
+// network evaluated on every interior interface of a shallow-water grid with
+// BF16 matrix-core products (FP32 accumulation), its fused forward/backward
+// pass for training, Adam on FP32 master weights, the fallback and conservative
+// application of the corrections, and the 2 x 2 coarsening of a fine state.
+//
+// The correction enters the update only as a flux difference, like every flux
+// of the method's conservative update (section 3, equation LW-update):
+//   Q^{n+1} = S(Q^n) - nu_x (dF_{i+1/2} - dF_{i-1/2}) - nu_y (dG_{j+1/2} - dG_{j-1/2})
+// with S the plain split step; wall faces carry no correction, so every
+// field's sum changes by rounding only.
+//
+// Interface frame: a face along direction d sees (h, m_n, m_t) = depth,
+// momentum along d, momentum across d; stencil cells k-2 .. k+1 around face
+// k - 1/2, mirrored across a wall with m_n negated.  Features per channel c:
+// (b - a)/sd_c, (e - b)/sd_c, (f - e)/sd_c, ((b + e)/2 - mu_c)/sl_c.
+//
+// Matrix-core layout (v_mfma_f32_16x16x16_bf16, 64 lanes, lane = n + 16 kb):
+//   A[i][k]  lane i + 16 (k/4), element k%4
+//   B[k][j]  lane j + 16 (k/4), element k%4
+//   D[i][j]  lane j + 16 (i/4), element i%4
+// The network runs transposed, Z^T = W Z_prev^T, with 16 faces as the N
+// dimension: the D tile of a layer is then exactly the B operand of the next
+// layer, so activations never leave registers.  Weight gradients need the
+// faces on the K dimension and go through a per-wavefront LDS transpose.
+#include "claw_launch.h"
+
+namespace claw {
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ short to_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x4 pack4(f32x4 v) {
+    bf16x4 r;
+    r[0] = to_bf16(v[0]);
+    r[1] = to_bf16(v[1]);
+    r[2] = to_bf16(v[2]);
+    r[3] = to_bf16(v[3]);
+    return r;
+}
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+    f32x4 r;
+    for (int e = 0; e < 4; ++e) r[e] = v[e] > 0.0f ? v[e] : 0.0f;
+    return r;
+}
+
+constexpr int WAVES = 4;  // wavefronts per workgroup
+
+// Geometry of one face tile of 64 consecutive faces along a line.
+struct FaceTile {
+    int axis;   // 0: x faces (face k between cells k-1, k of row j); 1: y faces
+    int line;   // x: row j; y: face row k (between rows k-1 and k)
+    int first;  // x: first face k; y: first column i
+};
+
+__device__ __forceinline__ float* pick3(float* b0, float* b1, float* b2, int i) {
+    return i == 0 ? b0 : (i == 1 ? b1 : b2);
+}
+
+__device__ __forceinline__ FaceTile tile_of(const LcNet& a, int t) {
+    FaceTile ft;
+    if (t < a.ntiles_x) {
+        ft.axis = 0;
+        ft.line = t / a.tpr_x;
+        ft.first = 1 + (t - ft.line * a.tpr_x) * 64;
+    } else {
+        const int u = t - a.ntiles_x;
+        ft.axis = 1;
+        ft.line = 1 + u / a.tpr_y;
+        ft.first = (u - (ft.line - 1) * a.tpr_y) * 64;
+    }
+    return ft;
+}
+
+// Field of frame channel c on faces of `axis`: x (h, hu, hv), y (h, hv, hu).
+__device__ __forceinline__ int frame_field(int axis, int c) { return (axis == 0 || c == 0) ? c : 3 - c; }
+
+// Stencil value s (0..3 = cells k-2 .. k+1) of channel c for face `pos` of
+// tile ft (pos: x face index k, y column i), with the wall mirror.
+__device__ __forceinline__ float stencil(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
+                                         int pos, int c, int s) {
+    const int f = frame_field(ft.axis, c);
+    const int n = ft.axis == 0 ? a.nx : a.ny;
+    int idx = (ft.axis == 0 ? pos : ft.line) - 2 + s;
+    float sign = 1.0f;
+    if (idx < 0) {
+        idx = -1 - idx;
+        if (c == 1) sign = -1.0f;
+    } else if (idx >= n) {
+        idx = 2 * n - 1 - idx;
+        if (c == 1) sign = -1.0f;
+    }
+    const int cell = ft.axis == 0 ? ft.line * a.nx + idx : idx * a.nx + pos;
+    return sign * q[(size_t)f * a.ncell + cell];
+}
+
+// Weights of one wavefront in operand registers.
+struct NetRegs {
+    bf16x4 A1[4];      // W1 tiles (units 16t.., features)
+    bf16x4 A2[4][4];   // W2 tiles [t][s]
+    bf16x4 A3[4];      // W3 (outputs, units 16s..)
+    f32x4 B1[4], B2[4], B3;
+};
+
+__device__ __forceinline__ void load_net(const LcNet& a, int lane, NetRegs& R) {
+    const int i = lane & 15, kb = lane >> 4;
+    for (int t = 0; t < 4; ++t) {
+        for (int e = 0; e < 4; ++e) {
+            R.A1[t][e] = (short)a.w1b[(16 * t + i) * 16 + 4 * kb + e];
+            R.B1[t][e] = a.theta[LC_OFF_B1 + 16 * t + 4 * kb + e];
+            R.B2[t][e] = a.theta[LC_OFF_B2 + 16 * t + 4 * kb + e];
+            R.A3[t][e] = (short)a.w3b[i * 64 + 16 * t + 4 * kb + e];
+        }
+        for (int s = 0; s < 4; ++s)
+            for (int e = 0; e < 4; ++e) R.A2[t][s][e] = (short)a.w2b[(16 * t + i) * 64 + 16 * s + 4 * kb + e];
+    }
+    for (int e = 0; e < 4; ++e) {
+        const int o = 4 * kb + e;
+        R.B3[e] = o < 3 ? a.theta[LC_OFF_B3 + o] : 0.0f;
+    }
+}
+
+// Inputs of 16 faces (group g of the tile) as the B operand: lane n + 16 kb
+// holds the four features of channel kb (none for kb = 3).
+__device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
+                                           int pos, int lane) {
+    const int kb = lane >> 4;
+    bf16x4 x = {0, 0, 0, 0};
+    if (kb < 3) {
+        const float v0 = stencil(a, q, ft, pos, kb, 0);
+        const float v1 = stencil(a, q, ft, pos, kb, 1);
+        const float v2 = stencil(a, q, ft, pos, kb, 2);
+        const float v3 = stencil(a, q, ft, pos, kb, 3);
+        const float sd = a.nm.sd[kb], sl = a.nm.sl[kb];
+        const float mu = kb == 0 ? a.nm.mu_h : 0.0f;
+        x[0] = to_bf16((v1 - v0) / sd);
+        x[1] = to_bf16((v2 - v1) / sd);
+        x[2] = to_bf16((v3 - v2) / sd);
+        x[3] = to_bf16(((v1 + v2) * 0.5f - mu) / sl);
+    }
+    return x;
+}
+
+struct Acts {
+    bf16x4 h1[4], h2[4];
+    f32x4 y;
+};
+
+__device__ __forceinline__ void net_forward(const NetRegs& R, bf16x4 x, Acts& A) {
+    for (int t = 0; t < 4; ++t) A.h1[t] = pack4(relu4(mma(R.A1[t], x, R.B1[t])));
+    for (int t = 0; t < 4; ++t) {
+        f32x4 z = R.B2[t];
+        for (int s = 0; s < 4; ++s) z = mma(R.A2[t][s], A.h1[s], z);
+        A.h2[t] = pack4(relu4(z));
+    }
+    f32x4 y = R.B3;
+    for (int s = 0; s < 4; ++s) y = mma(R.A3[s], A.h2[s], y);
+    A.y = y;
+}
+
+// Face position of lane n in group g, clamped into the line; valid flag.
+// (x tiles: faces 1 .. nx-1; y tiles: columns 0 .. nx-1 -- the same last index)
+__device__ __forceinline__ int face_pos(const LcNet& a, const FaceTile& ft, int g, int n, bool& valid) {
+    const int pos = ft.first + 16 * g + n;
+    valid = pos <= a.nx - 1;
+    return valid ? pos : a.nx - 1;
+}
+
+__device__ __forceinline__ const float* resolve_state(const LcNet& a, bool& skip) {
+    skip = false;
+    if (!a.ctrl) return a.q;
+    const StepState& s = a.ctrl->st[a.cq];
+    if (s.err || !s.last_accepted) {
+        skip = true;
+        return a.q;
+    }
+    return pick3(a.buf0, a.buf1, a.buf2, (s.cur + a.qsel) % 3);
+}
+
+// Forward pass over every interior face: corrections dF (3, ny, nx+1) and
+// dG (3, ny+1, nx) in state component order; wall faces written as zero.
+__global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
+    bool skip;
+    const float* __restrict__ q = resolve_state(a, skip);
+    if (skip) return;
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, kb = lane >> 4;
+    NetRegs R;
+    load_net(a, lane, R);
+    const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * WAVES;
+    const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
+    for (int t = wave; t < a.ntiles; t += nwaves) {
+        const FaceTile ft = tile_of(a, t);
+        for (int g = 0; g < 4; ++g) {
+            bool valid;
+            const int pos = face_pos(a, ft, g, n, valid);
+            const bf16x4 x = features(a, q, ft, pos, lane);
+            Acts A;
+            net_forward(R, x, A);
+            if (kb == 0 && valid) {
+                for (int c = 0; c < 3; ++c) {
+                    const float v = a.nm.s_out[c] * A.y[c];
+                    const int f = frame_field(ft.axis, c);
+                    if (ft.axis == 0)
+                        a.dF[f * fx + (size_t)ft.line * (a.nx + 1) + pos] = v;
+                    else
+                        a.dG[f * fy + (size_t)ft.line * a.nx + pos] = v;
+                }
+            }
+        }
+        // wall faces: x faces 0 and nx of this row; y face rows 0 and ny
+        if (ft.axis == 0 && ft.first == 1 && lane < 6) {
+            const int c = lane % 3;
+            const int k = lane < 3 ? 0 : a.nx;
+            a.dF[c * fx + (size_t)ft.line * (a.nx + 1) + k] = 0.0f;
+        }
+        if (ft.axis == 1 && (ft.line == 1 || ft.line == a.ny - 1)) {
+            const int i = ft.first + lane;
+            if (i < a.nx)
+                for (int c = 0; c < 3; ++c) {
+                    if (ft.line == 1) a.dG[c * fy + i] = 0.0f;
+                    if (ft.line == a.ny - 1) a.dG[c * fy + (size_t)a.ny * a.nx + i] = 0.0f;
+                }
+        }
+    }
+}
+
+// LDS transpose area of one wavefront, BF16, feature/unit-major [row][16 faces].
+struct WaveLds {
+    short x[16 * 16];
+    short h1[64 * 16], h2[64 * 16], z1[64 * 16], z2[64 * 16];
+    short y[16 * 16];
+};
+
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Store a D-layout tile (lane n + 16 kb, element e -> row 16 t + 4 kb + e, face n).
+__device__ __forceinline__ void put_tile(short* base, int t, int lane, bf16x4 v) {
+    const int n = lane & 15, kb = lane >> 4;
+    for (int e = 0; e < 4; ++e) base[(16 * t + 4 * kb + e) * 16 + n] = v[e];
+}
+// Operand with rows 16 t + (lane & 15) and the four faces 4 kb .. 4 kb + 3.
+__device__ __forceinline__ bf16x4 get_rows(const short* base, int t, int lane) {
+    const int i = lane & 15, kb = lane >> 4;
+    const short* p = base + (16 * t + i) * 16 + 4 * kb;
+    bf16x4 r;
+    r[0] = p[0];
+    r[1] = p[1];
+    r[2] = p[2];
+    r[3] = p[3];
+    return r;
+}
+
+// Fused training pass: forward again, output gradient from the cell
+// gradients g (dL/dF_{k-1/2} = nu (g_k - g_{k-1})), backward through the
+// network, and per-wavefront partial parameter gradients.
+__global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
+    __shared__ WaveLds lds_all[WAVES];
+    WaveLds& L = lds_all[threadIdx.x >> 6];
+    const float* __restrict__ q = a.q;
+    const int lane = threadIdx.x & 63;
+    const int n = lane & 15, kb = lane >> 4;
+    NetRegs R;
+    load_net(a, lane, R);
+    // transposed weights for the backward products
+    bf16x4 T3[4], T2[4][4];
+    for (int t = 0; t < 4; ++t) {
+        for (int e = 0; e < 4; ++e) {
+            const int o = 4 * kb + e;
+            T3[t][e] = o < 3 ? (short)a.w3b[o * 64 + 16 * t + n] : (short)0;
+        }
+        for (int s = 0; s < 4; ++s)
+            for (int e = 0; e < 4; ++e) T2[t][s][e] = (short)a.w2b[(16 * s + 4 * kb + e) * 64 + 16 * t + n];
+    }
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc1[4], acc2[4][4], acc3[4], sb1[4], sb2[4];
+    float sb3[3] = {0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 4; ++t) {
+        acc1[t] = zero;
+        acc3[t] = zero;
+        sb1[t] = zero;
+        sb2[t] = zero;
+        for (int s = 0; s < 4; ++s) acc2[t][s] = zero;
+    }
+    const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * WAVES;
+    for (int t = wave; t < a.ntiles; t += nwaves) {
+        const FaceTile ft = tile_of(a, t);
+        const float nu = ft.axis == 0 ? a.nux : a.nuy;
+        for (int grp = 0; grp < 4; ++grp) {
+            bool valid;
+            const int pos = face_pos(a, ft, grp, n, valid);
+            const bf16x4 x = features(a, q, ft, pos, lane);
+            Acts A;
+            net_forward(R, x, A);
+            // output gradient (lanes kb = 0 hold the three channels of face n)
+            float dy[3] = {0.0f, 0.0f, 0.0f};
+            if (kb == 0 && valid) {
+                for (int c = 0; c < 3; ++c) {
+                    const int f = frame_field(ft.axis, c);
+                    const float* gf = a.g + (size_t)f * a.ncell;
+                    float gr, gl;
+                    if (ft.axis == 0) {
+                        gr = gf[ft.line * a.nx + pos];
+                        gl = gf[ft.line * a.nx + pos - 1];
+                    } else {
+                        gr = gf[ft.line * a.nx + pos];
+                        gl = gf[(ft.line - 1) * a.nx + pos];
+                    }
+                    dy[c] = a.nm.s_out[c] * (nu * (gr - gl));
+                }
+            }
+            for (int c = 0; c < 3; ++c) sb3[c] += dy[c];
+            bf16x4 dyb = {0, 0, 0, 0};
+            if (kb == 0) {
+                dyb[0] = to_bf16(dy[0]);
+                dyb[1] = to_bf16(dy[1]);
+                dyb[2] = to_bf16(dy[2]);
+            }
+            bf16x4 dz2b[4], dz1b[4];
+            for (int t2 = 0; t2 < 4; ++t2) {
+                f32x4 d = mma(T3[t2], dyb, zero);
+                for (int e = 0; e < 4; ++e) d[e] = A.h2[t2][e] > 0 ? d[e] : 0.0f;  // bf16 > 0 as an integer
+                sb2[t2] += d;
+                dz2b[t2] = pack4(d);
+            }
+            for (int t1 = 0; t1 < 4; ++t1) {
+                f32x4 d = zero;
+                for (int s = 0; s < 4; ++s) d = mma(T2[t1][s], dz2b[s], d);
+                for (int e = 0; e < 4; ++e) d[e] = A.h1[t1][e] > 0 ? d[e] : 0.0f;
+                sb1[t1] += d;
+                dz1b[t1] = pack4(d);
+            }
+            // transposes through LDS: rows are units / features / outputs, columns faces
+            put_tile(L.x, 0, lane, x);
+            for (int t4 = 0; t4 < 4; ++t4) {
+                put_tile(L.h1, t4, lane, A.h1[t4]);
+                put_tile(L.h2, t4, lane, A.h2[t4]);
+                put_tile(L.z1, t4, lane, dz1b[t4]);
+                put_tile(L.z2, t4, lane, dz2b[t4]);
+            }
+            put_tile(L.y, 0, lane, dyb);
+            lds_sync();
+            const bf16x4 xr = get_rows(L.x, 0, lane);
+            bf16x4 yr = get_rows(L.y, 0, lane);
+            if (n >= 3) yr = bf16x4{0, 0, 0, 0};
+            for (int tk = 0; tk < 4; ++tk) {
+                const bf16x4 h1r = get_rows(L.h1, tk, lane);
+                const bf16x4 h2r = get_rows(L.h2, tk, lane);
+                acc3[tk] = mma(yr, h2r, acc3[tk]);
+                for (int tu = 0; tu < 4; ++tu) acc2[tu][tk] = mma(get_rows(L.z2, tu, lane), h1r, acc2[tu][tk]);
+            }
+            for (int tu = 0; tu < 4; ++tu) acc1[tu] = mma(get_rows(L.z1, tu, lane), xr, acc1[tu]);
+            lds_sync();
+        }
+    }
+    // partial gradients of this wavefront, in the parameter order
+    float* P = a.partial + (size_t)wave * LC_NPARAM;
+    for (int tu = 0; tu < 4; ++tu)
+        for (int e = 0; e < 4; ++e) {
+            const int u = 16 * tu + 4 * kb + e;
+            if (n < 12) P[LC_OFF_W1 + u * 12 + n] = acc1[tu][e];
+            for (int tk = 0; tk < 4; ++tk) P[LC_OFF_W2 + u * 64 + 16 * tk + n] = acc2[tu][tk][e];
+        }
+    if (kb == 0)
+        for (int tk = 0; tk < 4; ++tk)
+            for (int e = 0; e < 3; ++e) P[LC_OFF_W3 + e * 64 + 16 * tk + n] = acc3[tk][e];
+    // bias gradients: sum over the 16 faces (lanes) of each row group
+    for (int t = 0; t < 4; ++t)
+        for (int e = 0; e < 4; ++e) {
+            float v1 = sb1[t][e], v2 = sb2[t][e];
+            for (int m = 1; m < 16; m <<= 1) {
+                v1 += __shfl_xor(v1, m);
+                v2 += __shfl_xor(v2, m);
+            }
+            if (n == 0) {
+                P[LC_OFF_B1 + 16 * t + 4 * kb + e] = v1;
+                P[LC_OFF_B2 + 16 * t + 4 * kb + e] = v2;
+            }
+        }
+    for (int c = 0; c < 3; ++c) {
+        float v = sb3[c];
+        for (int m = 1; m < 16; m <<= 1) v += __shfl_xor(v, m);
+        if (lane == 0) P[LC_OFF_B3 + c] = v;
+    }
+}
+
+// Cell gradients of the loss  sum w_f (p - r)^2 / (3N),  p the correction's
+// flux difference and r = target - plain; per-block partial sums
+// (loss numerator, sum r_f^2) in FP64.
+__global__ __launch_bounds__(256) void k_lc_cellgrad(LcCell a) {
+    __shared__ double red[4][256];
+    const int tid = threadIdx.x;
+    double acc[4] = {0, 0, 0, 0};
+    const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
+    for (int c = blockIdx.x * 256 + tid; c < a.ncell; c += gridDim.x * 256) {
+        const int j = c / a.nx, i = c - j * a.nx;
+        for (int f = 0; f < 3; ++f) {
+            const float* F = a.dF + f * fx + (size_t)j * (a.nx + 1);
+            const float* G = a.dG + f * fy;
+            const float p = -a.nux * (F[i + 1] - F[i]) - a.nuy * (G[(size_t)(j + 1) * a.nx + i] - G[(size_t)j * a.nx + i]);
+            const float r = a.target[(size_t)f * a.ncell + c] - a.plain[(size_t)f * a.ncell + c];
+            const float d = p - r;
+            a.g[(size_t)f * a.ncell + c] = a.gscale[f] * d;
+            acc[0] += (double)a.w[f] * (double)d * (double)d;
+            acc[1 + f] += (double)r * (double)r;
+        }
+    }
+    for (int k = 0; k < 4; ++k) red[k][tid] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            for (int k = 0; k < 4; ++k) red[k][tid] += red[k][tid + s];
+        __syncthreads();
+    }
+    if (tid < 4) a.loss_part[blockIdx.x * 4 + tid] = red[tid][0];
+}
+
+// Sum of the per-wavefront partial gradients (fixed order) into grad, and of
+// the loss partials into loss[0..3] (the first block's spare threads).
+__global__ __launch_bounds__(256) void k_lc_reduce(const float* __restrict__ partial, int nparts, float* grad,
+                                                   const double* __restrict__ loss_part, int nloss, double inv3n,
+                                                   double* loss) {
+    __shared__ float red[4][64];
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int part = threadIdx.x >> 6;
+    float s = 0.0f;
+    if (p < LC_NPARAM)
+        for (int w = part; w < nparts; w += 4) s += partial[(size_t)w * LC_NPARAM + p];
+    red[part][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (part == 0 && p < LC_NPARAM) grad[p] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                               red[3][threadIdx.x];
+    if (blockIdx.x == 0 && threadIdx.x < 4 && loss) {
+        double v = 0.0;
+        for (int b = 0; b < nloss; ++b) v += loss_part[b * 4 + threadIdx.x];
+        loss[threadIdx.x] = threadIdx.x == 0 ? v * inv3n : v;
+    }
+}
+
+__device__ __forceinline__ void emit_bf16(LcParams a, int p, float v) {
+    if (p < LC_OFF_B1) {
+        a.w1b[(p / 12) * 16 + p % 12] = (unsigned short)to_bf16(v);
+    } else if (p >= LC_OFF_W2 && p < LC_OFF_B2) {
+        a.w2b[p - LC_OFF_W2] = (unsigned short)to_bf16(v);
+    } else if (p >= LC_OFF_W3 && p < LC_OFF_B3) {
+        const int o = (p - LC_OFF_W3) / 64, k = (p - LC_OFF_W3) % 64;
+        a.w3b[o * 64 + k] = (unsigned short)to_bf16(v);
+    }
+}
+
+// Zero the moments and the BF16 padding, then emit the BF16 weight copies.
+__global__ void k_lc_init(LcParams a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < 64 * 16) a.w1b[p] = 0;
+    if (p < 16 * 64) a.w3b[p] = 0;
+    if (p < LC_NPARAM) {
+        a.m[p] = 0.0f;
+        a.v[p] = 0.0f;
+    }
+}
+__global__ void k_lc_emit(LcParams a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < LC_NPARAM) emit_bf16(a, p, a.theta[p]);
+}
+
+// Adam on the FP32 masters (c1 = 1/(1 - beta1^t), c2 = 1/(1 - beta2^t)),
+// then the BF16 copy of the new weight.
+__global__ void k_lc_adam(LcParams a, const float* __restrict__ grad, float lr, float beta1, float beta2, float eps,
+                          float c1, float c2) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= LC_NPARAM) return;
+    const float g = grad[p];
+    const float m = beta1 * a.m[p] + (1.0f - beta1) * g;
+    const float v = beta2 * a.v[p] + (1.0f - beta2) * g * g;
+    a.m[p] = m;
+    a.v[p] = v;
+    const float th = a.theta[p] - lr * (m * c1) / (sqrtf(v * c2) + eps);
+    a.theta[p] = th;
+    emit_bf16(a, p, th);
+}
+
+// ---------------------------------------------------------------------------
+// Fallback and application (FP32, no contraction: the decisions must not
+// depend on how the compiler fuses the products).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float fmul(float x, float y) { return __fmul_rn(x, y); }
+__device__ __forceinline__ float fsub(float x, float y) { return __fsub_rn(x, y); }
+__device__ __forceinline__ float fadd(float x, float y) { return __fadd_rn(x, y); }
+
+struct ApplyState {
+    const float* qn;
+    const float* plain;
+    float* out;
+};
+
+__device__ __forceinline__ bool resolve_apply(const LcApply& a, ApplyState& S) {
+    S.qn = a.qn;
+    S.plain = a.plain;
+    S.out = a.out;
+    if (!a.ctrl) return true;
+    const StepState& s = a.ctrl->st[a.cq];
+    if (s.err || !s.last_accepted) return false;
+    S.qn = pick3(a.buf0, a.buf1, a.buf2, (s.cur + a.qsel) % 3);
+    S.out = pick3(a.buf0, a.buf1, a.buf2, s.cur);
+    S.plain = S.out;  // in place: each cell reads only its own plain values
+    return true;
+}
+
+// Indicator test of x face k of row j (1 <= k <= nx-1) or y face row k of column i.
+__device__ __forceinline__ bool face_ok(const LcApply& a, float hl, float hr, const float* __restrict__ d,
+                                        size_t stride, float nu) {
+    const float lo = hl < hr ? hl : hr;
+    const float hi = hl > hr ? hl : hr;
+    bool ok = fabsf(fsub(hr, hl)) <= fmul(a.tau, lo);
+    const float bound = fmul(a.kappa, hi);
+    for (int c = 0; c < 3; ++c) ok = ok && (fmul(nu, fabsf(d[c * stride])) <= bound);
+    return ok;
+}
+
+struct FaceKeep {
+    bool l, r, b, t;
+};
+
+__device__ __forceinline__ FaceKeep keep_of(const LcApply& a, const float* __restrict__ h, int i, int j) {
+    const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
+    const int nx = a.nx, ny = a.ny;
+    const float hc = h[j * nx + i];
+    FaceKeep k;
+    k.l = i > 0 && face_ok(a, h[j * nx + i - 1], hc, a.dF + (size_t)j * (nx + 1) + i, fx, a.nux);
+    k.r = i < nx - 1 && face_ok(a, hc, h[j * nx + i + 1], a.dF + (size_t)j * (nx + 1) + i + 1, fx, a.nux);
+    k.b = j > 0 && face_ok(a, h[(j - 1) * nx + i], hc, a.dG + (size_t)j * nx + i, fy, a.nuy);
+    k.t = j < ny - 1 && face_ok(a, hc, h[(j + 1) * nx + i], a.dG + (size_t)(j + 1) * nx + i, fy, a.nuy);
+    return k;
+}
+
+__device__ __forceinline__ float corrected(const LcApply& a, float plain, int f, int i, int j, const FaceKeep& k) {
+    const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
+    const float* F = a.dF + f * fx + (size_t)j * (a.nx + 1);
+    const float* G = a.dG + f * fy;
+    const float Fl = k.l ? F[i] : 0.0f, Fr = k.r ? F[i + 1] : 0.0f;
+    const float Gb = k.b ? G[(size_t)j * a.nx + i] : 0.0f, Gt = k.t ? G[(size_t)(j + 1) * a.nx + i] : 0.0f;
+    const float cx = fmul(a.nux, fsub(Fr, Fl));
+    const float cy = fmul(a.nuy, fsub(Gt, Gb));
+    return fsub(plain, fadd(cx, cy));
+}
+
+// Pass 1: cells whose depth the indicator-filtered correction would push
+// below half the plain depth, or to zero or below.
+__global__ __launch_bounds__(256) void k_lc_apply1(LcApply a) {
+    ApplyState S;
+    if (!resolve_apply(a, S)) return;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < a.ncell; c += gridDim.x * 256) {
+        const int j = c / a.nx, i = c - j * a.nx;
+        const FaceKeep k = keep_of(a, S.qn, i, j);
+        const float p = S.plain[c];
+        const float o = corrected(a, p, 0, i, j, k);
+        a.bad[c] = (o < fmul(0.5f, p) || o <= 0.0f) ? 1 : 0;
+    }
+}
+
+// Pass 2: faces next to a bad cell are dropped; every field is updated.
+__global__ __launch_bounds__(256) void k_lc_apply2(LcApply a) {
+    ApplyState S;
+    if (!resolve_apply(a, S)) return;
+    const int nx = a.nx;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < a.ncell; c += gridDim.x * 256) {
+        const int j = c / nx, i = c - j * nx;
+        FaceKeep k = keep_of(a, S.qn, i, j);
+        const bool me = a.bad[c] != 0;
+        k.l = k.l && !me && !a.bad[c - 1 + (i == 0)];
+        k.r = k.r && !me && !a.bad[c + 1 - (i == nx - 1)];
+        k.b = k.b && !me && !a.bad[c - (j > 0 ? nx : 0)];
+        k.t = k.t && !me && !a.bad[c + (j < a.ny - 1 ? nx : 0)];
+        float o[3];
+        for (int f = 0; f < 3; ++f) o[f] = corrected(a, S.plain[(size_t)f * a.ncell + c], f, i, j, k);
+        for (int f = 0; f < 3; ++f) S.out[(size_t)f * a.ncell + c] = o[f];
+        if (a.keep_x) {
+            if (i == 0) a.keep_x[(size_t)j * (nx + 1)] = 0;
+            a.keep_x[(size_t)j * (nx + 1) + i + 1] = k.r ? 1 : 0;
+        }
+        if (a.keep_y) {
+            if (j == 0) a.keep_y[i] = 0;
+            a.keep_y[(size_t)(j + 1) * nx + i] = k.t ? 1 : 0;
+        }
+    }
+}
+
+// 2 x 2 averages: coarse (3, ny, nx) from fine (3, 2ny, 2nx).
+__global__ __launch_bounds__(256) void k_lc_coarsen(const float* __restrict__ fine, float* __restrict__ coarse,
+                                                    int nx, int ny) {
+    const int ncell = nx * ny;
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < 3 * ncell; c += gridDim.x * 256) {
+        const int f = c / ncell, r = c - f * ncell;
+        const int j = r / nx, i = r - j * nx;
+        const float* F = fine + (size_t)f * 4 * ncell + (size_t)(2 * j) * (2 * nx) + 2 * i;
+        coarse[c] = 0.25f * ((F[0] + F[1]) + (F[2 * nx] + F[2 * nx + 1]));
+    }
+}
+
+int blocks_for(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (int)(b < 8192 ? (b > 0 ? b : 1) : 8192);
+}
+
+}  // namespace
+
+// Wavefronts of a network launch: one per face tile, at most `cap`, rounded
+// up to whole workgroups (the training pass writes one partial per wavefront).
+int lc_net_waves(const LcNet& a, int cap) {
+    const int w = a.ntiles < cap ? a.ntiles : cap;
+    return ((w + WAVES - 1) / WAVES) * WAVES;
+}
+
+hipError_t launch_lc_forward(const LcNet& a, hipStream_t s) {
+    const int w = lc_net_waves(a, 4096);
+    if (w <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lc_forward, dim3(w / WAVES), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_backward(const LcNet& a, hipStream_t s) {
+    const int w = lc_net_waves(a, 1024);
+    if (w <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lc_backward, dim3(w / WAVES), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int lc_cell_blocks(int64_t ncell) { return blocks_for(ncell) < 1024 ? blocks_for(ncell) : 1024; }
+
+hipError_t launch_lc_cellgrad(const LcCell& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_cellgrad, dim3(lc_cell_blocks(a.ncell)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_reduce(const float* partial, int nparts, float* grad, const double* loss_part, int nloss,
+                            double inv3n, double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_reduce, dim3((LC_NPARAM + 63) / 64), dim3(256), 0, s, partial, nparts, grad, loss_part,
+                       nloss, inv3n, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_init(const LcParams& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_init, dim3((LC_NPARAM + 255) / 256), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lc_emit, dim3((LC_NPARAM + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_adam(const LcParams& a, const float* grad, float lr, float beta1, float beta2, float eps,
+                          float c1, float c2, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_adam, dim3((LC_NPARAM + 255) / 256), dim3(256), 0, s, a, grad, lr, beta1, beta2, eps,
+                       c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_apply(const LcApply& a, hipStream_t s) {
+    const int b = blocks_for(a.ncell);
+    hipLaunchKernelGGL(k_lc_apply1, dim3(b), dim3(256), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lc_apply2, dim3(b), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_coarsen(const float* fine, float* coarse, int nx, int ny, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_coarsen, dim3(blocks_for(3LL * nx * ny)), dim3(256), 0, s, fine, coarse, nx, ny);
+    return hipGetLastError();
+}
+
+}  // namespace claw

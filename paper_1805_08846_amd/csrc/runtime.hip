@@ -1155,3 +1155,297 @@ claw_status claw_batch_destroy(claw_batch* b) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Learned coarse-grid flux correction (learned.hip): parameter block and
+// workspace layout, validation, and the composed learned step.
+// ===========================================================================
+namespace {
+
+constexpr size_t kLcAlign = 256;
+size_t lc_round(size_t v) { return (v + kLcAlign - 1) / kLcAlign * kLcAlign; }
+
+// Parameter block: masters, Adam m, Adam v (FP32), BF16 W1 [64][16], W2 [64][64], W3 [16][64].
+struct LcParamPlan {
+    size_t off_m, off_v, off_w1b, off_w2b, off_w3b, total;
+};
+LcParamPlan lc_param_plan() {
+    LcParamPlan p;
+    const size_t vec = lc_round(sizeof(float) * LC_NPARAM);
+    p.off_m = vec;
+    p.off_v = 2 * vec;
+    p.off_w1b = 3 * vec;
+    p.off_w2b = p.off_w1b + lc_round(2 * 64 * 16);
+    p.off_w3b = p.off_w2b + lc_round(2 * 64 * 64);
+    p.total = p.off_w3b + lc_round(2 * 16 * 64);
+    return p;
+}
+
+LcParams lc_params(void* base) {
+    const LcParamPlan p = lc_param_plan();
+    char* b = (char*)base;
+    LcParams a;
+    a.theta = (float*)b;
+    a.m = (float*)(b + p.off_m);
+    a.v = (float*)(b + p.off_v);
+    a.w1b = (unsigned short*)(b + p.off_w1b);
+    a.w2b = (unsigned short*)(b + p.off_w2b);
+    a.w3b = (unsigned short*)(b + p.off_w3b);
+    return a;
+}
+
+// Workspace: dF, dG, cell gradients, bad-cell flags, per-wavefront partial
+// gradients, per-block loss partials.
+struct LcWorkPlan {
+    size_t off_dF, off_dG, off_g, off_bad, off_part, off_loss, total;
+    int nparts, nloss;
+};
+
+LcNet lc_net_shape(const claw_lc_desc* d) {
+    LcNet a;
+    memset(&a, 0, sizeof a);
+    a.nx = (int)d->nx;
+    a.ny = (int)d->ny;
+    a.ncell = a.nx * a.ny;
+    a.tpr_x = (a.nx - 1 + 63) / 64;
+    a.tpr_y = (a.nx + 63) / 64;
+    a.ntiles_x = a.ny * a.tpr_x;
+    a.ntiles = a.ntiles_x + (a.ny - 1) * a.tpr_y;
+    a.nm.mu_h = d->mu_h;
+    for (int c = 0; c < 3; ++c) {
+        a.nm.sd[c] = d->sd[c];
+        a.nm.sl[c] = d->sl[c];
+        a.nm.s_out[c] = d->s_out[c];
+    }
+    return a;
+}
+
+LcWorkPlan lc_work_plan(const claw_lc_desc* d) {
+    const LcNet a = lc_net_shape(d);
+    const size_t nx = (size_t)d->nx, ny = (size_t)d->ny;
+    LcWorkPlan w;
+    w.nparts = lc_net_waves(a, 1024);
+    w.nloss = lc_cell_blocks((int64_t)(nx * ny));
+    w.off_dF = 0;
+    w.off_dG = w.off_dF + lc_round(sizeof(float) * 3 * ny * (nx + 1));
+    w.off_g = w.off_dG + lc_round(sizeof(float) * 3 * (ny + 1) * nx);
+    w.off_bad = w.off_g + lc_round(sizeof(float) * 3 * ny * nx);
+    w.off_part = w.off_bad + lc_round(ny * nx);
+    w.off_loss = w.off_part + lc_round(sizeof(float) * (size_t)w.nparts * LC_NPARAM);
+    w.total = w.off_loss + lc_round(sizeof(double) * 4 * (size_t)w.nloss);
+    return w;
+}
+
+claw_status lc_validate(const claw_lc_desc* d) {
+    if (!d) return fail(CLAW_E_INVALID, "learned-correction descriptor is NULL");
+    if (d->nx < 2 || d->ny < 2) return fail(CLAW_E_INVALID, "grid must be at least 2 x 2");
+    if (3 * d->nx * d->ny >= ((int64_t)1 << 31) || d->nx + 1 >= ((int64_t)1 << 31) / 3)
+        return fail(CLAW_E_UNSUPPORTED, "grid too large for 32-bit offsets");
+    if (!(d->sl[0] > 0 && d->sl[1] > 0 && d->sl[2] > 0 && d->sd[0] > 0 && d->sd[1] > 0 && d->sd[2] > 0))
+        return fail(CLAW_E_INVALID, "input scales must be positive");
+    if (!isfinite(d->mu_h) || !isfinite(d->s_out[0]) || !isfinite(d->s_out[1]) || !isfinite(d->s_out[2]))
+        return fail(CLAW_E_INVALID, "non-finite normalisation");
+    return CLAW_OK;
+}
+
+LcNet lc_net(const claw_lc_desc* d, const void* params) {
+    LcNet a = lc_net_shape(d);
+    const LcParams p = lc_params(const_cast<void*>(params));
+    a.theta = p.theta;
+    a.w1b = p.w1b;
+    a.w2b = p.w2b;
+    a.w3b = p.w3b;
+    return a;
+}
+
+LcApply lc_apply_args(const claw_lc_desc* d, const float* dF, const float* dG, void* work, double nux, double nuy,
+                      double tau, double kappa) {
+    const LcWorkPlan w = lc_work_plan(d);
+    LcApply a;
+    memset(&a, 0, sizeof a);
+    a.dF = dF;
+    a.dG = dG;
+    a.bad = (unsigned char*)work + w.off_bad;
+    a.nx = (int)d->nx;
+    a.ny = (int)d->ny;
+    a.ncell = a.nx * a.ny;
+    a.nux = (float)nux;
+    a.nuy = (float)nuy;
+    a.tau = (float)tau;
+    a.kappa = (float)kappa;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+claw_status claw_lc_sizes(const claw_lc_desc* d, size_t* param_bytes, size_t* work_bytes) {
+    if (param_bytes) *param_bytes = lc_param_plan().total;
+    if (work_bytes) {
+        claw_status st = lc_validate(d);
+        if (st) return st;
+        *work_bytes = lc_work_plan(d).total;
+    }
+    return CLAW_OK;
+}
+
+claw_status claw_lc_init(void* params, void* stream) {
+    if (!params) return fail(CLAW_E_INVALID, "params is NULL");
+    HIP_TRY(launch_lc_init(lc_params(params), (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_forward(const claw_lc_desc* d, const void* params, const float* q, float* dF, float* dG,
+                            void* stream) {
+    claw_status st = lc_validate(d);
+    if (st) return st;
+    if (!params || !q || !dF || !dG) return fail(CLAW_E_INVALID, "NULL buffer");
+    LcNet a = lc_net(d, params);
+    a.q = q;
+    a.dF = dF;
+    a.dG = dG;
+    HIP_TRY(launch_lc_forward(a, (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_loss_grad(const claw_lc_desc* d, const void* params, const float* q, const float* target,
+                              const float* plain, double nux, double nuy, const double* w, void* work,
+                              float* grad, double* loss, void* stream) {
+    claw_status st = lc_validate(d);
+    if (st) return st;
+    if (!params || !q || !target || !plain || !w || !work || !grad) return fail(CLAW_E_INVALID, "NULL buffer");
+    if (!(nux > 0) || !(nuy > 0)) return fail(CLAW_E_INVALID, "nu must be positive");
+    const hipStream_t s = (hipStream_t)stream;
+    const LcWorkPlan wp = lc_work_plan(d);
+    char* ws = (char*)work;
+    float* dF = (float*)(ws + wp.off_dF);
+    float* dG = (float*)(ws + wp.off_dG);
+    float* g = (float*)(ws + wp.off_g);
+    LcNet a = lc_net(d, params);
+    a.q = q;
+    a.dF = dF;
+    a.dG = dG;
+    HIP_TRY(launch_lc_forward(a, s));
+    LcCell c;
+    memset(&c, 0, sizeof c);
+    c.dF = dF;
+    c.dG = dG;
+    c.target = target;
+    c.plain = plain;
+    c.g = g;
+    c.loss_part = (double*)(ws + wp.off_loss);
+    c.nx = a.nx;
+    c.ny = a.ny;
+    c.ncell = a.ncell;
+    c.nux = (float)nux;
+    c.nuy = (float)nuy;
+    const double n3 = 3.0 * (double)a.ncell;
+    for (int f = 0; f < 3; ++f) {
+        c.w[f] = (float)w[f];
+        c.gscale[f] = (float)(2.0 * w[f] / n3);
+    }
+    HIP_TRY(launch_lc_cellgrad(c, s));
+    a.g = g;
+    a.nux = (float)nux;
+    a.nuy = (float)nuy;
+    a.partial = (float*)(ws + wp.off_part);
+    HIP_TRY(launch_lc_backward(a, s));
+    HIP_TRY(launch_lc_reduce(a.partial, wp.nparts, grad, c.loss_part, wp.nloss, 1.0 / n3, loss, s));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_adam(void* params, const float* grad, int64_t step, double lr, double beta1, double beta2,
+                         double eps, void* stream) {
+    if (!params || !grad) return fail(CLAW_E_INVALID, "NULL buffer");
+    if (step < 1) return fail(CLAW_E_INVALID, "Adam steps count from 1");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0))
+        return fail(CLAW_E_INVALID, "bad Adam hyperparameters");
+    const double c1 = 1.0 / (1.0 - pow(beta1, (double)step));
+    const double c2 = 1.0 / (1.0 - pow(beta2, (double)step));
+    HIP_TRY(launch_lc_adam(lc_params(params), grad, (float)lr, (float)beta1, (float)beta2, (float)eps, (float)c1,
+                           (float)c2, (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_apply(const claw_lc_desc* d, const float* qn, const float* plain, const float* dF,
+                          const float* dG, double nux, double nuy, double tau, double kappa, float* out,
+                          uint8_t* keep_x, uint8_t* keep_y, void* work, void* stream) {
+    claw_status st = lc_validate(d);
+    if (st) return st;
+    if (!qn || !plain || !dF || !dG || !out || !work) return fail(CLAW_E_INVALID, "NULL buffer");
+    if (out != plain) {
+        const size_t bytes = sizeof(float) * 3 * (size_t)d->nx * (size_t)d->ny;
+        const char* o = (const char*)out;
+        const char* p = (const char*)plain;
+        const char* qq = (const char*)qn;
+        if ((o < p + bytes && p < o + bytes) || (o < qq + bytes && qq < o + bytes))
+            return fail(CLAW_E_INVALID, "out may alias plain only exactly");
+    }
+    LcApply a = lc_apply_args(d, dF, dG, work, nux, nuy, tau, kappa);
+    a.qn = qn;
+    a.plain = plain;
+    a.out = out;
+    a.keep_x = keep_x;
+    a.keep_y = keep_y;
+    HIP_TRY(launch_lc_apply(a, (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_coarsen(int64_t nx, int64_t ny, const float* fine, float* coarse, void* stream) {
+    if (nx < 1 || ny < 1 || 12 * nx * ny >= ((int64_t)1 << 31)) return fail(CLAW_E_INVALID, "bad coarse grid");
+    if (!fine || !coarse) return fail(CLAW_E_INVALID, "NULL buffer");
+    HIP_TRY(launch_lc_coarsen(fine, coarse, (int)nx, (int)ny, (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* params, int64_t nsteps, double dt,
+                            double tau, double kappa, void* work) {
+    if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
+    claw_status st = lc_validate(d);
+    if (st) return st;
+    if (!params || !work) return fail(CLAW_E_INVALID, "NULL buffer");
+    if (!h->fp32 || h->d.riemann != CLAW_RP_SHALLOW_WATER || h->d.ndim != 2)
+        return fail(CLAW_E_UNSUPPORTED, "the learned correction runs on FP32 2D shallow water");
+    if (h->d.n[0] != d->nx || h->d.n[1] != d->ny) return fail(CLAW_E_INVALID, "grid differs from the solver's");
+    for (int k = 0; k < 2; ++k)
+        if (h->d.bc_lo[k] != CLAW_BC_WALL || h->d.bc_hi[k] != CLAW_BC_WALL)
+            return fail(CLAW_E_UNSUPPORTED, "the learned correction assumes walls on all sides");
+    if (nsteps < 0 || !(dt > 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "bad step count or dt");
+    const LcWorkPlan wp = lc_work_plan(d);
+    char* ws = (char*)work;
+    LcNet a = lc_net(d, params);
+    a.dF = (float*)(ws + wp.off_dF);
+    a.dG = (float*)(ws + wp.off_dG);
+    a.buf0 = (float*)h->buf[0];
+    a.buf1 = (float*)h->buf[1];
+    a.buf2 = (float*)h->buf[2];
+    a.qsel = 1;  // Q^n = result buffer - 2 (mod 3) of a 2D step
+    LcApply ap = lc_apply_args(d, a.dF, a.dG, work, dt / h->dx[0], dt / h->dx[1], tau, kappa);
+    ap.buf0 = a.buf0;
+    ap.buf1 = a.buf1;
+    ap.buf2 = a.buf2;
+    ap.qsel = 1;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        st = commit(h);
+        if (st) return st;
+        HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, result_offset(2), h->stream));
+        st = enqueue_trial(h, h->stream, nullptr);
+        if (!st) st = commit(h);
+        if (st) return st;
+        a.ctrl = h->ctrl;
+        a.cq = committed(h);
+        ap.ctrl = h->ctrl;
+        ap.cq = committed(h);
+        HIP_TRY(launch_lc_forward(a, h->stream));
+        HIP_TRY(launch_lc_apply(ap, h->stream));
+    }
+    st = sync_state(h);
+    if (st) return st;
+    Ctrl c;
+    st = read_ctrl(h, &c);
+    if (st) return st;
+    return ctrl_status(c.st[committed(h)]);
+}
+
+}  // extern "C"

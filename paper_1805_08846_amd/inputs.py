@@ -152,6 +152,42 @@ def sw_ensemble(count=256, seed=0, nmin=128, nmax=1024, dtype="f32", nsteps=500,
     return out
 
 
+def sw_hump(n=1024, seed=0, dtype="f32", nsteps=500):
+    """One member of the Gaussian-hump family of sw_ensemble at a given side n
+    (training and evaluation runs of the learned coarse correction): A, centre
+    and w drawn from default_rng(seed) in that order, same ranges, walls, g = 1."""
+    rng = np.random.default_rng(seed)
+    amp = rng.uniform(0.1, 0.5)
+    centre = rng.uniform(0.25, 0.75, size=2)
+    width = rng.uniform(0.05, 0.2)
+    prob = _base(2, (n, n), (0, 0), (1, 1), "shallow_water", 3, "wall", grav=1.0,
+                 nsteps=nsteps, dtype=dtype, name="sw_hump", seed=seed)
+    x, y, _ = cell_centers(prob)
+    q = np.zeros((3,) + x.shape)
+    q[0] = 1.0 + amp * np.exp(-((x - centre[0]) ** 2 + (y - centre[1]) ** 2) / width ** 2)
+    return prob, round_to(q, dtype), None
+
+
+def lc_init_params(seed=0, hidden=64, nin=12, nout=3, out_gain=0.1):
+    """Seeded initial parameters of the 12-64-64-3 correction network, flat in
+    the order W1 (64, 12), b1, W2 (64, 64), b2, W3 (3, 64), b3: weights normal
+    with standard deviation sqrt(2 / fan_in) (the last layer scaled by
+    out_gain), biases zero; values rounded to FP32, returned in FP64."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.normal(0.0, math.sqrt(2.0 / nin), size=(hidden, nin))
+    w2 = rng.normal(0.0, math.sqrt(2.0 / hidden), size=(hidden, hidden))
+    w3 = rng.normal(0.0, out_gain * math.sqrt(2.0 / hidden), size=(nout, hidden))
+    theta = np.concatenate([w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden),
+                            w3.ravel(), np.zeros(nout)])
+    return theta.astype(np.float32).astype(np.float64)
+
+
+def lc_norm(mu_h=1.0, sd=(0.01, 0.005, 0.005), sl=(0.2, 0.1, 0.1), s_out=(1e-4, 1e-4, 1e-4)):
+    """Input and output scales of the correction network (a plain dict)."""
+    return {"mu_h": float(mu_h), "sd": tuple(float(v) for v in sd),
+            "sl": tuple(float(v) for v in sl), "s_out": tuple(float(v) for v in s_out)}
+
+
 def problem(name, **kw):
     """(prob, q0, aux) for a named workload; keyword arguments override sizes."""
     return CONFIGS[name](**kw)

@@ -37,20 +37,22 @@ def test_library_exports_every_declared_function(claw):
     assert sorted(claw.EXPORTED) == declared
 
 
-def test_descriptor_layout_matches_header(claw, tmp_path):
+@pytest.mark.parametrize("struct", ["claw_desc", "claw_lc_desc"])
+def test_descriptor_layout_matches_header(claw, tmp_path, struct):
+    cls = getattr(claw, struct)
     src = tmp_path / "layout.c"
-    fields = [f for f, _ in claw.claw_desc._fields_]
-    body = "\n".join(f'printf("{f} %zu\\n", offsetof(claw_desc, {f}));' for f in fields)
+    fields = [f for f, _ in cls._fields_]
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof({struct}, {f}));' for f in fields)
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "claw.h"\nint main(void){\n'
-                   + body + '\nprintf("sizeof %zu\\n", sizeof(claw_desc));\nreturn 0;}\n')
+                   + body + f'\nprintf("sizeof %zu\\n", sizeof({struct}));\nreturn 0;}}\n')
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
     got = dict(line.split() for line in out.strip().splitlines())
     for f in fields:
-        assert int(got[f]) == getattr(claw.claw_desc, f).offset, f
-    assert int(got["sizeof"]) == ctypes.sizeof(claw.claw_desc)
+        assert int(got[f]) == getattr(cls, f).offset, f
+    assert int(got["sizeof"]) == ctypes.sizeof(cls)
 
 
 def _sw_desc(claw, n=64):
@@ -121,3 +123,43 @@ def test_null_handle_calls(claw):
 def test_status_strings(claw):
     for s in range(7):
         assert claw.claw_status_string(s)
+
+
+def _lc_desc(claw, nx=64, ny=48):
+    from paper_1805_08846_amd import inputs
+    return claw.lc_desc(nx, ny, inputs.lc_norm())
+
+
+def test_learned_sizes_and_validation(claw):
+    d = _lc_desc(claw)
+    pb, wb = claw.claw_lc_sizes(d)
+    assert pb >= 3 * 4 * claw.CLAW_LC_NPARAM + 2 * (64 * 16 + 64 * 64 + 16 * 64)
+    # dF, dG, cell gradients, flags and at least one partial gradient
+    assert wb >= 4 * 3 * (48 * 65 + 49 * 64 + 48 * 64) + 48 * 64 + 4 * claw.CLAW_LC_NPARAM
+    for field, value in [("nx", 1), ("ny", 0), ("nx", 1 << 40)]:
+        bad = _lc_desc(claw)
+        setattr(bad, field, value)
+        with pytest.raises(claw.ClawError):
+            claw.claw_lc_sizes(bad)
+    bad = _lc_desc(claw)
+    bad.sd[1] = 0.0
+    with pytest.raises(claw.ClawError):
+        claw.claw_lc_sizes(bad)
+
+
+def test_learned_calls_reject_null_buffers_before_touching_the_gpu(claw):
+    d = _lc_desc(claw)
+    L = claw._lib
+    assert L.claw_lc_init(None, None) == claw.CLAW_E_INVALID
+    assert L.claw_lc_forward(ctypes.byref(d), None, None, None, None, None) == claw.CLAW_E_INVALID
+    w = (ctypes.c_double * 3)(1, 1, 1)
+    assert L.claw_lc_loss_grad(ctypes.byref(d), None, None, None, None, 0.1, 0.1, w, None, None, None,
+                               None) == claw.CLAW_E_INVALID
+    assert L.claw_lc_adam(None, None, 1, 1e-3, 0.9, 0.999, 1e-8, None) == claw.CLAW_E_INVALID
+    fake = ctypes.c_void_p(4096)  # never dereferenced: the step count is checked first
+    assert L.claw_lc_adam(fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None) == claw.CLAW_E_INVALID
+    assert "count from 1" in claw.claw_last_error()
+    assert L.claw_lc_apply(ctypes.byref(d), None, None, None, None, 0.1, 0.1, 0.5, 0.01, None, None, None,
+                           None, None) == claw.CLAW_E_INVALID
+    assert L.claw_lc_coarsen(0, 4, fake, fake, None) == claw.CLAW_E_INVALID
+    assert L.claw_lc_advance(None, ctypes.byref(d), None, 1, 0.1, 0.5, 0.01, None) == claw.CLAW_E_INVALID
