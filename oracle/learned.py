@@ -18,9 +18,12 @@ is this project's extension of the method; the paper has no such part, so
 every definition here is the project's own and the pins are finite
 differences, invariants and special cases (tests/test_oracle_learned.py).
 
-Network.  12 -> 64 -> 64 -> 3 with ReLU, parameters
+Networks.  One per sweep direction (x faces, y faces): the split step
+sweeps x then y, so the two directions carry different errors and share no
+weights.  Each is 12 -> 64 -> 64 -> 3 with ReLU, parameters
     W1 (64, 12), b1 (64), W2 (64, 64), b2 (64), W3 (3, 64), b3 (3)
-flattened in that order (row-major) into a vector of 5187 numbers.
+flattened in that order (row-major) into 5187 numbers; the parameter vector
+is the x-face network followed by the y-face network (10374 numbers).
 
 Interface frame.  An interface along direction d sees its stencil in the
 channels (h, m_n, m_t): depth, momentum along d, momentum across d.  x faces
@@ -30,9 +33,15 @@ around face k-1/2; a cell outside the grid is the mirror image across the
 wall with m_n negated (reflecting walls, the same rule as the ghost cells of
 the plain method).
 
-Features (channel c, stencil values a, b, e, f):
-    x[4c+0] = (b - a) / sd_c,  x[4c+1] = (e - b) / sd_c,  x[4c+2] = (f - e) / sd_c,
-    x[4c+3] = ((b + e) / 2 - mu_c) / sl_c          (mu = (mu_h, 0, 0))
+Features (channel c, stencil values a, b, e, f): the level, slope, curvature
+and third difference of the stencil at the face, each over its own scale,
+    x[4c+0] = ((b + e) / 2 - mu_c) / sl_c          (mu = (mu_h, 0, 0))
+    x[4c+1] = (e - b) / sd1_c
+    x[4c+2] = ((a + f) - (b + e)) / sd2_c
+    x[4c+3] = ((f - a) - 3 (e - b)) / sd3_c
+(an invertible linear map of the four stencil values; separate scales keep
+each at full BF16 relative precision, where raw differences of nearly equal
+values would lose the higher differences to rounding).
 Output: d = s_out * y, per channel.
 
 Rounding points (BF16 operands, FP32-or-better accumulation), emulated when
@@ -49,8 +58,10 @@ and correction p = -nu_x (dF_{i+1/2} - dF_{i-1/2}) - nu_y (dG_{j+1/2} - dG_{j-1/
     L = sum_{c,f} w_f (p_{c,f} - r_{c,f})^2 / (3 N)
 
 Fallback (inference).  A face keeps its correction only if
-    |h_R - h_L| <= tau * min(h_L, h_R)                (no shock across it)
-    nu * |d_comp| <= kappa * max(h_L, h_R)  for all three components
+    |h_R - h_L| <= tau * min(h_L, h_R)       (no shock across it)
+    |d_c| <= kappa * s_out_c for all three components c of the face frame
+                                             (the output within kappa of its
+                                             training scale)
 and, after a first application, neither neighbour's corrected depth is below
 half its plain value or non-positive (one pass).  These decisions are taken
 in FP32 arithmetic on FP32 data, as the device takes them.
@@ -63,11 +74,12 @@ NIN = 12
 NOUT = 3
 SHAPES = (("W1", (H1, NIN)), ("b1", (H1,)), ("W2", (H2, H1)), ("b2", (H2,)),
           ("W3", (NOUT, H2)), ("b3", (NOUT,)))
-NPARAM = sum(int(np.prod(s)) for _, s in SHAPES)  # 5187
+NET = sum(int(np.prod(s)) for _, s in SHAPES)  # 5187 per network
+NPARAM = 2 * NET  # x-face network, then y-face network
 
 
 def unpack(theta):
-    """Flat parameter vector -> dict of arrays (views, FP64)."""
+    """Parameters of one network (NET numbers) -> dict of arrays (views, FP64)."""
     theta = np.asarray(theta, dtype=np.float64)
     out, o = {}, 0
     for name, shape in SHAPES:
@@ -133,13 +145,12 @@ def features(q, axis, norm):
     """Network inputs (L * (n-1), 12) of the interior faces along `axis`."""
     st = stencils(q, axis)
     mu = np.array([norm["mu_h"], 0.0, 0.0])
-    sd = np.asarray(norm["sd"], dtype=np.float64)
-    sl = np.asarray(norm["sl"], dtype=np.float64)
+    sl, s1, s2, s3 = (np.asarray(norm[k], dtype=np.float64) for k in ("sl", "sd1", "sd2", "sd3"))
     a, b, e, f = (st[..., s] for s in range(4))
     cols = []
     for c in range(3):
-        cols += [(b[c] - a[c]) / sd[c], (e[c] - b[c]) / sd[c], (f[c] - e[c]) / sd[c],
-                 ((b[c] + e[c]) / 2 - mu[c]) / sl[c]]
+        cols += [((b[c] + e[c]) * 0.5 - mu[c]) / sl[c], (e[c] - b[c]) / s1[c],
+                 ((a[c] + f[c]) - (b[c] + e[c])) / s2[c], ((f[c] - a[c]) - 3 * (e[c] - b[c])) / s3[c]]
     return np.stack([x.ravel() for x in cols], axis=1)
 
 
@@ -147,7 +158,8 @@ def features(q, axis, norm):
 # Network
 # ---------------------------------------------------------------------------
 def forward(theta, x, bf=True):
-    """Forward pass on inputs x (N, 12).  Returns a dict of every intermediate."""
+    """Forward pass of one network (NET parameters) on inputs x (N, 12).
+    Returns a dict of every intermediate."""
     p = unpack(theta)
     xb = _r(x, bf)
     W1, W2, W3 = _r(p["W1"], bf), _r(p["W2"], bf), _r(p["W3"], bf)
@@ -160,8 +172,8 @@ def forward(theta, x, bf=True):
 
 
 def backward(fw, dy, bf=True):
-    """Gradients of sum(dy * y) with respect to the parameters, given the
-    forward record `fw`; flat vector in the parameter order."""
+    """Gradients of sum(dy * y) with respect to one network's parameters,
+    given its forward record `fw`; flat vector in the parameter order."""
     dyr = _r(dy, bf)
     dh2 = dyr @ fw["W3"]
     dz2 = dh2 * (fw["h2"] > 0)
@@ -184,8 +196,9 @@ def face_corrections(theta, norm, q, bf=True):
     s_out = np.asarray(norm["s_out"], dtype=np.float64)
     dF = np.zeros((3, ny, nx + 1))
     dG = np.zeros((3, ny + 1, nx))
-    yx = forward(theta, features(q, 0, norm), bf)["y"] * s_out  # (ny*(nx-1), 3) frame (h, hu, hv)
-    yy = forward(theta, features(q, 1, norm), bf)["y"] * s_out  # (nx*(ny-1), 3) frame (h, hv, hu)
+    theta = np.asarray(theta, dtype=np.float64)
+    yx = forward(theta[:NET], features(q, 0, norm), bf)["y"] * s_out  # (ny*(nx-1), 3) frame (h, hu, hv)
+    yy = forward(theta[NET:], features(q, 1, norm), bf)["y"] * s_out  # (nx*(ny-1), 3) frame (h, hv, hu)
     yx = yx.reshape(ny, nx - 1, 3)
     yy = yy.reshape(nx, ny - 1, 3)
     dF[0, :, 1:nx] = yx[..., 0]
@@ -215,7 +228,7 @@ def loss_grad(theta, norm, q, target, plain, nux, nuy, w, bf=True):
     """(loss, flat gradient) of `loss` by the chain rule written out:
     cell gradient g = 2 w (p - r) / (3N); face gradient dL/dF_{k-1/2} =
     nu (g_k - g_{k-1}); output gradient dy = s_out * (face gradient in the
-    face frame); then the network's backward pass, x faces and y faces summed."""
+    face frame); then each network's backward pass over its faces."""
     _, ny, nx = q.shape
     s_out = np.asarray(norm["s_out"], dtype=np.float64)
     dF, dG = face_corrections(theta, norm, q, bf)
@@ -230,9 +243,10 @@ def loss_grad(theta, norm, q, target, plain, nux, nuy, w, bf=True):
     gGy = nuy * (g[:, 1:, :] - g[:, :-1, :])           # (3, ny-1, nx)
     dyx = np.stack([gFx[0], gFx[1], gFx[2]], axis=-1).reshape(-1, 3) * s_out
     dyy = np.stack([gGy[0].T, gGy[2].T, gGy[1].T], axis=-1).reshape(-1, 3) * s_out
-    grad = backward(forward(theta, features(q, 0, norm), bf), dyx, bf)
-    grad = grad + backward(forward(theta, features(q, 1, norm), bf), dyy, bf)
-    return L, grad
+    theta = np.asarray(theta, dtype=np.float64)
+    gx = backward(forward(theta[:NET], features(q, 0, norm), bf), dyx, bf)
+    gy = backward(forward(theta[NET:], features(q, 1, norm), bf), dyy, bf)
+    return L, np.concatenate([gx, gy])
 
 
 def adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -247,10 +261,11 @@ def adam(theta, m, v, grad, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 # ---------------------------------------------------------------------------
 # Inference: fallback and application
 # ---------------------------------------------------------------------------
-def apply(qn, plain, dF, dG, nux, nuy, tau, kappa):
+def apply(qn, plain, dF, dG, nux, nuy, tau, kappa, s_out):
     """Corrected coarse state from Q^n (qn), the plain step S(Q^n) (plain) and
-    face corrections dF, dG, with the fallback rules of the module docstring.
-    FP32 arithmetic throughout, as on the device.  Returns (q_out, keepF, keepG)."""
+    face corrections dF, dG (state component order), with the fallback rules
+    of the module docstring.  FP32 arithmetic throughout, as on the device.
+    Returns (q_out, keepF, keepG)."""
     f32 = np.float32
     qn = np.asarray(qn, dtype=f32)
     plain = np.asarray(plain, dtype=f32)
@@ -261,17 +276,20 @@ def apply(qn, plain, dF, dG, nux, nuy, tau, kappa):
     h = qn[0]
     keepF = np.zeros((ny, nx + 1), dtype=bool)
     keepG = np.zeros((ny + 1, nx), dtype=bool)
+    so = [f32(v) for v in s_out]
+    # bound per state component: x faces (h, hu, hv) = frame (h, m_n, m_t);
+    # y faces (h, hu, hv) = frame (h, m_t, m_n)
+    bx = [kappa * so[0], kappa * so[1], kappa * so[2]]
+    by = [kappa * so[0], kappa * so[2], kappa * so[1]]
     hl, hr = h[:, :-1], h[:, 1:]
     ok = np.abs(hr - hl) <= tau * np.minimum(hl, hr)
-    bound = kappa * np.maximum(hl, hr)
     for c in range(3):
-        ok &= nux * np.abs(dF[c, :, 1:nx]) <= bound
+        ok &= np.abs(dF[c, :, 1:nx]) <= bx[c]
     keepF[:, 1:nx] = ok
     hb, ht = h[:-1, :], h[1:, :]
     ok = np.abs(ht - hb) <= tau * np.minimum(hb, ht)
-    bound = kappa * np.maximum(hb, ht)
     for c in range(3):
-        ok &= nuy * np.abs(dG[c, 1:ny, :]) <= bound
+        ok &= np.abs(dG[c, 1:ny, :]) <= by[c]
     keepG[1:ny, :] = ok
 
     def corrected(kF, kG):

@@ -19,7 +19,8 @@ def _state(ny=10, nx=12, seed=3):
 
 
 def _norm():
-    return inputs.lc_norm(mu_h=1.1, sd=(0.1, 0.05, 0.05), sl=(0.2, 0.1, 0.1), s_out=(0.01, 0.02, 0.02))
+    return inputs.lc_norm(mu_h=1.1, sl=(0.2, 0.1, 0.1), sd1=(0.1, 0.05, 0.05), sd2=(0.1, 0.05, 0.05),
+                          sd3=(0.2, 0.1, 0.1), s_out=(0.01, 0.02, 0.02))
 
 
 def test_bf16_rounding_matches_torch():
@@ -38,10 +39,12 @@ def test_bf16_rounding_matches_torch():
 
 def test_param_layout():
     th = inputs.lc_init_params(seed=1)
-    assert th.size == L.NPARAM == 5187
-    p = L.unpack(th)
-    assert p["W1"].shape == (64, 12) and p["W3"].shape == (3, 64)
-    assert np.array_equal(L.pack(p), th)
+    assert L.NET == 5187 and th.size == L.NPARAM == 2 * L.NET
+    for net in (th[:L.NET], th[L.NET:]):
+        p = L.unpack(net)
+        assert p["W1"].shape == (64, 12) and p["W3"].shape == (3, 64)
+        assert np.array_equal(L.pack(p), net)
+    assert not np.array_equal(th[:L.NET], th[L.NET:])  # two networks, drawn one after the other
 
 
 def test_stencil_by_hand():
@@ -62,14 +65,24 @@ def test_stencil_by_hand():
     assert np.array_equal(sty, st)
 
 
-def test_features_on_a_ramp():
-    nx = 8
+@pytest.mark.parametrize("kind", ["linear", "quadratic", "cubic"])
+def test_features_reproduce_polynomials(kind):
+    # depth a polynomial of the cell index along x: slope, curvature and third
+    # difference of the stencil are exact (cells k-2 .. k+1 around face k-1/2)
+    nx = 10
+    x = np.arange(nx, dtype=np.float64)
+    coef = {"linear": (0.01, 0, 0), "quadratic": (0, 0.002, 0), "cubic": (0, 0, 0.0003)}[kind]
     q = np.zeros((3, 2, nx))
-    q[0] = 1.0 + 0.01 * np.arange(nx)
-    f = L.features(q, 0, inputs.lc_norm(mu_h=1.0, sd=(0.01, 1, 1), sl=(1, 1, 1)))
-    inner = f.reshape(2, nx - 1, 12)[:, 1:-1]  # faces away from the walls
-    assert np.allclose(inner[..., 0:3], 1.0, atol=1e-12)
-    assert np.allclose(inner[..., 3], 0.01 * (np.arange(2, nx - 1) - 0.5), atol=1e-12)
+    q[0] = 1.0 + coef[0] * x + coef[1] * x ** 2 + coef[2] * x ** 3
+    f = L.features(q, 0, inputs.lc_norm(mu_h=1.0, sl=(1, 1, 1), sd1=(1, 1, 1), sd2=(1, 1, 1), sd3=(1, 1, 1)))
+    inner = f.reshape(2, nx - 1, 12)[:, 1:-1]  # faces k = 2 .. nx-2, away from the walls
+    k = np.arange(2, nx - 1, dtype=np.float64)
+    level = coef[0] * (k - 0.5) + coef[1] * ((k - 1) ** 2 + k ** 2) / 2 + coef[2] * ((k - 1) ** 3 + k ** 3) / 2
+    slope = coef[0] + coef[1] * (2 * k - 1) + coef[2] * (3 * k * k - 3 * k + 1)
+    assert np.allclose(inner[..., 0], level, atol=1e-12)
+    assert np.allclose(inner[..., 1], slope, atol=1e-12)
+    assert np.allclose(inner[..., 2], 4 * coef[1] + coef[2] * (12 * k - 6), atol=1e-12)
+    assert np.allclose(inner[..., 3], 6 * coef[2], atol=1e-12)
     assert np.allclose(inner[..., 4:], 0.0)
 
 
@@ -83,9 +96,10 @@ def test_loss_gradient_finite_differences(seed):
     args = (_norm(), q, target, plain, 0.3, 0.25, (1.0, 2.0, 3.0))
     loss, g = L.loss_grad(th, *args, bf=False)
     assert loss == pytest.approx(L.loss(th, *args, bf=False), rel=1e-14)
-    idx = np.concatenate([rng.choice(768, 12, replace=False), 768 + rng.choice(64, 4, replace=False),
-                          832 + rng.choice(4096, 16, replace=False), 4928 + rng.choice(64, 4, replace=False),
-                          4992 + rng.choice(192, 8, replace=False), [5184, 5185, 5186]])
+    one = [rng.choice(768, 6, replace=False), 768 + rng.choice(64, 3, replace=False),
+           832 + rng.choice(4096, 8, replace=False), 4928 + rng.choice(64, 3, replace=False),
+           4992 + rng.choice(192, 5, replace=False), [5184, 5185, 5186]]
+    idx = np.concatenate(one + [L.NET + np.asarray(i) for i in one])  # both networks
     for i in idx:
         eps = 1e-6 * max(1.0, abs(th[i]))
         tp, tm = th.copy(), th.copy()
@@ -125,13 +139,13 @@ def test_zero_network_and_huge_corrections_give_plain():
     plain = (q + 0.01 * rng.normal(size=q.shape)).astype(np.float32)
     dF, dG = L.face_corrections(np.zeros(L.NPARAM), _norm(), q)
     assert not dF.any() and not dG.any()
-    out, _, _ = L.apply(q, plain, dF, dG, 0.3, 0.3, 0.5, 0.01)
+    out, _, _ = L.apply(q, plain, dF, dG, 0.3, 0.3, 0.5, 0.01, _norm()["s_out"])
     assert np.array_equal(out, plain)
     big = np.full_like(dF, 1e30)
     big[:, :, 0] = big[:, :, -1] = 0
     bigG = np.full_like(dG, -1e30)
     bigG[:, 0, :] = bigG[:, -1, :] = 0
-    out, kF, kG = L.apply(q, plain, big, bigG, 0.3, 0.3, 0.5, 0.01)
+    out, kF, kG = L.apply(q, plain, big, bigG, 0.3, 0.3, 0.5, 0.01, _norm()["s_out"])
     assert not kF.any() and not kG.any()
     assert np.array_equal(out, plain)
 
@@ -145,7 +159,7 @@ def test_apply_conserves_and_falls_back():
     dG = (1e-3 * rng.normal(size=(3, 17, 16))).astype(np.float32)
     dF[:, :, 0] = dF[:, :, -1] = 0
     dG[:, 0, :] = dG[:, -1, :] = 0
-    out, kF, kG = L.apply(q, plain, dF, dG, 0.3, 0.3, 0.5, 0.01)
+    out, kF, kG = L.apply(q, plain, dF, dG, 0.3, 0.3, 0.5, 1.0, _norm()["s_out"])
     assert not kF[5, 5] and not kF[5, 6] and not kG[5, 5] and not kG[6, 5]
     assert kF[:, 1:16].mean() > 0.8
     mass = np.sum(out[0].astype(np.float64)) - np.sum(plain[0].astype(np.float64))
@@ -153,21 +167,35 @@ def test_apply_conserves_and_falls_back():
     # a cell whose corrected depth would drop below half its plain depth
     dF2 = np.zeros_like(dF)
     dF2[0, 8, 8] = -0.9 / 0.3  # face 8 takes 0.9 of depth out of cell 8 and gives it to cell 7
-    out2, kF2, _ = L.apply(q, plain, dF2, np.zeros_like(dG), 0.3, 0.3, 0.5, 10.0)
+    out2, kF2, _ = L.apply(q, plain, dF2, np.zeros_like(dG), 0.3, 0.3, 0.5, 1000.0, _norm()["s_out"])
     assert not kF2[8, 8]
     assert np.array_equal(out2, plain)
+    # the magnitude test counts in output scales, per frame channel: a y face's
+    # hu component is its tangential channel
+    so = _norm()["s_out"]  # (h, m_n, m_t) = (0.01, 0.02, 0.02)
+    dG3 = np.zeros_like(dG)
+    dG3[1, 8, 3] = 1.5 * so[2]
+    dG3[2, 8, 4] = 0.5 * so[1]
+    _, _, kG3 = L.apply(q, plain, np.zeros_like(dF), dG3, 0.3, 0.3, 10.0, 1.0, (0.01, 0.02, 0.015))
+    assert not kG3[8, 3] and kG3[8, 4]
 
 
 def test_transpose_symmetry():
-    rng = np.random.default_rng(7)
-    q = _state(ny=9, nx=9, seed=7)
-    qt = np.transpose(q[[0, 2, 1]], (0, 2, 1))  # swap x <-> y
+    # swapping x <-> y (and hu <-> hv) in the state swaps the roles of the
+    # two networks: the x-face network of the swapped state sees what the
+    # y-face network of the original would see
+    q = _state(ny=9, nx=11, seed=7)
+    qt = np.transpose(q[[0, 2, 1]], (0, 2, 1))
     th = inputs.lc_init_params(seed=7, out_gain=1.0)
-    dF, dG = L.face_corrections(th, _norm(), q)
+    swapped = np.concatenate([th[L.NET:], th[:L.NET]])
+    dF, dG = L.face_corrections(swapped, _norm(), q)
     dFt, dGt = L.face_corrections(th, _norm(), qt)
     assert np.array_equal(dGt[[0, 2, 1]], np.transpose(dF, (0, 2, 1)))
     assert np.array_equal(dFt[[0, 2, 1]], np.transpose(dG, (0, 2, 1)))
-    del rng
+    # and the x faces use only the first network
+    dF2, dG2 = L.face_corrections(np.concatenate([th[:L.NET], np.zeros(L.NET)]), _norm(), q)
+    dF3, _ = L.face_corrections(th, _norm(), q)
+    assert np.array_equal(dF2, dF3) and not dG2.any()
 
 
 def test_adam_first_step_closed_form():
