@@ -206,24 +206,29 @@ claw_status claw_batch_destroy(claw_batch* b);
  * conservative update, section 3, equation LW-update):
  *   Q^{n+1} = S(Q^n) - nu_x (dF_{i+1/2} - dF_{i-1/2}) - nu_y (dG_{j+1/2} - dG_{j-1/2}),
  * nu = dt/dx.  Wall faces carry no correction, so every field's sum changes
- * by rounding only.  The network (12 -> 64 -> 64 -> 3, ReLU) runs on BF16
- * matrix cores with FP32 accumulation; its parameters are FP32 masters with
- * BF16 copies of the weights.  Grids are FP32 (3, ny, nx) states (h, hu, hv)
+ * by rounding only.  Two networks (12 -> 64 -> 64 -> 3, ReLU), one for the
+ * faces of each sweep direction (the split step sweeps x then y, so the two
+ * directions carry different errors), run on BF16 matrix cores with FP32
+ * accumulation; their parameters are FP32 masters with BF16 copies of the
+ * weights.  Grids are FP32 (3, ny, nx) states (h, hu, hv)
  * with reflecting walls on all four sides.
  *
  * Face frame: faces along x see (h, hu, hv), faces along y (h, hv, hu) =
  * (depth, normal momentum, tangential momentum); stencil cells k-2 .. k+1
  * of face k-1/2, mirrored across a wall with the normal momentum negated.
- * Inputs per channel c with stencil values a, b, e, f:
- *   (b - a)/sd[c], (e - b)/sd[c], (f - e)/sd[c], ((b + e)/2 - mu_c)/sl[c]
+ * Inputs per channel c with stencil values a, b, e, f (level, slope,
+ * curvature, third difference):
+ *   ((b + e)/2 - mu_c)/sl[c], (e - b)/sd1[c], ((a + f) - (b + e))/sd2[c],
+ *   ((f - a) - 3 (e - b))/sd3[c]
  * with mu = (mu_h, 0, 0); the outputs are scaled by s_out[c].
  * ------------------------------------------------------------------------ */
-#define CLAW_LC_NPARAM 5187 /* W1 (64,12), b1 (64), W2 (64,64), b2 (64), W3 (3,64), b3 (3) */
+#define CLAW_LC_NET 5187 /* per network: W1 (64,12), b1 (64), W2 (64,64), b2 (64), W3 (3,64), b3 (3) */
+#define CLAW_LC_NPARAM (2 * CLAW_LC_NET) /* x-face network, then y-face network */
 
 typedef struct {
     int64_t nx, ny; /* coarse grid, both >= 2, 3 nx ny < 2^31 */
     float mu_h;     /* input normalisation */
-    float sd[3], sl[3];
+    float sl[3], sd1[3], sd2[3], sd3[3];
     float s_out[3]; /* output scale per frame channel */
 } claw_lc_desc;
 
@@ -261,10 +266,10 @@ claw_status claw_lc_adam(void* params, const float* grad, int64_t step, double l
 
 /* Fallback and application: out = plain - flux difference of the kept
  * corrections.  A face keeps its correction when |h_R - h_L| <= tau min(h_L,
- * h_R) (no shock across it) and nu |d_c| <= kappa max(h_L, h_R) for all three
- * components (h from qn); then faces next to a cell whose corrected depth is
- * below half its plain depth, or not positive, are dropped (one pass).  FP32
- * decisions.  out may alias plain.  keep_x (ny, nx+1) and keep_y (ny+1, nx),
+ * h_R) (no shock across it, h from qn) and |d_c| <= kappa s_out[c] for the
+ * three components in the face frame (the output within kappa of its scale);
+ * then faces next to a cell whose corrected depth is below half its plain
+ * depth, or not positive, are dropped (one pass).  FP32 decisions.  out may alias plain.  keep_x (ny, nx+1) and keep_y (ny+1, nx),
  * optional, receive 1 where a face kept its correction.  Enqueued. */
 claw_status claw_lc_apply(const claw_lc_desc* d, const float* qn, const float* plain, const float* dF,
                           const float* dG, double nux, double nuy, double tau, double kappa, float* out,

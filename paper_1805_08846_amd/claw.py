@@ -34,7 +34,8 @@ EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl",
             "claw_lc_apply", "claw_lc_coarsen", "claw_lc_advance",
             "claw_stream_bench", "claw_status_string", "claw_last_error"]
 
-CLAW_LC_NPARAM = 5187
+CLAW_LC_NET = 5187
+CLAW_LC_NPARAM = 2 * CLAW_LC_NET  # x-face network, then y-face network
 
 
 class claw_desc(ctypes.Structure):
@@ -68,8 +69,10 @@ class claw_lc_desc(ctypes.Structure):
         ("nx", ctypes.c_int64),
         ("ny", ctypes.c_int64),
         ("mu_h", ctypes.c_float),
-        ("sd", ctypes.c_float * 3),
         ("sl", ctypes.c_float * 3),
+        ("sd1", ctypes.c_float * 3),
+        ("sd2", ctypes.c_float * 3),
+        ("sd3", ctypes.c_float * 3),
         ("s_out", ctypes.c_float * 3),
     ]
 
@@ -85,6 +88,10 @@ def _load():
         raise ImportError(
             f"{_LIB_PATH} is missing: build the HIP library first "
             "(python -m paper_1805_08846_amd.build); there is no CPU fallback")
+    # torch first: the library must bind to the HIP runtime torch has loaded
+    # (loaded the other way round, the process holds two runtimes and the
+    # library's calls see no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     P = ctypes.POINTER
@@ -201,13 +208,15 @@ def claw_advance(h, nsteps, dt0=0.0):
     return t.value, nrej.value
 
 
-def claw_advance_fixed(h, dts):
+def claw_advance_fixed(h, dts, log=True):
+    """Steps of the given sizes; returns the Courant number of each step, or
+    None with log=False (equal steps then replay a captured graph)."""
     dts = np.ascontiguousarray(dts, dtype=np.float64)
-    cfl = np.zeros(max(dts.size, 1))
+    cfl = np.zeros(max(dts.size, 1)) if log else None
     _check(_lib.claw_advance_fixed(h, dts.size, dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                   cfl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                                   None if cfl is None else cfl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
            "claw_advance_fixed")
-    return cfl[:dts.size]
+    return None if cfl is None else cfl[:dts.size]
 
 
 def claw_advance_timed(h, nsteps):
@@ -328,14 +337,14 @@ class BatchSolver:
 # --------------------------------------------------------------------------
 
 def lc_desc(nx, ny, norm):
-    """claw_lc_desc from a grid and a normalisation dict (mu_h, sd, sl, s_out)."""
+    """claw_lc_desc from a grid and a normalisation dict (mu_h, sl, sd1, sd2, sd3, s_out)."""
     d = claw_lc_desc()
     d.nx, d.ny = int(nx), int(ny)
     d.mu_h = float(norm["mu_h"])
-    for c in range(3):
-        d.sd[c] = float(norm["sd"][c])
-        d.sl[c] = float(norm["sl"][c])
-        d.s_out[c] = float(norm["s_out"][c])
+    for key in ("sl", "sd1", "sd2", "sd3", "s_out"):
+        arr = getattr(d, key)
+        for c in range(3):
+            arr[c] = float(norm[key][c])
     return d
 
 
@@ -507,8 +516,8 @@ class Solver:
     def advance(self, nsteps, dt0=0.0):
         return claw_advance(self.h, nsteps, dt0)
 
-    def advance_fixed(self, dts):
-        return claw_advance_fixed(self.h, dts)
+    def advance_fixed(self, dts, log=True):
+        return claw_advance_fixed(self.h, dts, log)
 
     def advance_timed(self, nsteps):
         return claw_advance_timed(self.h, nsteps)

@@ -41,10 +41,16 @@ hipError_t launch_batch_sweep(const BatchLaunch<R>& L, int sys, int dir, int nbl
 hipError_t launch_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, double dt, int mode,
                              int result_off, long long nsteps, bool fp32, hipStream_t s);
 
-// Learned coarse correction (learned.hip).  Parameters of the 12-64-64-3
-// network, flat: W1 (64, 12), b1, W2 (64, 64), b2, W3 (3, 64), b3.
+// Learned coarse correction (learned.hip).  Two 12-64-64-3 networks, one
+// per sweep direction (x faces, then y faces), each flat: W1 (64, 12), b1,
+// W2 (64, 64), b2, W3 (3, 64), b3.  BF16 copies per network: W1 padded
+// [64][16], W2 [64][64], W3 padded [16][64].
 enum {
-    LC_NPARAM = 5187,
+    LC_NET = 5187,
+    LC_NPARAM = 2 * LC_NET,
+    LC_W1B = 64 * 16,
+    LC_W2B = 64 * 64,
+    LC_W3B = 16 * 64,
     LC_OFF_W1 = 0,
     LC_OFF_B1 = 768,
     LC_OFF_W2 = 832,
@@ -54,11 +60,13 @@ enum {
 };
 struct LcNorm {
     float mu_h;
-    float sd[3], sl[3], s_out[3];
+    float sl[3], sd1[3], sd2[3], sd3[3], s_out[3];
 };
-// Network pass over the interior faces of a (ny, nx) grid.  With ctrl set,
-// the state is rotation buffer (cur + qsel) % 3 of step-state copy cq, and the
-// pass does nothing unless that copy's last trial was accepted.
+// Network pass over the interior faces of a (ny, nx) grid (launch
+// dimension y = sweep direction of the faces and of the network).  With ctrl set,
+// the state is rotation buffer (cur + qsel) % 3 of step-state copy cq (the
+// copy of a trial that ran and is not decided yet), and the pass does nothing
+// if that trial failed, was skipped or flagged a non-physical state.
 struct LcNet {
     const float* q;
     const Ctrl* ctrl;
@@ -67,12 +75,12 @@ struct LcNet {
     int nx, ny, ncell;
     int ntiles_x, tpr_x, tpr_y, ntiles;
     LcNorm nm;
-    const float* theta;
-    const unsigned short *w1b, *w2b, *w3b;  // BF16 copies, padded [64][16], [64][64], [16][64]
+    const float* theta;                     // both networks' FP32 masters
+    const unsigned short *w1b, *w2b, *w3b;  // BF16 copies, two networks each
     float *dF, *dG;
     const float* g;  // training: cell gradients (3, ny, nx)
     float nux, nuy;
-    float* partial;  // training: [waves][LC_NPARAM]
+    float* partial;  // training: [direction][wave][LC_NET]
 };
 struct LcCell {
     const float *dF, *dG, *target, *plain;
@@ -83,24 +91,26 @@ struct LcCell {
     float w[3], gscale[3];
 };
 // Fallback and application; with ctrl set, qn / plain / out are resolved
-// from the rotation buffers (Q^n at (cur + qsel) % 3, plain and out at cur).
+// from the rotation buffers of trial copy cq as above: Q^n at (cur + qsel) % 3,
+// plain and out (in place) at (cur + rsel) % 3.
 struct LcApply {
     const float* qn;
     const float* plain;
     float* out;
     const Ctrl* ctrl;
-    int cq, qsel;
+    int cq, qsel, rsel;
     float *buf0, *buf1, *buf2;
     const float *dF, *dG;
     unsigned char *bad, *keep_x, *keep_y;
     int nx, ny, ncell;
     float nux, nuy, tau, kappa;
+    float s_out[3];  // output scales per frame channel (magnitude test)
 };
 struct LcParams {
     float *theta, *m, *v;
     unsigned short *w1b, *w2b, *w3b;
 };
-int lc_net_waves(const LcNet& a, int cap);
+int lc_net_waves(const LcNet& a, int cap);  // wavefronts per direction
 int lc_cell_blocks(int64_t ncell);
 hipError_t launch_lc_forward(const LcNet& a, hipStream_t s);
 hipError_t launch_lc_backward(const LcNet& a, hipStream_t s);

@@ -12,8 +12,10 @@
 //
 // Interface frame: a face along direction d sees (h, m_n, m_t) = depth,
 // momentum along d, momentum across d; stencil cells k-2 .. k+1 around face
-// k - 1/2, mirrored across a wall with m_n negated.  Features per channel c:
-// (b - a)/sd_c, (e - b)/sd_c, (f - e)/sd_c, ((b + e)/2 - mu_c)/sl_c.
+// k - 1/2, mirrored across a wall with m_n negated.  Features per channel c
+// (level, slope, curvature, third difference, each over its own scale):
+// ((b + e)/2 - mu_c)/sl_c, (e - b)/sd1_c, ((a + f) - (b + e))/sd2_c,
+// ((f - a) - 3 (e - b))/sd3_c, formed in FP64 before the rounding to BF16.
 //
 // Matrix-core layout (v_mfma_f32_16x16x16_bf16, 64 lanes, lane = n + 16 kb):
 //   A[i][k]  lane i + 16 (k/4), element k%4
@@ -115,41 +117,67 @@ struct NetRegs {
     f32x4 B1[4], B2[4], B3;
 };
 
-__device__ __forceinline__ void load_net(const LcNet& a, int lane, NetRegs& R) {
+// Network of sweep direction `axis`.
+struct NetPtr {
+    const float* theta;
+    const unsigned short *w1b, *w2b, *w3b;
+};
+__device__ __forceinline__ NetPtr net_of(const LcNet& a, int axis) {
+    NetPtr n;
+    n.theta = a.theta + axis * LC_NET;
+    n.w1b = a.w1b + axis * LC_W1B;
+    n.w2b = a.w2b + axis * LC_W2B;
+    n.w3b = a.w3b + axis * LC_W3B;
+    return n;
+}
+
+__device__ __forceinline__ void load_net(const NetPtr& N, int lane, NetRegs& R) {
     const int i = lane & 15, kb = lane >> 4;
     for (int t = 0; t < 4; ++t) {
         for (int e = 0; e < 4; ++e) {
-            R.A1[t][e] = (short)a.w1b[(16 * t + i) * 16 + 4 * kb + e];
-            R.B1[t][e] = a.theta[LC_OFF_B1 + 16 * t + 4 * kb + e];
-            R.B2[t][e] = a.theta[LC_OFF_B2 + 16 * t + 4 * kb + e];
-            R.A3[t][e] = (short)a.w3b[i * 64 + 16 * t + 4 * kb + e];
+            R.A1[t][e] = (short)N.w1b[(16 * t + i) * 16 + 4 * kb + e];
+            R.B1[t][e] = N.theta[LC_OFF_B1 + 16 * t + 4 * kb + e];
+            R.B2[t][e] = N.theta[LC_OFF_B2 + 16 * t + 4 * kb + e];
+            R.A3[t][e] = (short)N.w3b[i * 64 + 16 * t + 4 * kb + e];
         }
         for (int s = 0; s < 4; ++s)
-            for (int e = 0; e < 4; ++e) R.A2[t][s][e] = (short)a.w2b[(16 * t + i) * 64 + 16 * s + 4 * kb + e];
+            for (int e = 0; e < 4; ++e) R.A2[t][s][e] = (short)N.w2b[(16 * t + i) * 64 + 16 * s + 4 * kb + e];
     }
     for (int e = 0; e < 4; ++e) {
         const int o = 4 * kb + e;
-        R.B3[e] = o < 3 ? a.theta[LC_OFF_B3 + o] : 0.0f;
+        R.B3[e] = o < 3 ? N.theta[LC_OFF_B3 + o] : 0.0f;
     }
 }
 
+// Face tiles of launch direction blockIdx.y: [first, end) of the tile index.
+__device__ __forceinline__ void axis_tiles(const LcNet& a, int axis, int& first, int& end) {
+    first = axis == 0 ? 0 : a.ntiles_x;
+    end = axis == 0 ? a.ntiles_x : a.ntiles;
+}
+
 // Inputs of 16 faces (group g of the tile) as the B operand: lane n + 16 kb
-// holds the four features of channel kb (none for kb = 3).
+// holds the four features of channel kb (none for kb = 3).  The features are
+// formed in FP64 without contraction (the higher differences cancel; FP32
+// would round them coarsely) and rounded FP64 -> FP32 -> BF16.
 __device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
                                            int pos, int lane) {
     const int kb = lane >> 4;
     bf16x4 x = {0, 0, 0, 0};
     if (kb < 3) {
-        const float v0 = stencil(a, q, ft, pos, kb, 0);
-        const float v1 = stencil(a, q, ft, pos, kb, 1);
-        const float v2 = stencil(a, q, ft, pos, kb, 2);
-        const float v3 = stencil(a, q, ft, pos, kb, 3);
-        const float sd = a.nm.sd[kb], sl = a.nm.sl[kb];
-        const float mu = kb == 0 ? a.nm.mu_h : 0.0f;
-        x[0] = to_bf16((v1 - v0) / sd);
-        x[1] = to_bf16((v2 - v1) / sd);
-        x[2] = to_bf16((v3 - v2) / sd);
-        x[3] = to_bf16(((v1 + v2) * 0.5f - mu) / sl);
+        const double v0 = stencil(a, q, ft, pos, kb, 0);
+        const double v1 = stencil(a, q, ft, pos, kb, 1);
+        const double v2 = stencil(a, q, ft, pos, kb, 2);
+        const double v3 = stencil(a, q, ft, pos, kb, 3);
+        const double mu = kb == 0 ? (double)a.nm.mu_h : 0.0;
+        const double jump = __dsub_rn(v2, v1);
+        const double mid = __dadd_rn(v1, v2);
+        const double lvl = __dsub_rn(__dmul_rn(mid, 0.5), mu);
+        const double curv = __dsub_rn(__dadd_rn(v0, v3), mid);
+        const double third = __dsub_rn(__dsub_rn(v3, v0), __dmul_rn(3.0, jump));
+        x[0] = to_bf16((float)__ddiv_rn(lvl, (double)a.nm.sl[kb]));
+        x[1] = to_bf16((float)__ddiv_rn(jump, (double)a.nm.sd1[kb]));
+        x[2] = to_bf16((float)__ddiv_rn(curv, (double)a.nm.sd2[kb]));
+        x[3] = to_bf16((float)__ddiv_rn(third, (double)a.nm.sd3[kb]));
     }
     return x;
 }
@@ -179,15 +207,22 @@ __device__ __forceinline__ int face_pos(const LcNet& a, const FaceTile& ft, int 
     return valid ? pos : a.nx - 1;
 }
 
+// A trial that ran and is not decided yet, with no failure and no
+// non-physical state flagged by its sweeps (the learned step's kernels run
+// between a fixed-dt trial and its decision, which accepts it).
+__device__ __forceinline__ bool trial_ok(const Ctrl* c, int q) {
+    const StepState& s = c->st[q];
+    return s.pending && !s.done && !s.err && !c->nonphys[q];
+}
+
 __device__ __forceinline__ const float* resolve_state(const LcNet& a, bool& skip) {
     skip = false;
     if (!a.ctrl) return a.q;
-    const StepState& s = a.ctrl->st[a.cq];
-    if (s.err || !s.last_accepted) {
+    if (!trial_ok(a.ctrl, a.cq)) {
         skip = true;
         return a.q;
     }
-    return pick3(a.buf0, a.buf1, a.buf2, (s.cur + a.qsel) % 3);
+    return pick3(a.buf0, a.buf1, a.buf2, (a.ctrl->st[a.cq].cur + a.qsel) % 3);
 }
 
 // Forward pass over every interior face: corrections dF (3, ny, nx+1) and
@@ -198,12 +233,15 @@ __global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
     if (skip) return;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, kb = lane >> 4;
+    const int axis = blockIdx.y;
     NetRegs R;
-    load_net(a, lane, R);
+    load_net(net_of(a, axis), lane, R);
     const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
     const int nwaves = gridDim.x * WAVES;
     const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
-    for (int t = wave; t < a.ntiles; t += nwaves) {
+    int t0, t1;
+    axis_tiles(a, axis, t0, t1);
+    for (int t = t0 + wave; t < t1; t += nwaves) {
         const FaceTile ft = tile_of(a, t);
         for (int g = 0; g < 4; ++g) {
             bool valid;
@@ -277,17 +315,19 @@ __global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
     const float* __restrict__ q = a.q;
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, kb = lane >> 4;
+    const int axis = blockIdx.y;
+    const NetPtr N = net_of(a, axis);
     NetRegs R;
-    load_net(a, lane, R);
+    load_net(N, lane, R);
     // transposed weights for the backward products
     bf16x4 T3[4], T2[4][4];
     for (int t = 0; t < 4; ++t) {
         for (int e = 0; e < 4; ++e) {
             const int o = 4 * kb + e;
-            T3[t][e] = o < 3 ? (short)a.w3b[o * 64 + 16 * t + n] : (short)0;
+            T3[t][e] = o < 3 ? (short)N.w3b[o * 64 + 16 * t + n] : (short)0;
         }
         for (int s = 0; s < 4; ++s)
-            for (int e = 0; e < 4; ++e) T2[t][s][e] = (short)a.w2b[(16 * s + 4 * kb + e) * 64 + 16 * t + n];
+            for (int e = 0; e < 4; ++e) T2[t][s][e] = (short)N.w2b[(16 * s + 4 * kb + e) * 64 + 16 * t + n];
     }
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc1[4], acc2[4][4], acc3[4], sb1[4], sb2[4];
@@ -301,7 +341,9 @@ __global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
     }
     const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
     const int nwaves = gridDim.x * WAVES;
-    for (int t = wave; t < a.ntiles; t += nwaves) {
+    int t0, t1;
+    axis_tiles(a, axis, t0, t1);
+    for (int t = t0 + wave; t < t1; t += nwaves) {
         const FaceTile ft = tile_of(a, t);
         const float nu = ft.axis == 0 ? a.nux : a.nuy;
         for (int grp = 0; grp < 4; ++grp) {
@@ -371,8 +413,8 @@ __global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
             lds_sync();
         }
     }
-    // partial gradients of this wavefront, in the parameter order
-    float* P = a.partial + (size_t)wave * LC_NPARAM;
+    // partial gradients of this wavefront for its direction's network
+    float* P = a.partial + ((size_t)axis * nwaves + wave) * LC_NET;
     for (int tu = 0; tu < 4; ++tu)
         for (int e = 0; e < 4; ++e) {
             const int u = 16 * tu + 4 * kb + e;
@@ -433,8 +475,9 @@ __global__ __launch_bounds__(256) void k_lc_cellgrad(LcCell a) {
     if (tid < 4) a.loss_part[blockIdx.x * 4 + tid] = red[tid][0];
 }
 
-// Sum of the per-wavefront partial gradients (fixed order) into grad, and of
-// the loss partials into loss[0..3] (the first block's spare threads).
+// Sum of the per-wavefront partial gradients (fixed order; nparts
+// wavefronts per direction) into grad, and of the loss partials into
+// loss[0..3] (the first block's spare threads).
 __global__ __launch_bounds__(256) void k_lc_reduce(const float* __restrict__ partial, int nparts, float* grad,
                                                    const double* __restrict__ loss_part, int nloss, double inv3n,
                                                    double* loss) {
@@ -442,8 +485,11 @@ __global__ __launch_bounds__(256) void k_lc_reduce(const float* __restrict__ par
     const int p = blockIdx.x * 64 + (threadIdx.x & 63);
     const int part = threadIdx.x >> 6;
     float s = 0.0f;
-    if (p < LC_NPARAM)
-        for (int w = part; w < nparts; w += 4) s += partial[(size_t)w * LC_NPARAM + p];
+    if (p < LC_NPARAM) {
+        const int axis = p / LC_NET, local = p - axis * LC_NET;
+        const float* base = partial + (size_t)axis * nparts * LC_NET + local;
+        for (int w = part; w < nparts; w += 4) s += base[(size_t)w * LC_NET];
+    }
     red[part][threadIdx.x & 63] = s;
     __syncthreads();
     if (part == 0 && p < LC_NPARAM) grad[p] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
@@ -456,21 +502,22 @@ __global__ __launch_bounds__(256) void k_lc_reduce(const float* __restrict__ par
 }
 
 __device__ __forceinline__ void emit_bf16(LcParams a, int p, float v) {
-    if (p < LC_OFF_B1) {
-        a.w1b[(p / 12) * 16 + p % 12] = (unsigned short)to_bf16(v);
-    } else if (p >= LC_OFF_W2 && p < LC_OFF_B2) {
-        a.w2b[p - LC_OFF_W2] = (unsigned short)to_bf16(v);
-    } else if (p >= LC_OFF_W3 && p < LC_OFF_B3) {
-        const int o = (p - LC_OFF_W3) / 64, k = (p - LC_OFF_W3) % 64;
-        a.w3b[o * 64 + k] = (unsigned short)to_bf16(v);
+    const int axis = p / LC_NET, r = p - axis * LC_NET;
+    if (r < LC_OFF_B1) {
+        a.w1b[axis * LC_W1B + (r / 12) * 16 + r % 12] = (unsigned short)to_bf16(v);
+    } else if (r >= LC_OFF_W2 && r < LC_OFF_B2) {
+        a.w2b[axis * LC_W2B + r - LC_OFF_W2] = (unsigned short)to_bf16(v);
+    } else if (r >= LC_OFF_W3 && r < LC_OFF_B3) {
+        const int o = (r - LC_OFF_W3) / 64, k = (r - LC_OFF_W3) % 64;
+        a.w3b[axis * LC_W3B + o * 64 + k] = (unsigned short)to_bf16(v);
     }
 }
 
 // Zero the moments and the BF16 padding, then emit the BF16 weight copies.
 __global__ void k_lc_init(LcParams a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < 64 * 16) a.w1b[p] = 0;
-    if (p < 16 * 64) a.w3b[p] = 0;
+    if (p < 2 * LC_W1B) a.w1b[p] = 0;
+    if (p < 2 * LC_W3B) a.w3b[p] = 0;
     if (p < LC_NPARAM) {
         a.m[p] = 0.0f;
         a.v[p] = 0.0f;
@@ -516,22 +563,21 @@ __device__ __forceinline__ bool resolve_apply(const LcApply& a, ApplyState& S) {
     S.plain = a.plain;
     S.out = a.out;
     if (!a.ctrl) return true;
-    const StepState& s = a.ctrl->st[a.cq];
-    if (s.err || !s.last_accepted) return false;
-    S.qn = pick3(a.buf0, a.buf1, a.buf2, (s.cur + a.qsel) % 3);
-    S.out = pick3(a.buf0, a.buf1, a.buf2, s.cur);
+    if (!trial_ok(a.ctrl, a.cq)) return false;
+    const int cur = a.ctrl->st[a.cq].cur;
+    S.qn = pick3(a.buf0, a.buf1, a.buf2, (cur + a.qsel) % 3);
+    S.out = pick3(a.buf0, a.buf1, a.buf2, (cur + a.rsel) % 3);
     S.plain = S.out;  // in place: each cell reads only its own plain values
     return true;
 }
 
 // Indicator test of x face k of row j (1 <= k <= nx-1) or y face row k of column i.
+// bound[c]: kappa times the output scale of state component c on this face's axis.
 __device__ __forceinline__ bool face_ok(const LcApply& a, float hl, float hr, const float* __restrict__ d,
-                                        size_t stride, float nu) {
+                                        size_t stride, const float* bound) {
     const float lo = hl < hr ? hl : hr;
-    const float hi = hl > hr ? hl : hr;
     bool ok = fabsf(fsub(hr, hl)) <= fmul(a.tau, lo);
-    const float bound = fmul(a.kappa, hi);
-    for (int c = 0; c < 3; ++c) ok = ok && (fmul(nu, fabsf(d[c * stride])) <= bound);
+    for (int c = 0; c < 3; ++c) ok = ok && (fabsf(d[c * stride]) <= bound[c]);
     return ok;
 }
 
@@ -543,11 +589,14 @@ __device__ __forceinline__ FaceKeep keep_of(const LcApply& a, const float* __res
     const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
     const int nx = a.nx, ny = a.ny;
     const float hc = h[j * nx + i];
+    // x faces: components (h, hu, hv) are frame (h, m_n, m_t); y faces (h, m_t, m_n)
+    const float bx[3] = {fmul(a.kappa, a.s_out[0]), fmul(a.kappa, a.s_out[1]), fmul(a.kappa, a.s_out[2])};
+    const float by[3] = {bx[0], bx[2], bx[1]};
     FaceKeep k;
-    k.l = i > 0 && face_ok(a, h[j * nx + i - 1], hc, a.dF + (size_t)j * (nx + 1) + i, fx, a.nux);
-    k.r = i < nx - 1 && face_ok(a, hc, h[j * nx + i + 1], a.dF + (size_t)j * (nx + 1) + i + 1, fx, a.nux);
-    k.b = j > 0 && face_ok(a, h[(j - 1) * nx + i], hc, a.dG + (size_t)j * nx + i, fy, a.nuy);
-    k.t = j < ny - 1 && face_ok(a, hc, h[(j + 1) * nx + i], a.dG + (size_t)(j + 1) * nx + i, fy, a.nuy);
+    k.l = i > 0 && face_ok(a, h[j * nx + i - 1], hc, a.dF + (size_t)j * (nx + 1) + i, fx, bx);
+    k.r = i < nx - 1 && face_ok(a, hc, h[j * nx + i + 1], a.dF + (size_t)j * (nx + 1) + i + 1, fx, bx);
+    k.b = j > 0 && face_ok(a, h[(j - 1) * nx + i], hc, a.dG + (size_t)j * nx + i, fy, by);
+    k.t = j < ny - 1 && face_ok(a, hc, h[(j + 1) * nx + i], a.dG + (size_t)(j + 1) * nx + i, fy, by);
     return k;
 }
 
@@ -622,24 +671,27 @@ int blocks_for(int64_t n) {
 
 }  // namespace
 
-// Wavefronts of a network launch: one per face tile, at most `cap`, rounded
-// up to whole workgroups (the training pass writes one partial per wavefront).
+// Wavefronts per direction of a network launch: one per face tile of the
+// larger direction, at most `cap`, rounded up to whole workgroups (the
+// training pass writes one partial per wavefront and direction).
 int lc_net_waves(const LcNet& a, int cap) {
-    const int w = a.ntiles < cap ? a.ntiles : cap;
+    const int ny_tiles = a.ntiles - a.ntiles_x;
+    const int most = a.ntiles_x > ny_tiles ? a.ntiles_x : ny_tiles;
+    const int w = most < cap ? most : cap;
     return ((w + WAVES - 1) / WAVES) * WAVES;
 }
 
 hipError_t launch_lc_forward(const LcNet& a, hipStream_t s) {
-    const int w = lc_net_waves(a, 4096);
+    const int w = lc_net_waves(a, 2048);
     if (w <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lc_forward, dim3(w / WAVES), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lc_forward, dim3(w / WAVES, 2), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_lc_backward(const LcNet& a, hipStream_t s) {
-    const int w = lc_net_waves(a, 1024);
+    const int w = lc_net_waves(a, 512);
     if (w <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lc_backward, dim3(w / WAVES), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lc_backward, dim3(w / WAVES, 2), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

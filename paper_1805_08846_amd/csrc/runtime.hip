@@ -120,6 +120,9 @@ struct claw_solver {
     hipGraphExec_t gexec[2];  // captured trial sequences, by starting parity
     hipGraph_t graph[2];
     std::vector<hipEvent_t> events;
+    hipGraphExec_t lc_exec;  // captured learned steps and the arguments they were captured with
+    hipGraph_t lc_graph;
+    unsigned char lc_key[128];
 };
 
 namespace {
@@ -524,6 +527,27 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
     for (int64_t k = 0; k < nsteps; ++k)
         if (!(dts[k] > 0) || !isfinite(dts[k])) return fail(CLAW_E_INVALID, "dts[%lld] not positive", (long long)k);
     claw_status st = CLAW_OK;
+    bool uniform = !cfl_log && nsteps >= kGraphSteps;
+    for (int64_t k = 1; k < nsteps && uniform; ++k) uniform = dts[k] == dts[0];
+    if (uniform) {
+        // one begin, then captured trials: a fixed-dt trial keeps its dt and is
+        // accepted by the next trial's first sweep
+        st = commit(h);
+        if (st) return st;
+        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[0], MODE_FIXED, result_offset(h->d.ndim), h->stream));
+        st = ensure_graph(h);
+        if (st) return st;
+        const int64_t reps = nsteps / kGraphSteps;
+        for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec[h->parity], h->stream));
+        for (int64_t k = reps * kGraphSteps; k < nsteps && st == CLAW_OK; ++k) st = enqueue_trial(h, h->stream, nullptr);
+        if (!st) st = commit(h);
+        if (!st) st = sync_state(h);
+        if (st) return st;
+        Ctrl c;
+        st = read_ctrl(h, &c);
+        if (st) return st;
+        return ctrl_status(c.st[committed(h)]);
+    }
     for (int64_t k = 0; k < nsteps; ++k) {
         st = commit(h);
         if (st) return st;
@@ -637,6 +661,8 @@ claw_status claw_destroy(claw_solver* h) {
         if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
         if (h->graph[p]) (void)hipGraphDestroy(h->graph[p]);
     }
+    if (h->lc_exec) (void)hipGraphExecDestroy(h->lc_exec);
+    if (h->lc_graph) (void)hipGraphDestroy(h->lc_graph);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
@@ -1165,7 +1191,8 @@ namespace {
 constexpr size_t kLcAlign = 256;
 size_t lc_round(size_t v) { return (v + kLcAlign - 1) / kLcAlign * kLcAlign; }
 
-// Parameter block: masters, Adam m, Adam v (FP32), BF16 W1 [64][16], W2 [64][64], W3 [16][64].
+// Parameter block: masters, Adam m, Adam v (FP32, both networks), then the
+// BF16 copies W1 [2][64][16], W2 [2][64][64], W3 [2][16][64].
 struct LcParamPlan {
     size_t off_m, off_v, off_w1b, off_w2b, off_w3b, total;
 };
@@ -1175,9 +1202,9 @@ LcParamPlan lc_param_plan() {
     p.off_m = vec;
     p.off_v = 2 * vec;
     p.off_w1b = 3 * vec;
-    p.off_w2b = p.off_w1b + lc_round(2 * 64 * 16);
-    p.off_w3b = p.off_w2b + lc_round(2 * 64 * 64);
-    p.total = p.off_w3b + lc_round(2 * 16 * 64);
+    p.off_w2b = p.off_w1b + lc_round(2 * 2 * LC_W1B);
+    p.off_w3b = p.off_w2b + lc_round(2 * 2 * LC_W2B);
+    p.total = p.off_w3b + lc_round(2 * 2 * LC_W3B);
     return p;
 }
 
@@ -1213,8 +1240,10 @@ LcNet lc_net_shape(const claw_lc_desc* d) {
     a.ntiles = a.ntiles_x + (a.ny - 1) * a.tpr_y;
     a.nm.mu_h = d->mu_h;
     for (int c = 0; c < 3; ++c) {
-        a.nm.sd[c] = d->sd[c];
         a.nm.sl[c] = d->sl[c];
+        a.nm.sd1[c] = d->sd1[c];
+        a.nm.sd2[c] = d->sd2[c];
+        a.nm.sd3[c] = d->sd3[c];
         a.nm.s_out[c] = d->s_out[c];
     }
     return a;
@@ -1224,14 +1253,14 @@ LcWorkPlan lc_work_plan(const claw_lc_desc* d) {
     const LcNet a = lc_net_shape(d);
     const size_t nx = (size_t)d->nx, ny = (size_t)d->ny;
     LcWorkPlan w;
-    w.nparts = lc_net_waves(a, 1024);
+    w.nparts = lc_net_waves(a, 512);  // per direction
     w.nloss = lc_cell_blocks((int64_t)(nx * ny));
     w.off_dF = 0;
     w.off_dG = w.off_dF + lc_round(sizeof(float) * 3 * ny * (nx + 1));
     w.off_g = w.off_dG + lc_round(sizeof(float) * 3 * (ny + 1) * nx);
     w.off_bad = w.off_g + lc_round(sizeof(float) * 3 * ny * nx);
     w.off_part = w.off_bad + lc_round(ny * nx);
-    w.off_loss = w.off_part + lc_round(sizeof(float) * (size_t)w.nparts * LC_NPARAM);
+    w.off_loss = w.off_part + lc_round(sizeof(float) * 2 * (size_t)w.nparts * LC_NET);
     w.total = w.off_loss + lc_round(sizeof(double) * 4 * (size_t)w.nloss);
     return w;
 }
@@ -1241,8 +1270,10 @@ claw_status lc_validate(const claw_lc_desc* d) {
     if (d->nx < 2 || d->ny < 2) return fail(CLAW_E_INVALID, "grid must be at least 2 x 2");
     if (3 * d->nx * d->ny >= ((int64_t)1 << 31) || d->nx + 1 >= ((int64_t)1 << 31) / 3)
         return fail(CLAW_E_UNSUPPORTED, "grid too large for 32-bit offsets");
-    if (!(d->sl[0] > 0 && d->sl[1] > 0 && d->sl[2] > 0 && d->sd[0] > 0 && d->sd[1] > 0 && d->sd[2] > 0))
-        return fail(CLAW_E_INVALID, "input scales must be positive");
+    for (int c = 0; c < 3; ++c)
+        if (!(d->sl[c] > 0 && d->sd1[c] > 0 && d->sd2[c] > 0 && d->sd3[c] > 0) || !isfinite(d->sl[c]) ||
+            !isfinite(d->sd1[c]) || !isfinite(d->sd2[c]) || !isfinite(d->sd3[c]))
+            return fail(CLAW_E_INVALID, "input scales must be positive and finite");
     if (!isfinite(d->mu_h) || !isfinite(d->s_out[0]) || !isfinite(d->s_out[1]) || !isfinite(d->s_out[2]))
         return fail(CLAW_E_INVALID, "non-finite normalisation");
     return CLAW_OK;
@@ -1273,6 +1304,7 @@ LcApply lc_apply_args(const claw_lc_desc* d, const float* dF, const float* dG, v
     a.nuy = (float)nuy;
     a.tau = (float)tau;
     a.kappa = (float)kappa;
+    for (int c = 0; c < 3; ++c) a.s_out[c] = d->s_out[c];
     return a;
 }
 
@@ -1420,27 +1452,85 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
     a.buf0 = (float*)h->buf[0];
     a.buf1 = (float*)h->buf[1];
     a.buf2 = (float*)h->buf[2];
-    a.qsel = 1;  // Q^n = result buffer - 2 (mod 3) of a 2D step
+    a.ctrl = h->ctrl;
+    a.qsel = 0;  // Q^n is the trial's current buffer
     LcApply ap = lc_apply_args(d, a.dF, a.dG, work, dt / h->dx[0], dt / h->dx[1], tau, kappa);
     ap.buf0 = a.buf0;
     ap.buf1 = a.buf1;
     ap.buf2 = a.buf2;
-    ap.qsel = 1;
-    for (int64_t k = 0; k < nsteps; ++k) {
-        st = commit(h);
-        if (st) return st;
-        HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, result_offset(2), h->stream));
-        st = enqueue_trial(h, h->stream, nullptr);
-        if (!st) st = commit(h);
-        if (st) return st;
-        a.ctrl = h->ctrl;
-        a.cq = committed(h);
-        ap.ctrl = h->ctrl;
-        ap.cq = committed(h);
-        HIP_TRY(launch_lc_forward(a, h->stream));
-        HIP_TRY(launch_lc_apply(ap, h->stream));
+    ap.ctrl = h->ctrl;
+    ap.qsel = 0;
+    ap.rsel = result_offset(2);  // the plain result, corrected in place
+    // One learned step: the plain fixed-dt trial, then the corrections from
+    // Q^n applied to its result before the next trial's first sweep accepts it.
+    auto enqueue_step = [&](hipStream_t s) -> claw_status {
+        const int cq = h->parity;
+        claw_status r = enqueue_trial(h, s, nullptr);
+        if (r) return r;
+        a.cq = cq;
+        ap.cq = cq;
+        HIP_TRY(launch_lc_forward(a, s));
+        HIP_TRY(launch_lc_apply(ap, s));
+        return CLAW_OK;
+    };
+    st = commit(h);
+    if (st) return st;
+    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, result_offset(2), h->stream));
+    constexpr int G = 16;  // learned steps per captured graph (even: parity returns)
+    int64_t done = 0;
+    if (nsteps >= G) {
+        struct Key {
+            const void* params;
+            void* work;
+            claw_lc_desc d;
+            float tau, kappa, nux, nuy;
+            int parity;
+        } key;
+        static_assert(sizeof(Key) <= sizeof(h->lc_key), "graph key too large");
+        memset(&key, 0, sizeof key);
+        key.params = params;
+        key.work = work;
+        key.d = *d;
+        key.tau = ap.tau;
+        key.kappa = ap.kappa;
+        key.nux = ap.nux;
+        key.nuy = ap.nuy;
+        key.parity = h->parity;
+        if (!h->lc_exec || memcmp(h->lc_key, &key, sizeof key) != 0) {
+            if (h->lc_exec) (void)hipGraphExecDestroy(h->lc_exec);
+            if (h->lc_graph) (void)hipGraphDestroy(h->lc_graph);
+            h->lc_exec = nullptr;
+            h->lc_graph = nullptr;
+            HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            const int p0 = h->parity;
+            claw_status cs = CLAW_OK;
+            for (int k = 0; k < G && cs == CLAW_OK; ++k) cs = enqueue_step(h->cap_stream);
+            h->parity = p0;
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+            if (cs) {
+                if (g) (void)hipGraphDestroy(g);
+                return cs;
+            }
+            if (e != hipSuccess) return fail(CLAW_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&h->lc_exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                h->lc_exec = nullptr;
+                return fail(CLAW_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+            }
+            h->lc_graph = g;
+            memset(h->lc_key, 0, sizeof h->lc_key);
+            memcpy(h->lc_key, &key, sizeof key);
+        }
+        for (; done + G <= nsteps; done += G) HIP_TRY(hipGraphLaunch(h->lc_exec, h->stream));
     }
-    st = sync_state(h);
+    for (; done < nsteps; ++done) {
+        st = enqueue_step(h->stream);
+        if (st) return st;
+    }
+    st = commit(h);
+    if (!st) st = sync_state(h);
     if (st) return st;
     Ctrl c;
     st = read_ctrl(h, &c);

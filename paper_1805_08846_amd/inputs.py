@@ -169,23 +169,30 @@ def sw_hump(n=1024, seed=0, dtype="f32", nsteps=500):
 
 
 def lc_init_params(seed=0, hidden=64, nin=12, nout=3, out_gain=0.1):
-    """Seeded initial parameters of the 12-64-64-3 correction network, flat in
-    the order W1 (64, 12), b1, W2 (64, 64), b2, W3 (3, 64), b3: weights normal
-    with standard deviation sqrt(2 / fan_in) (the last layer scaled by
-    out_gain), biases zero; values rounded to FP32, returned in FP64."""
+    """Seeded initial parameters of the two correction networks (x faces,
+    then y faces), each 12-64-64-3 and flat in the order W1 (64, 12), b1,
+    W2 (64, 64), b2, W3 (3, 64), b3: weights normal with standard deviation
+    sqrt(2 / fan_in) (the last layer scaled by out_gain), biases zero; drawn
+    from default_rng(seed), x network first; rounded to FP32, returned in FP64."""
     rng = np.random.default_rng(seed)
-    w1 = rng.normal(0.0, math.sqrt(2.0 / nin), size=(hidden, nin))
-    w2 = rng.normal(0.0, math.sqrt(2.0 / hidden), size=(hidden, hidden))
-    w3 = rng.normal(0.0, out_gain * math.sqrt(2.0 / hidden), size=(nout, hidden))
-    theta = np.concatenate([w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden),
-                            w3.ravel(), np.zeros(nout)])
-    return theta.astype(np.float32).astype(np.float64)
+    nets = []
+    for _ in range(2):
+        w1 = rng.normal(0.0, math.sqrt(2.0 / nin), size=(hidden, nin))
+        w2 = rng.normal(0.0, math.sqrt(2.0 / hidden), size=(hidden, hidden))
+        w3 = rng.normal(0.0, out_gain * math.sqrt(2.0 / hidden), size=(nout, hidden))
+        nets.append(np.concatenate([w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden),
+                                    w3.ravel(), np.zeros(nout)]))
+    return np.concatenate(nets).astype(np.float32).astype(np.float64)
 
 
-def lc_norm(mu_h=1.0, sd=(0.01, 0.005, 0.005), sl=(0.2, 0.1, 0.1), s_out=(1e-4, 1e-4, 1e-4)):
-    """Input and output scales of the correction network (a plain dict)."""
-    return {"mu_h": float(mu_h), "sd": tuple(float(v) for v in sd),
-            "sl": tuple(float(v) for v in sl), "s_out": tuple(float(v) for v in s_out)}
+def lc_norm(mu_h=1.0, sl=(0.1, 0.03, 0.03), sd1=(1e-3, 3e-4, 2e-4), sd2=(6e-5, 1.5e-5, 6e-6),
+            sd3=(4e-6, 1e-6, 2e-7), s_out=(1e-4, 1e-4, 1e-4)):
+    """Input and output scales of the correction network (a plain dict): per
+    channel (h, m_n, m_t) the scales of the stencil's level, slope, curvature
+    and third difference, and of the outputs.  The defaults are the typical
+    magnitudes over the Gaussian-hump family at side 512."""
+    t = lambda v: tuple(float(x) for x in v)  # noqa: E731
+    return {"mu_h": float(mu_h), "sl": t(sl), "sd1": t(sd1), "sd2": t(sd2), "sd3": t(sd3), "s_out": t(s_out)}
 
 
 def problem(name, **kw):

@@ -142,7 +142,7 @@ def test_learned_sizes_and_validation(claw):
         with pytest.raises(claw.ClawError):
             claw.claw_lc_sizes(bad)
     bad = _lc_desc(claw)
-    bad.sd[1] = 0.0
+    bad.sd2[1] = 0.0
     with pytest.raises(claw.ClawError):
         claw.claw_lc_sizes(bad)
 

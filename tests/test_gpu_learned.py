@@ -1,11 +1,13 @@
 """GPU parity of the learned coarse-grid correction against the CPU oracle
 (oracle/learned.py), through the C ABI.
 
-Network outputs and gradients: the device accumulates BF16 products in FP32,
-the oracle in FP64 with the same BF16 rounding points, so an activation that
-lands next to a BF16 rounding boundary can round the other way; outputs are
-compared at 2e-3 of their largest magnitude (most agree to ~1e-6), gradients
-at 1e-3 relative per parameter tensor.  Application and fallback decisions
+Network outputs and gradients: the device forms the features and sums the
+BF16 products in FP32, the oracle in FP64 with the same BF16 rounding points,
+so an input or activation next to a BF16 rounding boundary can round the other
+way (one BF16 step is 2^-8 of that value).  Outputs: all but 0.1 % of the
+faces (or 4 faces on small grids) agree to 1e-4 of the largest output (the
+median to ~1e-9), every face to 1e-2.
+Gradients, sums over all faces: 1e-3 relative per parameter tensor.  Application and fallback decisions
 are FP32 on both sides from the same inputs: bitwise.
 """
 import numpy as np
@@ -27,7 +29,8 @@ def claw():
 
 
 def _norm():
-    return inputs.lc_norm(mu_h=1.1, sd=(0.02, 0.01, 0.01), sl=(0.2, 0.1, 0.1), s_out=(0.01, 0.02, 0.03))
+    return inputs.lc_norm(mu_h=1.1, sl=(0.2, 0.1, 0.1), sd1=(0.02, 0.01, 0.01), sd2=(0.03, 0.01, 0.01),
+                          sd3=(0.05, 0.02, 0.02), s_out=(0.01, 0.02, 0.03))
 
 
 def _state(ny, nx, seed):
@@ -64,8 +67,9 @@ def test_forward_matches_oracle(claw, ny, nx):
         scale = np.abs(ref).max()
         err = np.abs(got - ref)
         print(f"{ny}x{nx}: max {err.max() / scale:.2e}, median {np.median(err) / scale:.2e}")
-        assert err.max() <= 2e-3 * scale
-        assert np.median(err) <= 1e-5 * scale
+        assert err.max() <= 1e-2 * scale
+        assert np.sum(err > 1e-4 * scale) <= max(12, 1e-3 * err.size)  # a few faces (3 components each)
+        assert np.median(err) <= 1e-6 * scale
 
 
 @pytest.mark.parametrize("ny,nx,seed", [(70, 130, 0), (33, 40, 1)])
@@ -87,13 +91,15 @@ def test_loss_gradient_matches_oracle(claw, ny, nx, seed):
     r = target.astype(np.float64) - plain
     assert np.allclose(loss[1:], (r * r).sum(axis=(1, 2)), rtol=1e-5)
     o = 0
-    for name, shape in L.SHAPES:
-        k = int(np.prod(shape))
-        g, e = got[o:o + k], ref[o:o + k]
-        rel = np.abs(g - e).max() / np.abs(e).max()
-        print(f"{name}: rel {rel:.2e}")
-        assert rel <= 1e-3, name
-        o += k
+    for net in ("x", "y"):
+        for name, shape in L.SHAPES:
+            k = int(np.prod(shape))
+            g, e = got[o:o + k], ref[o:o + k]
+            rel = np.abs(g - e).max() / np.abs(e).max()
+            print(f"{net} {name}: rel {rel:.2e}")
+            assert rel <= 1e-3, (net, name)
+            o += k
+    assert o == L.NPARAM
 
 
 def test_adam_matches_oracle(claw):
@@ -116,7 +122,8 @@ def test_adam_matches_oracle(claw):
     lc.forward(_dev(q), dF, dG)
     torch.cuda.synchronize()
     rF, _ = L.face_corrections(got, _norm(), q.astype(np.float64))
-    assert np.abs(dF.double().cpu().numpy() - rF).max() <= 2e-3 * np.abs(rF).max()
+    err = np.abs(dF.double().cpu().numpy() - rF)
+    assert err.max() <= 1e-2 * np.abs(rF).max() and np.median(err) <= 1e-6 * np.abs(rF).max()
 
 
 def _apply_case(ny, nx, seed, big=False, scale=1.0):
@@ -133,10 +140,10 @@ def _apply_case(ny, nx, seed, big=False, scale=1.0):
     return qn, plain, dF, dG
 
 
-# kappa 0.005: the magnitude test decides; kappa 10 with 50x larger
+# kappa 1: the magnitude test decides; kappa 1000 with 50x larger
 # corrections: the positivity pass decides
-@pytest.mark.parametrize("ny,nx,seed,kappa,scale", [(70, 130, 0, 0.005, 1.0), (70, 130, 1, 10.0, 50.0),
-                                                    (9, 5, 1, 0.005, 1.0), (2, 2, 2, 0.005, 1.0)])
+@pytest.mark.parametrize("ny,nx,seed,kappa,scale", [(70, 130, 0, 1.0, 1.0), (70, 130, 1, 1000.0, 50.0),
+                                                    (9, 5, 1, 1.0, 1.0), (2, 2, 2, 1.0, 1.0)])
 def test_apply_matches_oracle_bitwise(claw, ny, nx, seed, kappa, scale):
     qn, plain, dF, dG = _apply_case(ny, nx, seed, scale=scale)
     nux, nuy, tau = 0.45, 0.4, 0.3
@@ -146,7 +153,7 @@ def test_apply_matches_oracle_bitwise(claw, ny, nx, seed, kappa, scale):
     ky = torch.full((ny + 1, nx), 7, dtype=torch.uint8, device="cuda")
     lc.apply(_dev(qn), _dev(plain), _dev(dF), _dev(dG), nux, nuy, tau, kappa, out, kx, ky)
     torch.cuda.synchronize()
-    ref, rkx, rky = L.apply(qn, plain, dF, dG, nux, nuy, tau, kappa)
+    ref, rkx, rky = L.apply(qn, plain, dF, dG, nux, nuy, tau, kappa, _norm()["s_out"])
     assert np.array_equal(kx.cpu().numpy().astype(bool), rkx)
     assert np.array_equal(ky.cpu().numpy().astype(bool), rky)
     assert np.array_equal(out.cpu().numpy(), ref)
@@ -178,12 +185,13 @@ def test_coarsen_matches_oracle(claw):
     assert np.abs(coarse.double().cpu().numpy() - ref).max() <= 2e-7 * np.abs(ref).max()
 
 
-def test_learned_advance_equals_composition_and_conserves(claw):
-    n, steps, dt = 64, 6, 0.4 / 64
+@pytest.mark.parametrize("steps", [6, 40])  # 40: two captured graphs of 16 and 8 eager steps
+def test_learned_advance_equals_composition_and_conserves(claw, steps):
+    n, dt = 64, 0.4 / 64
     prob, q0, _ = inputs.sw_hump(n=n, seed=9, dtype="f32", nsteps=steps)
     th = inputs.lc_init_params(seed=9, out_gain=1.0)
     norm = inputs.lc_norm(s_out=(2e-3, 2e-3, 2e-3))
-    tau, kappa = 0.5, 0.05
+    tau, kappa = 0.5, 5.0
     # fused: plain step + correction from Q^n, on the device, no host round trip
     qa = _dev(q0)
     sa = claw.Solver(prob, qa)
@@ -213,3 +221,18 @@ def test_learned_advance_equals_composition_and_conserves(claw):
     assert not np.array_equal(qc.cpu().numpy(), a)
     for s in (sa, sb, sc):
         s.close()
+
+
+def test_fixed_steps_graph_path_equals_eager_path(claw):
+    prob, q0, _ = inputs.sw_hump(n=96, seed=2, dtype="f32", nsteps=70)
+    dt = 0.5 / 96
+    qa, qb = _dev(q0), _dev(q0)
+    sa, sb = claw.Solver(prob, qa), claw.Solver(prob, qb)
+    assert sa.advance_fixed([dt] * 70, log=False) is None  # 2 graphs of 32 + 6 eager
+    cfl = sb.advance_fixed([dt] * 70)
+    torch.cuda.synchronize()
+    assert np.array_equal(qa.cpu().numpy(), qb.cpu().numpy())
+    assert sa.control()["t"] == sb.control()["t"]
+    assert 0.3 < cfl.max() < 1.0
+    sa.close()
+    sb.close()
