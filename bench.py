@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -146,6 +148,62 @@ def bench_ensemble(args, torch, claw, inputs):
     }
 
 
+def bench_learned(args, torch, claw, inputs):
+    """Learned coarse correction: train the two direction networks on the GPU
+    (200 seeded Gaussian-hump runs at 1024^2, 500 fine steps each, samples
+    every 2 fine steps coarse-grained to 512^2), then on held-out seeds compare
+    the corrected 512^2 run with plain 512^2 and 1024^2 runs against the plain
+    2048^2 run coarse-grained (L1 of depth over T = 250 coarse steps).  The
+    value is the speedup at equal L1: T_plain(n_eq) / T_learned."""
+    from paper_1805_08846_amd import learned
+    runs = args.train_runs
+    t0 = time.perf_counter()
+    tr = learned.Trainer(n_fine=1024, total_samples=runs * 250)
+    for k in range(runs):
+        tr.run(seed=1000 + k)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"# learned: trained on {runs} runs ({tr.samples} Adam steps) in {t_train:.1f} s", file=sys.stderr,
+          flush=True)
+    seeds = list(range(1, 1 + args.eval_seeds))
+    one_plain, one_learned = learned.one_step_gain(tr.lc, seeds=seeds[:2])
+    res = learned.evaluate(tr.lc, seeds=seeds, steps_coarse=250)
+    rows = res.pop("rows")
+    tr.close()
+    fields = {
+        "plain_512": np.mean([r["plain"][512]["l1_fields"] for r in rows], axis=0).tolist(),
+        "plain_1024": np.mean([r["plain"][1024]["l1_fields"] for r in rows], axis=0).tolist(),
+        "learned_512": np.mean([r["learned"]["l1_fields"] for r in rows], axis=0).tolist(),
+    }
+    return {
+        "metric": "speedup at equal L1 error vs plain fine grid (learned 512^2)",
+        "value": res["speedup_equal_l1"],
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": 250,
+        "warmup": 0,
+        "ms_per_step": res["seconds_learned"] / 250 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 state, bf16 network (fp32 accumulation)",
+        "data": "synthetic (seeded Gaussian humps; held-out seeds for evaluation)",
+        "config": {"workload": "learned coarse flux correction, shallow water 512^2 (trained at 1024^2, "
+                               "reference 2048^2)", "train_runs": runs, "eval_seeds": seeds,
+                   "parallelism": "single GPU"},
+        "l1_depth": {"plain_512": res["l1_plain"][0], "plain_1024": res["l1_plain"][-1],
+                     "learned_512": res["l1_learned"]},
+        "l1_fields_h_hu_hv": fields,
+        "seconds_per_run": {"plain_512": res["seconds_plain"][0], "plain_1024": res["seconds_plain"][-1],
+                            "learned_512": res["seconds_learned"]},
+        "n_equal": res["n_equal"],
+        "note": res.get("note"),
+        "one_step_l1_h_hu_hv": {"plain": one_plain, "learned": one_learned},
+        "mass_drift_max": res["mass_drift_max"],
+        "train_seconds": t_train,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,8 +219,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
-    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble"])
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned"])
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
+    ap.add_argument("--train-runs", type=int, default=200, help="learned: training runs")
+    ap.add_argument("--eval-seeds", type=int, default=5, help="learned: held-out evaluation seeds")
     args = ap.parse_args()
     args.steps_given = "--steps" in sys.argv
     args.warmup_given = "--warmup" in sys.argv
@@ -180,6 +240,9 @@ def main():
         sys.exit(1)
     if args.workload == "ensemble":
         print(json.dumps(bench_ensemble(args, torch, claw, inputs)), flush=True)
+        return
+    if args.workload == "learned":
+        print(json.dumps(bench_learned(args, torch, claw, inputs)), flush=True)
         return
 
     prob, q0, _ = inputs.sw_radial_dam(n=args.n, dtype=args.dtype, nsteps=args.steps)

@@ -185,12 +185,13 @@ def lc_init_params(seed=0, hidden=64, nin=12, nout=3, out_gain=0.1):
     return np.concatenate(nets).astype(np.float32).astype(np.float64)
 
 
-def lc_norm(mu_h=1.0, sl=(0.1, 0.03, 0.03), sd1=(1e-3, 3e-4, 2e-4), sd2=(6e-5, 1.5e-5, 6e-6),
-            sd3=(4e-6, 1e-6, 2e-7), s_out=(1e-4, 1e-4, 1e-4)):
+def lc_norm(mu_h=1.0, sl=(0.1, 0.03, 0.03), sd1=(1e-3, 3e-4, 3e-4), sd2=(6e-5, 1.5e-5, 1.5e-5),
+            sd3=(4e-6, 1e-6, 1e-6), s_out=(1e-4, 1e-4, 1e-4)):
     """Input and output scales of the correction network (a plain dict): per
     channel (h, m_n, m_t) the scales of the stencil's level, slope, curvature
     and third difference, and of the outputs.  The defaults are the typical
-    magnitudes over the Gaussian-hump family at side 512."""
+    magnitudes over the Gaussian-hump family at side 512, the same for both
+    momentum channels and kept well above FP32 rounding of the states."""
     t = lambda v: tuple(float(x) for x in v)  # noqa: E731
     return {"mu_h": float(mu_h), "sl": t(sl), "sd1": t(sd1), "sd2": t(sd2), "sd3": t(sd3), "s_out": t(s_out)}
 

@@ -33,6 +33,13 @@ from . import claw, inputs
 
 S_MAX = 1.6  # bound on |u| + sqrt(g h) over the hump family's runs (checked per run: CFL <= 1)
 CFL = 0.9
+# Training input noise per field (h, hu, hv): the network sees Q^n perturbed
+# at about the level by which a coarse run drifts from the coarse-grained fine
+# run, so that it does not build on grid-scale detail its own corrections
+# would feed back (without it the corrected runs go unstable).
+NOISE = (1e-5, 3e-5, 3e-5)
+TAU = 0.3      # shock test: relative depth jump across a face
+KAPPA = 1000.0  # magnitude test, in output scales (only far-out outputs fall back)
 
 
 def fine_dt(n_fine):
@@ -73,7 +80,8 @@ class Trainer:
     correction network on side n_fine / 2."""
 
     def __init__(self, n_fine=1024, norm=None, theta0=None, init_seed=0, lr=1e-3, lr_final=3e-5,
-                 total_samples=None, resync=1, tau=0.3, kappa=4.0):
+                 total_samples=None, resync=1, tau=0.3, kappa=KAPPA, noise=NOISE, noise_seed=0,
+                 correct_depth=True):
         torch = _torch()
         self.nf = int(n_fine)
         self.nc = self.nf // 2
@@ -87,6 +95,10 @@ class Trainer:
         self.lr, self.lr_final = lr, lr_final
         self.total = total_samples
         self.resync, self.tau, self.kappa = int(resync), tau, kappa
+        self.correct_depth = bool(correct_depth)
+        # input noise per field (random draws are inputs: torch's seeded generator)
+        self.noise = tuple(float(v) for v in noise)
+        self.gen = torch.Generator(device="cuda").manual_seed(int(noise_seed))
         self.samples = 0
         self.losses = []
         self.scaled = False
@@ -111,7 +123,8 @@ class Trainer:
         ms = np.asarray(r2, dtype=np.float64) / (self.nc * self.nc)
         rms = np.sqrt(np.maximum(ms, 1e-30))
         mom = 0.5 * (rms[1] + rms[2])
-        s = (rms[0] / self.nu, mom / self.nu, mom / self.nu)
+        # correct_depth False: momentum-only corrections (output scale of h zero)
+        s = (rms[0] / self.nu if self.correct_depth else 0.0, mom / self.nu, mom / self.nu)
         self.norm["s_out"] = tuple(float(v) for v in s)
         self.lc.desc = claw.lc_desc(self.nc, self.nc, self.norm)
         self.w = tuple(float(1.0 / m) for m in np.maximum(ms, 1e-30))
@@ -136,7 +149,13 @@ class Trainer:
             self.coarse.advance_fixed([self.dt_c], log=False)
             fine.advance_fixed([self.dt_f, self.dt_f], log=False)
             claw.claw_lc_coarsen(self.nc, self.nc, qf, self.target, _stream())
-            self.lc.loss_grad(self.qcn, self.target, self.plain, self.nu, self.nu, self.w)
+            if any(self.noise) and self.scaled:
+                # the network sees a perturbed Q^n; the plain step and the target do not
+                qin = self.qcn + torch.randn(self.qcn.shape, generator=self.gen, device="cuda") * \
+                    torch.tensor(self.noise, device="cuda").view(3, 1, 1)
+            else:
+                qin = self.qcn
+            self.lc.loss_grad(qin, self.target, self.plain, self.nu, self.nu, self.w)
             if not self.scaled:
                 first.append(self.lc.loss[1:].cpu().numpy().copy())
                 if len(first) == 8:
@@ -228,7 +247,7 @@ def _timed_learned(lc, prob, q0, dt, steps, tau, kappa, repeat=2):
     return out, best
 
 
-def evaluate(lc, seeds, n_coarse=512, steps_coarse=250, grids=(512, 1024), tau=0.3, kappa=4.0,
+def evaluate(lc, seeds, n_coarse=512, steps_coarse=250, grids=(512, 1024), tau=TAU, kappa=KAPPA,
              ref_factor=4):
     """Errors and times of plain runs on `grids` (multiples of n_coarse that
     divide the reference's side, so every remap is an exact block average) and
@@ -266,6 +285,44 @@ def evaluate(lc, seeds, n_coarse=512, steps_coarse=250, grids=(512, 1024), tau=0
                                               / q0[0].astype(np.float64).sum())}
         rows.append(row)
     return summarize(rows)
+
+
+def one_step_gain(lc, seeds, n_fine=1024, steps_fine=500, every=10, tau=TAU, kappa=KAPPA):
+    """Teacher-forced one-step errors on held-out runs: from Q_c = C(Q_f^{2n})
+    the plain coarse step and the corrected one, each against C(Q_f^{2n+2});
+    mean absolute error per field over the sampled steps, (plain, learned)."""
+    torch = _torch()
+    nf, nc = int(n_fine), int(n_fine) // 2
+    dtf = fine_dt(nf)
+    dtc, nu = 2 * dtf, 2 * dtf * nc
+    shp = (3, nc, nc)
+    plain = torch.empty(shp, dtype=torch.float32, device="cuda")
+    qcn, target, out = torch.empty_like(plain), torch.empty_like(plain), torch.empty_like(plain)
+    dF = torch.empty((3, nc, nc + 1), dtype=torch.float32, device="cuda")
+    dG = torch.empty((3, nc + 1, nc), dtype=torch.float32, device="cuda")
+    pc, _, _ = inputs.sw_hump(n=nc, seed=0, dtype="f32")
+    coarse = claw.Solver(pc, plain)
+    e_plain, e_learned, count = np.zeros(3), np.zeros(3), 0
+    for seed in seeds:
+        pf, qf0, _ = inputs.sw_hump(n=nf, seed=seed, dtype="f32")
+        qf = _dev(qf0)
+        fine = claw.Solver(pf, qf)
+        claw.claw_lc_coarsen(nc, nc, qf, qcn, _stream())
+        for k in range(steps_fine // 2):
+            plain.copy_(qcn)
+            coarse.advance_fixed([dtc], log=False)
+            fine.advance_fixed([dtf, dtf], log=False)
+            claw.claw_lc_coarsen(nc, nc, qf, target, _stream())
+            if k % every == every // 2:
+                lc.forward(qcn, dF, dG)
+                lc.apply(qcn, plain, dF, dG, nu, nu, tau, kappa, out)
+                e_plain += (plain - target).abs().mean(dim=(1, 2)).double().cpu().numpy()
+                e_learned += (out - target).abs().mean(dim=(1, 2)).double().cpu().numpy()
+                count += 1
+            qcn, target = target, qcn
+        fine.close()
+    coarse.close()
+    return (e_plain / count).tolist(), (e_learned / count).tolist()
 
 
 def summarize(rows):
