@@ -36,7 +36,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "claw_device.h"):
+    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h"):
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
