@@ -46,6 +46,12 @@ extern "C" {
 
 typedef struct claw_solver claw_solver; /* opaque */
 
+/* claw_desc.flags: CLAW_FLAG_FUSED_STEP runs each 2D shallow-water step as one
+ * kernel (the x sweep kept in LDS, then the y sweep) instead of an x and a y
+ * sweep kernel; same results to rounding, one read and one write of the state
+ * per step.  Needs non-periodic y boundaries; ignored for other problems. */
+#define CLAW_FLAG_FUSED_STEP 1
+
 typedef enum {
     CLAW_OK = 0,
     CLAW_E_INVALID = 1,     /* bad descriptor, pointer or argument */
@@ -82,7 +88,7 @@ typedef struct {
     int32_t bc_lo[3];    /* claw_bc per direction */
     int32_t bc_hi[3];
     int32_t num_ghost;   /* must be 2 */
-    int32_t reserved;
+    int32_t flags;       /* CLAW_FLAG_* bits, 0 for the default path */
     double rho, bulk;    /* acoustics coefficients when maux = 0 */
     double grav;         /* shallow water gravity */
     double cfl_desired;  /* target Courant number for the next step (0.9) */

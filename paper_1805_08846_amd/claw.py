@@ -21,6 +21,7 @@ CLAW_FP32, CLAW_FP64 = 0, 1
 CLAW_RP_ACOUSTICS, CLAW_RP_SHALLOW_WATER = 0, 1
 CLAW_BC_EXTRAP, CLAW_BC_WALL, CLAW_BC_PERIODIC = 0, 1, 2
 CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER = 0, 1, 2
+CLAW_FLAG_FUSED_STEP = 1
 
 _BC = {"extrap": CLAW_BC_EXTRAP, "wall": CLAW_BC_WALL, "periodic": CLAW_BC_PERIODIC}
 _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER}
@@ -54,7 +55,7 @@ class claw_desc(ctypes.Structure):
         ("bc_lo", ctypes.c_int32 * 3),
         ("bc_hi", ctypes.c_int32 * 3),
         ("num_ghost", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
         ("rho", ctypes.c_double),
         ("bulk", ctypes.c_double),
         ("grav", ctypes.c_double),
@@ -479,6 +480,7 @@ def desc_from_problem(prob):
     d.cfl_max = float(prob.get("cfl_max", 1.0))
     dm = prob.get("dt_max", float("inf"))
     d.dt_max = float(dm) if dm is not None else math.inf
+    d.flags = CLAW_FLAG_FUSED_STEP if prob.get("fused_step") else 0
     return d
 
 

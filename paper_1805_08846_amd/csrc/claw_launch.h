@@ -12,6 +12,20 @@ namespace claw {
 template <typename R>
 hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds, hipStream_t s);
 
+// Fused 2D shallow-water step (fused.hip): x sweep into an LDS tile, y sweep
+// out of it.  a: the x-sweep arguments (grid, buffers, control, x boundaries,
+// parity); ny and the y boundaries complete the grid.
+template <typename R>
+struct FusedArgs {
+    SweepArgs<R> a;
+    int32_t ny, bcy_lo, bcy_hi, pad;
+};
+template <typename R>
+hipError_t launch_step2d(const FusedArgs<R>& F, hipStream_t s);
+// Decides the previous trial into step-state copy p and clears p's speed slots.
+hipError_t launch_open(Ctrl* c, int p, bool fp32, hipStream_t s);
+int fused_tile_rows();
+
 // One-thread step-control kernels on step-state copy q (see control.hip).
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired,
                             double cfl_max, double dt_max, hipStream_t s);

@@ -64,6 +64,7 @@ claw_status validate(const claw_desc* d) {
     }
     if (d->ndim == 2 && d->n[2] != 1) return fail(CLAW_E_INVALID, "2D grids need n[2] = 1");
     if (d->num_ghost != 2) return fail(CLAW_E_INVALID, "num_ghost must be 2 (got %d)", d->num_ghost);
+    if (d->flags & ~CLAW_FLAG_FUSED_STEP) return fail(CLAW_E_INVALID, "unknown flags 0x%x", (unsigned)d->flags);
     if (d->dtype != CLAW_FP32 && d->dtype != CLAW_FP64) return fail(CLAW_E_INVALID, "unknown dtype");
     if (d->limiter < 0 || d->limiter > 2) return fail(CLAW_E_INVALID, "unknown limiter");
     if (!(d->cfl_desired > 0) || !(d->cfl_max >= d->cfl_desired))
@@ -110,6 +111,7 @@ struct claw_solver {
     Plan plan;
     int sys;
     bool fp32;
+    bool fused;  // one fused kernel per 2D step (fused.hip) instead of an x and a y sweep
     hipStream_t stream;
     hipStream_t cap_stream;
     void* buf[3];
@@ -225,11 +227,35 @@ hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, bool
 
 int committed(const claw_solver* h) { return h->parity ^ 1; }
 
+// Buffer offset of a step's result: the fused 2D step writes cur + 1.
+int result_offset_of(const claw_solver* h) { return h->fused ? 1 : result_offset(h->d.ndim); }
+
+template <typename R>
+FusedArgs<R> fused_args(const claw_solver* h, int parity) {
+    FusedArgs<R> F;
+    memset(&F, 0, sizeof F);
+    F.a = sweep_args<R>(h, 0, 0, 1);
+    F.a.parity = parity;
+    F.ny = (int32_t)h->d.n[1];
+    F.bcy_lo = h->d.bc_lo[1];
+    F.bcy_hi = h->d.bc_hi[1];
+    return F;
+}
+
 // One trial step: the sweeps x, y (, z).  The first decides the previous
 // trial on the device; the trial itself is decided by the next trial's first
 // sweep or by a commit.  ev (optional) receives an event before each sweep and
 // one after the last.
 claw_status enqueue_trial(claw_solver* h, hipStream_t s, hipEvent_t* ev) {
+    if (h->fused) {
+        HIP_TRY(launch_open(h->ctrl, h->parity, h->fp32, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+        if (h->fp32) HIP_TRY(launch_step2d<float>(fused_args<float>(h, h->parity), s));
+        else HIP_TRY(launch_step2d<double>(fused_args<double>(h, h->parity), s));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+        h->parity ^= 1;
+        return CLAW_OK;
+    }
     for (int dir = 0; dir < h->d.ndim; ++dir) {
         int so, dof;
         step_offsets(h->d.ndim, dir, &so, &dof);
@@ -288,7 +314,7 @@ double smax_value(const claw_solver* h, const Ctrl& c, int q, int dir) {
 // dt_next of a previous run, else cfl_desired / sigma of a speed pass.
 claw_status begin_adaptive(claw_solver* h, double dt0) {
     const int q = committed(h);
-    const int roff = result_offset(h->d.ndim);
+    const int roff = result_offset_of(h);
     if (dt0 > 0) {
         HIP_TRY(launch_begin(h->ctrl, q, dt0, MODE_ADAPT, roff, h->stream));
         return CLAW_OK;
@@ -387,6 +413,8 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
     h->plan = p;
     h->fp32 = d->dtype == CLAW_FP32;
     h->sys = d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC);
+    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && h->sys == SYS_SW && d->ndim == 2 &&
+               d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;
     h->stream = (hipStream_t)stream;
     char* ws = (char*)workspace;
     h->ctrl = (Ctrl*)(ws + p.off_ctrl);
@@ -443,7 +471,7 @@ claw_status claw_step(claw_solver* h, double dt, double* cfl) {
     if (!(dt > 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be positive and finite");
     claw_status st = commit(h);
     if (st) return st;
-    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_STEP, result_offset(h->d.ndim), h->stream));
+    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_STEP, result_offset_of(h), h->stream));
     st = enqueue_trial(h, h->stream, nullptr);
     if (!st) st = commit(h);
     if (st || !cfl) return st;
@@ -534,7 +562,7 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
         // accepted by the next trial's first sweep
         st = commit(h);
         if (st) return st;
-        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[0], MODE_FIXED, result_offset(h->d.ndim), h->stream));
+        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[0], MODE_FIXED, result_offset_of(h), h->stream));
         st = ensure_graph(h);
         if (st) return st;
         const int64_t reps = nsteps / kGraphSteps;
@@ -551,7 +579,7 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
     for (int64_t k = 0; k < nsteps; ++k) {
         st = commit(h);
         if (st) return st;
-        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[k], MODE_FIXED, result_offset(h->d.ndim), h->stream));
+        HIP_TRY(launch_begin(h->ctrl, committed(h), dts[k], MODE_FIXED, result_offset_of(h), h->stream));
         st = enqueue_trial(h, h->stream, nullptr);
         if (!st) st = commit(h);
         if (st) return st;
@@ -595,9 +623,10 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
             st = commit(h);
             if (st) return st;
             HIP_TRY(hipStreamSynchronize(h->stream));
+            const int nk = h->fused ? 1 : h->d.ndim;  // timed kernels per trial
             for (int64_t k = 0; k < n; ++k) {
                 hipEvent_t* ev = &h->events[k * per];
-                for (int j = 0; j < h->d.ndim; ++j) {
+                for (int j = 0; j < nk; ++j) {
                     float v = 0;
                     HIP_TRY(hipEventElapsedTime(&v, ev[j], ev[j + 1]));
                     ms[j] += v;
@@ -1460,7 +1489,7 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
     ap.buf2 = a.buf2;
     ap.ctrl = h->ctrl;
     ap.qsel = 0;
-    ap.rsel = result_offset(2);  // the plain result, corrected in place
+    ap.rsel = result_offset_of(h);  // the plain result, corrected in place
     // One learned step: the plain fixed-dt trial, then the corrections from
     // Q^n applied to its result before the next trial's first sweep accepts it.
     auto enqueue_step = [&](hipStream_t s) -> claw_status {
@@ -1475,7 +1504,7 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
     };
     st = commit(h);
     if (st) return st;
-    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, result_offset(2), h->stream));
+    HIP_TRY(launch_begin(h->ctrl, committed(h), dt, MODE_FIXED, result_offset_of(h), h->stream));
     constexpr int G = 16;  // learned steps per captured graph (even: parity returns)
     int64_t done = 0;
     if (nsteps >= G) {

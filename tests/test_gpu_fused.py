@@ -1,0 +1,91 @@
+"""The fused 2D shallow-water step (CLAW_FLAG_FUSED_STEP: x sweep kept in LDS,
+then the y sweep, one kernel per step) against the CPU oracle and against the
+two-kernel path: same tolerances as the two-kernel path (FP64 1e-12, FP32 1e-5
+relative L-infinity of the whole state); tile edges in x and y, ragged tiles,
+FP32 and FP64 tile widths, walls and extrapolation in y."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_08846_amd import inputs
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def claw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+def _run(claw, prob, q0, fused, steps=None, dts=None):
+    prob = dict(prob, fused_step=fused)
+    dt = torch.float64 if prob["dtype"] == "f64" else torch.float32
+    q = torch.tensor(q0, dtype=dt, device="cuda").contiguous()
+    s = claw.Solver(prob, q)
+    if dts is None:
+        t, nrej = s.advance(steps)
+    else:
+        s.advance_fixed(dts)
+        t, nrej = s.control()["t"], 0
+    torch.cuda.synchronize()
+    out = q.double().cpu().numpy()
+    ms, cnt = s.advance_timed(1)
+    s.close()
+    return out, t, nrej, cnt
+
+
+@pytest.mark.parametrize("dtype,n", [("f64", 200), ("f32", 333), ("f64", 131), ("f32", 64)])
+def test_fused_adaptive_matches_oracle(claw, dtype, n):
+    prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=dtype, nsteps=60, seed=3)
+    out, t, nrej, cnt = _run(claw, prob, q0, True, steps=60)
+    assert cnt[0] >= 1 and cnt[1] == 0  # one kernel per step
+    ref = oracle.advance(prob, q0, None, 60)
+    err, per = rel_linf(out, ref["q"])
+    print(f"fused {dtype} {n}^2: rel {err:.2e} per field {per}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("bc", ["extrap", "wall"])
+def test_fused_rectangular_and_boundaries(claw, bc):
+    prob, q0, _ = inputs.sw_radial_dam(n=96, dtype="f64", nsteps=30, seed=4)
+    prob["n"] = (250, 37, 1)
+    prob["bc_lo"] = ("wall", bc, bc)
+    prob["bc_hi"] = ("extrap", bc, bc)
+    rng = np.random.default_rng(4)
+    q0 = np.zeros((3, 1, 37, 250))
+    q0[0] = 1.0 + 0.5 * rng.uniform(size=(1, 37, 250))
+    q0[1] = 0.1 * rng.uniform(-1, 1, size=(1, 37, 250))
+    q0[2] = 0.1 * rng.uniform(-1, 1, size=(1, 37, 250))
+    out, _, _, _ = _run(claw, prob, q0, True, steps=30)
+    split, _, _, _ = _run(claw, prob, q0, False, steps=30)
+    ref = oracle.advance(prob, q0, None, 30)
+    err, _ = rel_linf(out, ref["q"])
+    assert err <= 1e-12
+    assert rel_linf(out, split)[0] <= 1e-13
+
+
+def test_fused_prescribed_steps_fp32(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=257, dtype="f32", nsteps=40, seed=8)
+    ref = oracle.advance(prob, q0, None, 40)
+    dts = ref["dts"][ref["accepted"]]
+    out, _, _, _ = _run(claw, prob, q0, True, dts=dts)
+    qf, _ = oracle.advance_fixed(prob, q0, None, dts)
+    assert rel_linf(out, qf)[0] <= 1e-5
+
+
+def test_periodic_y_falls_back_to_two_kernels(claw):
+    prob, q0, _ = inputs.sw_radial_dam(n=64, dtype="f64", nsteps=5, seed=1)
+    prob["bc_lo"] = ("wall", "periodic", "periodic")
+    prob["bc_hi"] = ("wall", "periodic", "periodic")
+    out, _, _, cnt = _run(claw, prob, q0, True, steps=5)
+    assert cnt[1] >= 1  # x and y sweep kernels
+    ref = oracle.advance(prob, q0, None, 5)
+    assert rel_linf(out, ref["q"])[0] <= 1e-12

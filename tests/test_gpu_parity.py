@@ -265,7 +265,8 @@ def test_graph_path_equals_eager_path_bitwise(claw):
     s1.advance(70)
     s2, q2 = _solver(claw, prob, q0)
     ms, cnt = s2.advance_timed(70)
-    assert cnt[0] == cnt[1] >= 70 and cnt[3] == 0
+    # x and y sweeps, or one fused step kernel per trial (2D shallow water)
+    assert cnt[0] >= 70 and cnt[1] in (0, cnt[0]) and cnt[3] == 0
     assert np.array_equal(_host(q1), _host(q2))
 
 
