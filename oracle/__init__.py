@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 _SYSTEM = {"acoustics": 0, "shallow_water": 1}
 _BC = {"extrap": 0, "wall": 1, "periodic": 2}
-_LIM = {"mc": 0, "none": 1, "first_order": 2}
+_LIM = {"mc": 0, "none": 1, "first_order": 2, "minmod": 3, "superbee": 4, "vanleer": 5}
 
 STATUS = {0: "ok", 1: "invalid description", 5: "non-physical state", 6: "step control failed"}
 
@@ -61,6 +61,8 @@ def _lib(precision="f64"):
         vp = ctypes.c_void_p
         lib.oracle_mc_phi.restype = ctypes.c_double
         lib.oracle_mc_phi.argtypes = [ctypes.c_double]
+        lib.oracle_phi.restype = ctypes.c_double
+        lib.oracle_phi.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.oracle_riemann_acoustics.argtypes = [vp, vp] + [ctypes.c_double] * 4 + [
             ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         lib.oracle_riemann_sw.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
@@ -126,6 +128,11 @@ def set_num_threads(n, precision="f64"):
 
 def mc_phi(theta, precision="f64"):
     return _lib(precision).oracle_mc_phi(float(theta))
+
+
+def phi(limiter, theta, precision="f64"):
+    """phi(theta) of a named limiter ("mc", "minmod", "superbee", "vanleer", "none", "first_order")."""
+    return _lib(precision).oracle_phi(_LIM[limiter], float(theta))
 
 
 def riemann_acoustics(ql, qr, Zl, cl, Zr, cr, normal, precision="f64"):

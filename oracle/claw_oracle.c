@@ -187,6 +187,23 @@ static real phi_mc(real theta)
 
 double oracle_mc_phi(double theta) { return (double)phi_mc((real)theta); }
 
+/* The other classical wave limiters of the high-resolution method (LeVeque
+ * 2002, section 6.12): minmod max(0, min(1, theta)); superbee
+ * max(0, min(1, 2 theta), min(2, theta)); van Leer (theta + |theta|) / (1 + |theta|). */
+static real phi_of(int limiter, real theta)
+{
+    switch (limiter) {
+    case ORC_LIM_MC: return phi_mc(theta);
+    case ORC_LIM_MINMOD: return rmax(0, rmin(1, theta));
+    case ORC_LIM_SUPERBEE: return rmax(0, rmax(rmin(1, 2 * theta), rmin(2, theta)));
+    case ORC_LIM_VANLEER: return (theta + rabs(theta)) / (1 + rabs(theta));
+    case ORC_LIM_NONE: return 1;
+    default: return 0;
+    }
+}
+
+double oracle_phi(int limiter, double theta) { return (double)phi_of(limiter, (real)theta); }
+
 int oracle_riemann_acoustics(const double* ql, const double* qr, double Zl, double cl,
                              double Zr, double cr, int meqn, int normal, double* W,
                              double* s, double* amdq, double* apdq)
@@ -337,11 +354,11 @@ static int sweep_line(const line_cfg* c, long m, line_work* w, real* smax, int s
             real wnorm2 = 0, phi, coef;
             for (i = 0; i < meqn; i++) wnorm2 += WV(w, j, p, i) * WV(w, j, p, i);
             if (wnorm2 == 0) continue; /* no wave: no correction */
-            if (c->limiter == ORC_LIM_MC) {
+            if (c->limiter != ORC_LIM_NONE) {
                 long J = sp > 0 ? j - 1 : j + 1; /* upwind interface */
                 real dotup = 0;
                 for (i = 0; i < meqn; i++) dotup += WV(w, J, p, i) * WV(w, j, p, i);
-                phi = phi_mc(dotup / wnorm2);
+                phi = phi_of(c->limiter, dotup / wnorm2);
             } else {
                 phi = 1;
             }
@@ -403,7 +420,7 @@ static int check_desc(const oracle_desc* d)
         if (d->bc_lo[k] < 0 || d->bc_lo[k] > 2 || d->bc_hi[k] < 0 || d->bc_hi[k] > 2) return 1;
     }
     if (d->ndim == 2 && d->n[2] != 1) return 1;
-    if (d->limiter < 0 || d->limiter > 2) return 1;
+    if (d->limiter < 0 || d->limiter > 5) return 1;
     if (d->system == ORC_ACOUSTICS) {
         if (d->meqn != 1 + d->ndim) return 1;
         if (!d->has_aux && !(d->rho > 0 && d->bulk > 0)) return 1;

@@ -31,7 +31,8 @@ extern "C" {
 
 enum { ORC_ACOUSTICS = 0, ORC_SHALLOW_WATER = 1 };
 enum { ORC_BC_EXTRAP = 0, ORC_BC_WALL = 1, ORC_BC_PERIODIC = 2 };
-enum { ORC_LIM_MC = 0, ORC_LIM_NONE = 1 /* phi = 1: Lax-Wendroff */, ORC_FIRST_ORDER = 2 };
+enum { ORC_LIM_MC = 0, ORC_LIM_NONE = 1 /* phi = 1: Lax-Wendroff */, ORC_FIRST_ORDER = 2,
+       ORC_LIM_MINMOD = 3, ORC_LIM_SUPERBEE = 4, ORC_LIM_VANLEER = 5 };
 
 typedef struct {
     int ndim;            /* 2 or 3 */
@@ -61,6 +62,8 @@ int oracle_riemann_sw(const double* ql, const double* qr, double grav, int norma
 
 /* MC limiter function phi(theta). */
 double oracle_mc_phi(double theta);
+/* phi(theta) of a limiter (ORC_LIM_*); 1 for ORC_LIM_NONE, 0 for ORC_FIRST_ORDER. */
+double oracle_phi(int limiter, double theta);
 
 /* One directional sweep d (0 = x, 1 = y, 2 = z) with time step dt:
  * qout = sweep_d(q); *smax = largest |s| over the sweep's interfaces. */

@@ -115,6 +115,22 @@ def test_mc_limiter_table():
         assert oracle.mc_phi(theta) == phi
 
 
+@pytest.mark.parametrize("limiter,table", [
+    ("minmod", {-1: 0.0, 0: 0.0, 0.5: 0.5, 1: 1.0, 2: 1.0, 10: 1.0}),
+    ("superbee", {-1: 0.0, 0: 0.0, 0.25: 0.5, 0.5: 1.0, 1: 1.0, 1.5: 1.5, 2: 2.0, 10: 2.0}),
+    ("vanleer", {-1: 0.0, 0: 0.0, 0.5: 2 / 3, 1: 1.0, 2: 4 / 3, 3: 1.5, 10: 20 / 11}),
+    ("mc", {-1: 0.0, 0.5: 0.75, 3: 2.0}),
+    ("none", {-5: 1.0, 0: 1.0, 7: 1.0}),
+])
+def test_limiter_tables(limiter, table):
+    # the classical limiters, all symmetric (phi(theta)/theta = phi(1/theta)) and phi(1) = 1
+    for theta, phi in table.items():
+        assert oracle.phi(limiter, theta) == pytest.approx(phi, rel=1e-15)
+    if limiter != "none":
+        for theta in (0.3, 0.7, 2.5, 4.0):
+            assert oracle.phi(limiter, theta) / theta == pytest.approx(oracle.phi(limiter, 1 / theta), rel=1e-14)
+
+
 # ---------------------------------------------------------------------------
 # Single steps with closed forms on linear acoustics
 # ---------------------------------------------------------------------------
@@ -144,7 +160,14 @@ def _scalar_hr_step(w, nu, positive, limiter):
         up = np.roll(d_minus, 1, axis=-1) if positive else d_plus  # upwind jump of d_{i-1/2}
         with np.errstate(divide="ignore", invalid="ignore"):
             theta = np.where(d_minus != 0, up / np.where(d_minus != 0, d_minus, 1), 0)
-        phi_m = np.maximum(0, np.minimum(np.minimum((1 + theta) / 2, 2), 2 * theta))
+        if limiter == "mc":
+            phi_m = np.maximum(0, np.minimum(np.minimum((1 + theta) / 2, 2), 2 * theta))
+        elif limiter == "minmod":
+            phi_m = np.maximum(0, np.minimum(1, theta))
+        elif limiter == "superbee":
+            phi_m = np.maximum(0, np.maximum(np.minimum(1, 2 * theta), np.minimum(2, theta)))
+        else:  # van Leer
+            phi_m = (theta + np.abs(theta)) / (1 + np.abs(theta))
         phi_m = np.where(d_minus != 0, phi_m, 0)
     phi_p = np.roll(phi_m, -1, axis=-1)
     corr = 0.5 * nu * (1 - nu) * (phi_p * d_plus - phi_m * d_minus)
@@ -153,7 +176,7 @@ def _scalar_hr_step(w, nu, positive, limiter):
     return w + nu * d_plus - corr
 
 
-@pytest.mark.parametrize("limiter", ["first_order", "none", "mc"])
+@pytest.mark.parametrize("limiter", ["first_order", "none", "mc", "minmod", "superbee", "vanleer"])
 @pytest.mark.parametrize("direction", [0, 1])
 def test_single_sweep_matches_characteristic_closed_form(limiter, direction):
     rho, K = 1.0, 4.0
