@@ -315,6 +315,11 @@ def main():
         line["achievable_GBps"] = bw
         best_rw = max(bw["copy"], bw["copy_nt"])
         line["roofline"]["frac_of_achievable_copy"] = achieved / best_rw
+        # the same copy kernels at one sweep's size (one state read, one written),
+        # back to back like the sweeps: launch gaps and ramp included
+        bw_s = achievable_bandwidth(torch, claw, nbytes=alg_bytes // 2, reps=200)
+        line["achievable_GBps_sweep_size"] = bw_s
+        line["roofline"]["frac_of_copy_at_sweep_size"] = achieved / max(bw_s["copy"], bw_s["copy_nt"])
     if not args.no_cpu_baseline:
         print(f"# cpu baseline: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps)

@@ -71,7 +71,17 @@ typedef enum { CLAW_RP_ACOUSTICS = 0, CLAW_RP_SHALLOW_WATER = 1 } claw_riemann;
  * reflecting wall (normal velocity / momentum negated), periodic. */
 typedef enum { CLAW_BC_EXTRAP = 0, CLAW_BC_WALL = 1, CLAW_BC_PERIODIC = 2 } claw_bc;
 /* Wave limiter: MC; none (phi = 1, Lax-Wendroff); first order (no correction). */
-typedef enum { CLAW_LIM_MC = 0, CLAW_LIM_NONE = 1, CLAW_FIRST_ORDER = 2 } claw_limiter;
+/* Wave limiters phi(theta) of the high-resolution method (section 3): MC,
+ * none (phi = 1, Lax-Wendroff), first order (no correction), minmod, superbee,
+ * van Leer. */
+typedef enum {
+    CLAW_LIM_MC = 0,
+    CLAW_LIM_NONE = 1,
+    CLAW_FIRST_ORDER = 2,
+    CLAW_LIM_MINMOD = 3,
+    CLAW_LIM_SUPERBEE = 4,
+    CLAW_LIM_VANLEER = 5
+} claw_limiter;
 
 typedef struct {
     int32_t ndim;        /* 2 or 3 */

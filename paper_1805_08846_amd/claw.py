@@ -20,11 +20,12 @@ CLAW_OK, CLAW_E_INVALID, CLAW_E_UNSUPPORTED, CLAW_E_HIP, CLAW_E_CFL, CLAW_E_NONP
 CLAW_FP32, CLAW_FP64 = 0, 1
 CLAW_RP_ACOUSTICS, CLAW_RP_SHALLOW_WATER = 0, 1
 CLAW_BC_EXTRAP, CLAW_BC_WALL, CLAW_BC_PERIODIC = 0, 1, 2
-CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER = 0, 1, 2
+CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER, CLAW_LIM_MINMOD, CLAW_LIM_SUPERBEE, CLAW_LIM_VANLEER = range(6)
 CLAW_FLAG_FUSED_STEP = 1
 
 _BC = {"extrap": CLAW_BC_EXTRAP, "wall": CLAW_BC_WALL, "periodic": CLAW_BC_PERIODIC}
-_LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER}
+_LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER, "minmod": CLAW_LIM_MINMOD,
+        "superbee": CLAW_LIM_SUPERBEE, "vanleer": CLAW_LIM_VANLEER}
 
 EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
             "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",

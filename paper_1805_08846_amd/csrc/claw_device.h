@@ -26,7 +26,7 @@
 namespace claw {
 
 enum { BC_EXTRAP = 0, BC_WALL = 1, BC_PERIODIC = 2 };
-enum { LIM_MC = 0, LIM_NONE = 1, LIM_FIRST = 2 };
+enum { LIM_MC = 0, LIM_NONE = 1, LIM_FIRST = 2, LIM_MINMOD = 3, LIM_SUPERBEE = 4, LIM_VANLEER = 5 };
 // system kinds as compiled: constant-coefficient acoustics, acoustics with
 // per-cell coefficients, shallow water
 enum { SYS_AC = 0, SYS_ACV = 1, SYS_SW = 2 };
@@ -337,6 +337,28 @@ __device__ __forceinline__ R mc_limited(R alpha, R n_over_r2) {
     return sg * m;
 }
 
+// phi(theta) * alpha for the limiter `lim`, with a = |alpha| and b = theta |alpha|
+// (theta never formed): MC as above; minmod max(0, min(a, b)); superbee
+// max(0, min(a, 2b), min(2a, b)); van Leer (b + |b|) a / (a + |b|).
+template <typename R>
+__device__ __forceinline__ R wave_limited(R alpha, R n_over_r2, int lim) {
+    if (lim == LIM_MC) return mc_limited(alpha, n_over_r2);
+    const R sg = rsign1(alpha);
+    const R a = rabs(alpha);
+    const R b = sg * n_over_r2;
+    R m;
+    if (lim == LIM_MINMOD) {
+        m = rmax(R(0), rmin(a, b));
+    } else if (lim == LIM_SUPERBEE) {
+        m = rmax(R(0), rmax(rmin(a, b + b), rmin(a + a, b)));
+    } else {  // van Leer
+        const R ab = rabs(b);
+        const R den = a + ab;
+        m = den > R(0) ? (b + ab) * a * frcp(den) : R(0);
+    }
+    return sg * m;
+}
+
 // Output of one limited interface: contributions to its left and right cell
 // in the interface's normal frame.  Shallow water: (h, m_n, m_t); acoustics:
 // (p, u_n) in slots 0, 1.
@@ -373,9 +395,9 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_SW>& k, const Iface<R
     const R a2u = p2 ? km.alpha[1] : kp.alpha[1];
     const R n1 = a1u * (R(1) + s1u * k.s[0] + v1u * k.e0);
     const R n3 = a3u * (R(1) + s3u * k.s[2] + v3u * k.e0);
-    w[0] = mc_limited(k.alpha[0], n1 * ir1);
-    w[1] = mc_limited(k.alpha[1], a2u);
-    w[2] = mc_limited(k.alpha[2], n3 * ir3);
+    w[0] = wave_limited(k.alpha[0], n1 * ir1, limiter);
+    w[1] = wave_limited(k.alpha[1], a2u, limiter);
+    w[2] = wave_limited(k.alpha[2], n3 * ir3, limiter);
 }
 
 // Acoustics: wave 1 moves left (upwind neighbour k + 1), wave 2 right (k - 1).
@@ -388,8 +410,8 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_AC>& k, const Iface<R
         return;
     }
     // constant coefficients: r_p is the same at every interface
-    w[0] = mc_limited(k.alpha[0], kp.alpha[0]);
-    w[1] = mc_limited(k.alpha[1], km.alpha[1]);
+    w[0] = wave_limited(k.alpha[0], kp.alpha[0], limiter);
+    w[1] = wave_limited(k.alpha[1], km.alpha[1], limiter);
 }
 template <typename R>
 __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<R, SYS_ACV>& km,
@@ -405,8 +427,8 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<
     const R t = frcp(r1 * r2);
     const R n1 = kp.alpha[0] * (R(1) + kp.e0 * k.e0);
     const R n2 = km.alpha[1] * (R(1) + km.e1 * k.e1);
-    w[0] = mc_limited(k.alpha[0], n1 * (t * r2));
-    w[1] = mc_limited(k.alpha[1], n2 * (t * r1));
+    w[0] = wave_limited(k.alpha[0], n1 * (t * r2), limiter);
+    w[1] = wave_limited(k.alpha[1], n2 * (t * r1), limiter);
 }
 
 // Limits interface k and forms its contributions to the left cell

@@ -66,7 +66,7 @@ claw_status validate(const claw_desc* d) {
     if (d->num_ghost != 2) return fail(CLAW_E_INVALID, "num_ghost must be 2 (got %d)", d->num_ghost);
     if (d->flags & ~CLAW_FLAG_FUSED_STEP) return fail(CLAW_E_INVALID, "unknown flags 0x%x", (unsigned)d->flags);
     if (d->dtype != CLAW_FP32 && d->dtype != CLAW_FP64) return fail(CLAW_E_INVALID, "unknown dtype");
-    if (d->limiter < 0 || d->limiter > 2) return fail(CLAW_E_INVALID, "unknown limiter");
+    if (d->limiter < 0 || d->limiter > 5) return fail(CLAW_E_INVALID, "unknown limiter");
     if (!(d->cfl_desired > 0) || !(d->cfl_max >= d->cfl_desired))
         return fail(CLAW_E_INVALID, "need 0 < cfl_desired <= cfl_max");
     if (!(d->dt_max > 0)) return fail(CLAW_E_INVALID, "dt_max must be positive");
@@ -144,7 +144,7 @@ int col_chunk(int64_t m, int64_t nx, int64_t nlines_o) {
     // chunks long enough to keep the 3-interface halo small
     static const int64_t target_waves = [] {
         const char* e = getenv("CLAW_COL_WAVES");
-        return e ? (int64_t)atoll(e) : (int64_t)4096;
+        return e ? (int64_t)atoll(e) : (int64_t)2731;  // 24-row chunks at 2048^2 (measured best)
     }();
     static const int64_t forced = [] {
         const char* e = getenv("CLAW_COL_CHUNK");

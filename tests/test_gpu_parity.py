@@ -278,3 +278,39 @@ def test_run_to_run_determinism(claw):
         s.advance(30)
         outs.append(_host(q))
     assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# the other wave limiters (minmod, superbee, van Leer): whole adaptive runs
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("limiter", ["minmod", "superbee", "vanleer"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_limiters_shallow_water(claw, limiter, dtype):
+    prob, q0, _ = inputs.sw_radial_dam(n=160, dtype=dtype, nsteps=60, seed=6)
+    prob["limiter"] = limiter
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(60)
+    ref = oracle.advance(prob, q0, None, 60)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"sw 160^2 {limiter} {dtype}: rel {err:.2e}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("limiter", ["minmod", "superbee", "vanleer"])
+def test_limiters_acoustics(claw, limiter):
+    # constant coefficients in 2D, per-cell coefficients in 3D
+    prob, q0, _ = inputs.acoustics2d_pulse(n=96, nsteps=40)
+    prob["limiter"] = limiter
+    s, q = _solver(claw, prob, q0)
+    s.advance(40)
+    ref = oracle.advance(prob, q0, None, 40)
+    assert rel_linf(_host(q), ref["q"])[0] <= 1e-12
+    prob, q0, aux = inputs.acoustics3d_layers(n=40, dtype="f64", nsteps=15, seed=2)
+    prob["limiter"] = limiter
+    s, q = _solver(claw, prob, q0, aux)
+    s.advance(15)
+    ref = oracle.advance(prob, q0, aux, 15)
+    assert rel_linf(_host(q), ref["q"])[0] <= 1e-12
