@@ -46,6 +46,7 @@ class _Desc(ctypes.Structure):
         ("rho", ctypes.c_double),
         ("bulk", ctypes.c_double),
         ("grav", ctypes.c_double),
+        ("splitting", ctypes.c_int),
     ]
 
 
@@ -97,6 +98,7 @@ def make_desc(prob):
     d.meqn = int(prob["meqn"])
     d.system = _SYSTEM[prob["system"]]
     d.limiter = _LIM[prob.get("limiter", "mc")]
+    d.splitting = {"godunov": 0, "strang": 1}[prob.get("splitting", "godunov")]
     d.efix = 1 if prob.get("efix", True) else 0
     d.has_aux = 1 if prob.get("has_aux", False) else 0
     d.rho = float(prob.get("rho", 1.0))

@@ -421,6 +421,7 @@ static int check_desc(const oracle_desc* d)
     }
     if (d->ndim == 2 && d->n[2] != 1) return 1;
     if (d->limiter < 0 || d->limiter > 5) return 1;
+    if (d->splitting != ORC_GODUNOV && d->splitting != ORC_STRANG) return 1;
     if (d->system == ORC_ACOUSTICS) {
         if (d->meqn != 1 + d->ndim) return 1;
         if (!d->has_aux && !(d->rho > 0 && d->bulk > 0)) return 1;
@@ -568,21 +569,43 @@ int oracle_sweep(const oracle_desc* d, const double* q, const double* aux, int d
 /* One split step on real arrays.  The input q0 is left untouched (a rejected
  * step must keep Q^n); the sweeps alternate between the scratch arrays s1 and
  * s2 and *res points at the one holding the result. */
+/* One split step (section 3): Godunov splitting sweeps x, y (, z) with dt;
+ * Strang splitting sweeps x, y (, z) with dt/2 except the last direction,
+ * which takes dt, and then the half steps again in reverse order
+ * (x/2 y x/2 in 2D, x/2 y/2 z y/2 x/2 in 3D).  The Courant number is dt times
+ * the largest max|s|/dx over the directions. */
 static int step_real(const oracle_desc* d, const real* q0, real* s1, real* s2, const real* aux,
                      double dt, real** res, double* smax, double* cfl)
 {
-    int dir, rc;
+    int k, rc, nsw, seq[5];
+    double frac[5];
     const real* src = q0;
     real* dst = s1;
-    double sigma = 0;
-    for (dir = 0; dir < d->ndim; dir++) {
+    double sm_dir[3] = {0, 0, 0}, sigma = 0;
+    if (d->splitting == ORC_STRANG) {
+        nsw = 2 * d->ndim - 1;
+        for (k = 0; k < nsw; k++) {
+            seq[k] = k < d->ndim ? k : nsw - 1 - k;
+            frac[k] = seq[k] == d->ndim - 1 ? 1.0 : 0.5;
+        }
+    } else {
+        nsw = d->ndim;
+        for (k = 0; k < nsw; k++) {
+            seq[k] = k;
+            frac[k] = 1.0;
+        }
+    }
+    for (k = 0; k < nsw; k++) {
         real sm = 0;
-        rc = sweep_grid(d, src, aux, dir, dt, dst, &sm, 0);
+        rc = sweep_grid(d, src, aux, seq[k], frac[k] * dt, dst, &sm, 0);
         if (rc) return rc;
-        if (smax) smax[dir] = (double)sm;
-        if ((double)sm / cell_width(d, dir) > sigma) sigma = (double)sm / cell_width(d, dir);
+        if ((double)sm > sm_dir[seq[k]]) sm_dir[seq[k]] = (double)sm;
         src = dst;
         dst = dst == s1 ? s2 : s1;
+    }
+    for (k = 0; k < d->ndim; k++) {
+        if (smax) smax[k] = sm_dir[k];
+        if (sm_dir[k] / cell_width(d, k) > sigma) sigma = sm_dir[k] / cell_width(d, k);
     }
     *res = (real*)src;
     if (cfl) *cfl = dt * sigma;

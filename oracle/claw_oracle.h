@@ -48,7 +48,11 @@ typedef struct {
     int has_aux;         /* acoustics: 1 = per-cell rho, K in aux */
     double rho, bulk;    /* acoustics coefficients when has_aux == 0 */
     double grav;         /* shallow water gravity */
+    int splitting;       /* ORC_GODUNOV: x, y (, z) sweeps of dt; ORC_STRANG: half-step
+                            sweeps around a full step of the last direction */
 } oracle_desc;
+
+enum { ORC_GODUNOV = 0, ORC_STRANG = 1 };
 
 /* Single-interface Riemann solvers (section 3; section 4.2 point-wise form).
  * ql, qr: the meqn-vectors of the left and right cell.  normal: index of the
