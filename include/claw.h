@@ -51,6 +51,11 @@ typedef struct claw_solver claw_solver; /* opaque */
  * sweep kernel; same results to rounding, one read and one write of the state
  * per step.  Needs non-periodic y boundaries; ignored for other problems. */
 #define CLAW_FLAG_FUSED_STEP 1
+/* claw_desc.flags: CLAW_FLAG_STRANG replaces Godunov splitting (x, y (, z)
+ * sweeps of dt) by Strang splitting: sweeps of dt/2 around a full-dt sweep of
+ * the last direction (x/2 y x/2 in 2D, x/2 y/2 z y/2 x/2 in 3D), second order
+ * in time; the Courant number is still dt times the largest max|s|/dx. */
+#define CLAW_FLAG_STRANG 2
 
 typedef enum {
     CLAW_OK = 0,

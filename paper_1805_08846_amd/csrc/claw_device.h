@@ -65,6 +65,7 @@ struct alignas(256) Ctrl {
     int32_t pad;
     double dx[3];
     double inv_dx[3];   // 1 / dx_d, so a decision costs one division
+    double sweep_frac[3];  // fraction of dt each direction's sweeps take (Strang: 1/2 but the last)
     double cfl_desired, cfl_max, dt_max;
 };
 
@@ -337,12 +338,13 @@ __device__ __forceinline__ R mc_limited(R alpha, R n_over_r2) {
     return sg * m;
 }
 
-// phi(theta) * alpha for the limiter `lim`, with a = |alpha| and b = theta |alpha|
-// (theta never formed): MC as above; minmod max(0, min(a, b)); superbee
-// max(0, min(a, 2b), min(2a, b)); van Leer (b + |b|) a / (a + |b|).
+// phi(theta) * alpha for the other limiters, with a = |alpha| and b = theta |alpha|
+// (theta never formed): minmod max(0, min(a, b)); superbee
+// max(0, min(a, 2b), min(2a, b)); van Leer (b + |b|) a / (a + |b|).  The
+// limiter is uniform, so callers branch once per interface and MC keeps its
+// straight-line path.
 template <typename R>
 __device__ __forceinline__ R wave_limited(R alpha, R n_over_r2, int lim) {
-    if (lim == LIM_MC) return mc_limited(alpha, n_over_r2);
     const R sg = rsign1(alpha);
     const R a = rabs(alpha);
     const R b = sg * n_over_r2;
@@ -395,9 +397,15 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_SW>& k, const Iface<R
     const R a2u = p2 ? km.alpha[1] : kp.alpha[1];
     const R n1 = a1u * (R(1) + s1u * k.s[0] + v1u * k.e0);
     const R n3 = a3u * (R(1) + s3u * k.s[2] + v3u * k.e0);
-    w[0] = wave_limited(k.alpha[0], n1 * ir1, limiter);
-    w[1] = wave_limited(k.alpha[1], a2u, limiter);
-    w[2] = wave_limited(k.alpha[2], n3 * ir3, limiter);
+    if (limiter == LIM_MC) {
+        w[0] = mc_limited(k.alpha[0], n1 * ir1);
+        w[1] = mc_limited(k.alpha[1], a2u);
+        w[2] = mc_limited(k.alpha[2], n3 * ir3);
+    } else {
+        w[0] = wave_limited(k.alpha[0], n1 * ir1, limiter);
+        w[1] = wave_limited(k.alpha[1], a2u, limiter);
+        w[2] = wave_limited(k.alpha[2], n3 * ir3, limiter);
+    }
 }
 
 // Acoustics: wave 1 moves left (upwind neighbour k + 1), wave 2 right (k - 1).
@@ -410,8 +418,13 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_AC>& k, const Iface<R
         return;
     }
     // constant coefficients: r_p is the same at every interface
-    w[0] = wave_limited(k.alpha[0], kp.alpha[0], limiter);
-    w[1] = wave_limited(k.alpha[1], km.alpha[1], limiter);
+    if (limiter == LIM_MC) {
+        w[0] = mc_limited(k.alpha[0], kp.alpha[0]);
+        w[1] = mc_limited(k.alpha[1], km.alpha[1]);
+    } else {
+        w[0] = wave_limited(k.alpha[0], kp.alpha[0], limiter);
+        w[1] = wave_limited(k.alpha[1], km.alpha[1], limiter);
+    }
 }
 template <typename R>
 __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<R, SYS_ACV>& km,
@@ -427,8 +440,13 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<
     const R t = frcp(r1 * r2);
     const R n1 = kp.alpha[0] * (R(1) + kp.e0 * k.e0);
     const R n2 = km.alpha[1] * (R(1) + km.e1 * k.e1);
-    w[0] = wave_limited(k.alpha[0], n1 * (t * r2), limiter);
-    w[1] = wave_limited(k.alpha[1], n2 * (t * r1), limiter);
+    if (limiter == LIM_MC) {
+        w[0] = mc_limited(k.alpha[0], n1 * (t * r2));
+        w[1] = mc_limited(k.alpha[1], n2 * (t * r1));
+    } else {
+        w[0] = wave_limited(k.alpha[0], n1 * (t * r2), limiter);
+        w[1] = wave_limited(k.alpha[1], n2 * (t * r1), limiter);
+    }
 }
 
 // Limits interface k and forms its contributions to the left cell
@@ -559,7 +577,7 @@ enum { MODE_ADAPT = 0, MODE_STEP = 1, MODE_FIXED = 2 };
 __device__ __forceinline__ void set_trial_dt(const Ctrl* c, StepState& s, double dt) {
     s.dt = dt;
     for (int d = 0; d < 3; ++d) {
-        const double v = d < c->ndim ? dt * c->inv_dx[d] : 0.0;
+        const double v = d < c->ndim ? dt * c->inv_dx[d] * c->sweep_frac[d] : 0.0;
         s.dtdx[d] = v;
         s.dtdx_f[d] = (float)v;
     }

@@ -28,7 +28,7 @@ int fused_tile_rows();
 
 // One-thread step-control kernels on step-state copy q (see control.hip).
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired,
-                            double cfl_max, double dt_max, hipStream_t s);
+                            double cfl_max, double dt_max, bool strang, int result_off, hipStream_t s);
 hipError_t launch_commit(Ctrl* c, int q, bool fp32, hipStream_t s);
 hipError_t launch_begin(Ctrl* c, int q, double dt, int mode, int result_off, hipStream_t s);
 hipError_t launch_zero_speeds(Ctrl* c, int q, hipStream_t s);

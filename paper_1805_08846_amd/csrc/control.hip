@@ -14,7 +14,7 @@
 namespace claw {
 
 __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndim, double cfl_desired,
-                            double cfl_max, double dt_max) {
+                            double cfl_max, double dt_max, int strang, int result_off) {
     for (int q = 0; q < 2; ++q) {
         StepState& s = c->st[q];
         s.t = s.dt = s.dt_next = s.cfl = 0.0;
@@ -23,7 +23,7 @@ __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndi
             s.dtdx_f[d] = 0.0f;
         }
         s.cur = s.done = s.err = s.last_accepted = s.pending = s.mode = s.pad = 0;
-        s.result_off = ndim == 2 ? 2 : 1;
+        s.result_off = result_off;
         s.accepted = s.rejected = s.target = s.consecutive = s.trials = 0;
         for (int d = 0; d < 4; ++d) {
             c->smax32[q][d] = 0u;
@@ -38,6 +38,7 @@ __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndi
     c->inv_dx[0] = 1.0 / dx0;
     c->inv_dx[1] = 1.0 / dx1;
     c->inv_dx[2] = 1.0 / dx2;
+    for (int d = 0; d < 3; ++d) c->sweep_frac[d] = (strang && d < ndim - 1) ? 0.5 : 1.0;
     c->cfl_desired = cfl_desired;
     c->cfl_max = cfl_max;
     c->dt_max = dt_max;
@@ -134,9 +135,9 @@ __global__ void k_sync_state(const Ctrl* c, int q, R* b0, const R* b1, const R* 
 __global__ void k_reset_cur(Ctrl* c, int q) { c->st[q].cur = 0; }
 
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired, double cfl_max,
-                            double dt_max, hipStream_t s) {
+                            double dt_max, bool strang, int result_off, hipStream_t s) {
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, s, c, dx[0], dx[1], dx[2], ndim, cfl_desired,
-                       cfl_max, dt_max);
+                       cfl_max, dt_max, strang ? 1 : 0, result_off);
     return hipGetLastError();
 }
 hipError_t launch_commit(Ctrl* c, int q, bool fp32, hipStream_t s) {

@@ -64,7 +64,8 @@ claw_status validate(const claw_desc* d) {
     }
     if (d->ndim == 2 && d->n[2] != 1) return fail(CLAW_E_INVALID, "2D grids need n[2] = 1");
     if (d->num_ghost != 2) return fail(CLAW_E_INVALID, "num_ghost must be 2 (got %d)", d->num_ghost);
-    if (d->flags & ~CLAW_FLAG_FUSED_STEP) return fail(CLAW_E_INVALID, "unknown flags 0x%x", (unsigned)d->flags);
+    if (d->flags & ~(CLAW_FLAG_FUSED_STEP | CLAW_FLAG_STRANG))
+        return fail(CLAW_E_INVALID, "unknown flags 0x%x", (unsigned)d->flags);
     if (d->dtype != CLAW_FP32 && d->dtype != CLAW_FP64) return fail(CLAW_E_INVALID, "unknown dtype");
     if (d->limiter < 0 || d->limiter > 5) return fail(CLAW_E_INVALID, "unknown limiter");
     if (!(d->cfl_desired > 0) || !(d->cfl_max >= d->cfl_desired))
@@ -111,7 +112,8 @@ struct claw_solver {
     Plan plan;
     int sys;
     bool fp32;
-    bool fused;  // one fused kernel per 2D step (fused.hip) instead of an x and a y sweep
+    bool fused;   // one fused kernel per 2D step (fused.hip) instead of an x and a y sweep
+    bool strang;  // Strang splitting: half-step sweeps around a full step of the last direction
     hipStream_t stream;
     hipStream_t cap_stream;
     void* buf[3];
@@ -129,14 +131,6 @@ struct claw_solver {
 
 namespace {
 
-// Buffer offsets of the sweeps of one step (relative to the current buffer):
-// x: cur -> cur+1, y: cur+1 -> cur+2, z: cur+2 -> cur+1.  Q^n is never written.
-void step_offsets(int ndim, int dir, int* src_off, int* dst_off) {
-    if (dir == 0) { *src_off = 0; *dst_off = 1; }
-    else if (dir == 1) { *src_off = 1; *dst_off = 2; }
-    else { *src_off = 2; *dst_off = 1; }
-    (void)ndim;
-}
 int result_offset(int ndim) { return ndim == 2 ? 2 : 1; }
 
 int col_chunk(int64_t m, int64_t nx, int64_t nlines_o) {
@@ -227,8 +221,29 @@ hipError_t enqueue_sweep(claw_solver* h, int dir, int src_off, int dst_off, bool
 
 int committed(const claw_solver* h) { return h->parity ^ 1; }
 
+// Sweeps of one trial: direction, dt fraction implied by the control block,
+// source and destination buffer offsets (relative to the current buffer).
+// Offsets run 0 -> 1 -> 2 -> 1 -> 2 ..., so Q^n (offset 0) is never written;
+// Godunov 2D x: 0->1, y: 1->2; 3D adds z: 2->1; Strang 2D x/2: 0->1,
+// y: 1->2, x/2: 2->1.
+int trial_sweeps(const claw_solver* h, int* dirs, int* so, int* dof) {
+    const int nd = h->d.ndim;
+    const int k = h->strang ? 2 * nd - 1 : nd;
+    for (int i = 0; i < k; ++i) {
+        dirs[i] = i < nd ? i : k - 1 - i;
+        so[i] = i == 0 ? 0 : (i % 2 ? 1 : 2);
+        dof[i] = (i + 1) % 2 ? 1 : 2;
+    }
+    return k;
+}
+
 // Buffer offset of a step's result: the fused 2D step writes cur + 1.
-int result_offset_of(const claw_solver* h) { return h->fused ? 1 : result_offset(h->d.ndim); }
+int result_offset_of(const claw_solver* h) {
+    if (h->fused) return 1;
+    int dirs[5], so[5], dof[5];
+    const int k = trial_sweeps(h, dirs, so, dof);
+    return dof[k - 1];
+}
 
 template <typename R>
 FusedArgs<R> fused_args(const claw_solver* h, int parity) {
@@ -256,13 +271,13 @@ claw_status enqueue_trial(claw_solver* h, hipStream_t s, hipEvent_t* ev) {
         h->parity ^= 1;
         return CLAW_OK;
     }
-    for (int dir = 0; dir < h->d.ndim; ++dir) {
-        int so, dof;
-        step_offsets(h->d.ndim, dir, &so, &dof);
-        if (ev) HIP_TRY(hipEventRecord(ev[dir], s));
-        HIP_TRY(enqueue_sweep(h, dir, so, dof, false, h->parity, dir == 0, dir == h->d.ndim - 1, s));
+    int dirs[5], so[5], dof[5];
+    const int k = trial_sweeps(h, dirs, so, dof);
+    for (int i = 0; i < k; ++i) {
+        if (ev) HIP_TRY(hipEventRecord(ev[i], s));
+        HIP_TRY(enqueue_sweep(h, dirs[i], so[i], dof[i], false, h->parity, i == 0, i == k - 1, s));
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[h->d.ndim], s));
+    if (ev) HIP_TRY(hipEventRecord(ev[k], s));
     h->parity ^= 1;
     return CLAW_OK;
 }
@@ -413,7 +428,8 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
     h->plan = p;
     h->fp32 = d->dtype == CLAW_FP32;
     h->sys = d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC);
-    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && h->sys == SYS_SW && d->ndim == 2 &&
+    h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
+    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && !h->strang && h->sys == SYS_SW && d->ndim == 2 &&
                d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;
     h->stream = (hipStream_t)stream;
     char* ws = (char*)workspace;
@@ -429,7 +445,8 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
         delete h;
         return fail(CLAW_E_HIP, "stream create failed: %s", hipGetErrorString(e));
     }
-    e = launch_ctrl_init(h->ctrl, h->dx, d->ndim, d->cfl_desired, d->cfl_max, d->dt_max, h->stream);
+    e = launch_ctrl_init(h->ctrl, h->dx, d->ndim, d->cfl_desired, d->cfl_max, d->dt_max, h->strang,
+                         result_offset_of(h), h->stream);
     if (e == hipSuccess && d->maux) {
         if (h->fp32) e = launch_derive_zc<float>((const float*)aux, (float*)h->zc, p.ncell, h->stream);
         else e = launch_derive_zc<double>((const double*)aux, (double*)h->zc, p.ncell, h->stream);
@@ -600,7 +617,7 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
     if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
     double ms[4] = {0, 0, 0, 0};
     int64_t cnt[4] = {0, 0, 0, 0};
-    const int per = h->d.ndim + 1;
+    const int per = 2 * h->d.ndim;  // events per trial: one before each sweep and one after the last
     const int batch = 64;
     while ((int)h->events.size() < batch * per) {
         hipEvent_t e;
@@ -623,14 +640,16 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
             st = commit(h);
             if (st) return st;
             HIP_TRY(hipStreamSynchronize(h->stream));
-            const int nk = h->fused ? 1 : h->d.ndim;  // timed kernels per trial
+            int dirs[5], so[5], dof[5];
+            const int nk = h->fused ? 1 : trial_sweeps(h, dirs, so, dof);  // timed kernels per trial
             for (int64_t k = 0; k < n; ++k) {
                 hipEvent_t* ev = &h->events[k * per];
                 for (int j = 0; j < nk; ++j) {
                     float v = 0;
                     HIP_TRY(hipEventElapsedTime(&v, ev[j], ev[j + 1]));
-                    ms[j] += v;
-                    cnt[j] += 1;
+                    const int slot = h->fused ? 0 : dirs[j];
+                    ms[slot] += v;
+                    cnt[slot] += 1;
                 }
             }
             Ctrl c;
@@ -755,6 +774,7 @@ claw_status batch_validate(const claw_desc* d, int32_t count) {
         if (d[i].riemann != CLAW_RP_SHALLOW_WATER || d[i].ndim != 2)
             return fail(CLAW_E_UNSUPPORTED, "batches hold 2D shallow-water instances (instance %d)", i);
         if (d[i].dtype != d[0].dtype) return fail(CLAW_E_INVALID, "all instances need the same dtype");
+        if (d[i].flags) return fail(CLAW_E_UNSUPPORTED, "batches run the default split step (instance %d)", i);
     }
     return CLAW_OK;
 }
@@ -1059,7 +1079,8 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
     for (int i = 0; i < count; ++i) {
         double dx[3];
         for (int k = 0; k < 3; ++k) dx[k] = k < 2 ? (descs[i].upper[k] - descs[i].lower[k]) / (double)descs[i].n[k] : 1.0;
-        e = launch_ctrl_init(b->ctrl[i], dx, 2, descs[i].cfl_desired, descs[i].cfl_max, descs[i].dt_max, b->stream);
+        e = launch_ctrl_init(b->ctrl[i], dx, 2, descs[i].cfl_desired, descs[i].cfl_max, descs[i].dt_max, false,
+                             result_offset(2), b->stream);
         if (e != hipSuccess) return bail(fail(CLAW_E_HIP, "control init failed: %s", hipGetErrorString(e)));
     }
     e = hipMemcpyAsync(b->ctrl_ptrs, b->ctrl.data(), sizeof(Ctrl*) * count, hipMemcpyHostToDevice, b->stream);

@@ -314,3 +314,35 @@ def test_limiters_acoustics(claw, limiter):
     s.advance(15)
     ref = oracle.advance(prob, q0, aux, 15)
     assert rel_linf(_host(q), ref["q"])[0] <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Strang splitting (CLAW_FLAG_STRANG)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_strang_shallow_water_adaptive(claw, dtype):
+    prob, q0, _ = inputs.sw_radial_dam(n=150, dtype=dtype, nsteps=50, seed=7)
+    prob["splitting"] = "strang"
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(50)
+    ref = oracle.advance(prob, q0, None, 50)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"strang sw {dtype}: rel {err:.2e}")
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-6)
+    assert nrej == ref["nreject"]
+    ms, cnt = s.advance_timed(3)
+    assert cnt[0] == 2 * cnt[1] > 0  # two x half sweeps per y sweep
+
+
+def test_strang_acoustics3d_fixed_steps(claw):
+    prob, q0, aux = inputs.acoustics3d_layers(n=36, dtype="f64", nsteps=10, seed=3)
+    prob["splitting"] = "strang"
+    ref = oracle.advance(prob, q0, aux, 10)
+    dts = ref["dts"][ref["accepted"]]
+    s, q = _solver(claw, prob, q0, aux)
+    cfl = s.advance_fixed(dts)
+    qf, cfl_ref = oracle.advance_fixed(prob, q0, aux, dts)
+    assert rel_linf(_host(q), qf)[0] <= 1e-12
+    assert np.allclose(cfl, cfl_ref, rtol=1e-12)
