@@ -17,7 +17,7 @@ from . import build as _build
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
-_SYSTEM = {"acoustics": 0, "shallow_water": 1}
+_SYSTEM = {"acoustics": 0, "shallow_water": 1, "burgers": 2}
 _BC = {"extrap": 0, "wall": 1, "periodic": 2}
 _LIM = {"mc": 0, "none": 1, "first_order": 2, "minmod": 3, "superbee": 4, "vanleer": 5}
 
@@ -47,6 +47,7 @@ class _Desc(ctypes.Structure):
         ("bulk", ctypes.c_double),
         ("grav", ctypes.c_double),
         ("splitting", ctypes.c_int),
+        ("coef", ctypes.c_double * 3),
     ]
 
 
@@ -68,6 +69,7 @@ def _lib(precision="f64"):
             ctypes.c_int, ctypes.c_int, vp, vp, vp, vp]
         lib.oracle_riemann_sw.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                           vp, vp, vp, vp]
+        lib.oracle_riemann_burgers.argtypes = [ctypes.c_double] * 3 + [vp] * 4
         lib.oracle_sweep.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_double, vp, vp]
         lib.oracle_step.argtypes = [vp, vp, vp, ctypes.c_double, vp, vp, vp]
         lib.oracle_speeds.argtypes = [vp, vp, vp, vp]
@@ -104,6 +106,9 @@ def make_desc(prob):
     d.rho = float(prob.get("rho", 1.0))
     d.bulk = float(prob.get("bulk", 1.0))
     d.grav = float(prob.get("grav", 1.0))
+    coef = tuple(prob.get("coef", (1.0, 1.0, 1.0))) + (0.0,) * 3
+    for k in range(3):
+        d.coef[k] = float(coef[k])
     return d
 
 
@@ -166,6 +171,16 @@ def riemann_sw(ql, qr, grav, normal, efix=True, precision="f64"):
     if rc:
         raise OracleError(rc, "riemann_sw")
     return W, s, am, ap
+
+
+def riemann_burgers(ql, qr, coef, precision="f64"):
+    """Burgers-type Riemann problem with flux coef q^2/2: (W, s, amdq, apdq)."""
+    out = [np.zeros(1) for _ in range(4)]
+    rc = _lib(precision).oracle_riemann_burgers(float(ql), float(qr), float(coef),
+                                                *[_ptr(a) for a in out])
+    if rc:
+        raise OracleError(rc, "riemann_burgers")
+    return tuple(float(a[0]) for a in out)
 
 
 def sweep(prob, q, aux, direction, dt, precision="f64"):

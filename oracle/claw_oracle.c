@@ -177,6 +177,29 @@ static int rp_shallow_water(const real* ql, const real* qr, real g, int nrm, int
     return 0;
 }
 
+/* Scalar Burgers-type law with flux f(q) = c q^2 / 2 along the sweep: the
+ * wave is the jump qr - ql and its speed the Rankine-Hugoniot shock speed
+ * (f(qr) - f(ql)) / (qr - ql) = c (ql + qr) / 2 (LeVeque 2002, section 11.8
+ * and the Burgers solver of section 12.2).  Entropy fix: when the
+ * characteristic speeds c ql < 0 < c qr the exact solution is a transonic
+ * rarefaction whose flux at the interface is f(0) = 0, so A-dQ = f(0) - f(ql)
+ * and A+dQ = f(qr) - f(0); otherwise the whole jump moves to one side. */
+static int rp_burgers(real ql, real qr, real c, real W[MAXW][MAXEQ], real s[MAXW],
+                      real amdq[MAXEQ], real apdq[MAXEQ])
+{
+    if (!isfinite((double)ql) || !isfinite((double)qr)) return 5;
+    W[0][0] = qr - ql;
+    s[0] = c * (ql + qr) / 2;
+    if (c * ql < 0 && c * qr > 0) {
+        amdq[0] = -(c * ql * ql / 2);
+        apdq[0] = c * qr * qr / 2;
+    } else {
+        amdq[0] = rmin(s[0], 0) * W[0][0];
+        apdq[0] = rmax(s[0], 0) * W[0][0];
+    }
+    return 0;
+}
+
 /* MC limiter: phi(theta) = max(0, min((1 + theta) / 2, 2, 2 theta)). */
 static real phi_mc(real theta)
 {
@@ -250,13 +273,26 @@ int oracle_riemann_sw(const double* ql, const double* qr, double grav, int norma
     return 0;
 }
 
+int oracle_riemann_burgers(double ql, double qr, double c, double* W, double* s, double* amdq,
+                           double* apdq)
+{
+    real w[MAXW][MAXEQ], sp[MAXW], am[MAXEQ], ap[MAXEQ];
+    int rc = rp_burgers((real)ql, (real)qr, (real)c, w, sp, am, ap);
+    if (rc) return rc;
+    W[0] = w[0][0];
+    s[0] = sp[0];
+    amdq[0] = am[0];
+    apdq[0] = ap[0];
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One line of one sweep.                                                   */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
     int system, meqn, mwaves, nrm, limiter, efix, has_aux;
-    real g, dtdx, Z0, c0;
+    real g, dtdx, Z0, c0, coef;
 } line_cfg;
 
 typedef struct {
@@ -327,9 +363,13 @@ static int sweep_line(const line_cfg* c, long m, line_work* w, real* smax, int s
             real cr = c->has_aux ? w->cp[j] : c->c0;
             rp_acoustics(ql, qr, Zl, cl, Zr, cr, meqn, c->nrm, Wl, sl, w->amdq + j * MAXEQ,
                          w->apdq + j * MAXEQ);
-        } else {
+        } else if (c->system == ORC_SHALLOW_WATER) {
             int rc = rp_shallow_water(ql, qr, c->g, c->nrm, c->efix, Wl, sl,
                                       w->amdq + j * MAXEQ, w->apdq + j * MAXEQ);
+            if (rc) return rc;
+        } else {
+            int rc = rp_burgers(ql[0], qr[0], c->coef, Wl, sl, w->amdq + j * MAXEQ,
+                                w->apdq + j * MAXEQ);
             if (rc) return rc;
         }
         for (p = 0; p < mw; p++) {
@@ -427,6 +467,10 @@ static int check_desc(const oracle_desc* d)
         if (!d->has_aux && !(d->rho > 0 && d->bulk > 0)) return 1;
     } else if (d->system == ORC_SHALLOW_WATER) {
         if (d->ndim != 2 || d->meqn != 3 || !(d->grav > 0)) return 1;
+    } else if (d->system == ORC_BURGERS) {
+        if (d->meqn != 1) return 1;
+        for (k = 0; k < d->ndim; k++)
+            if (!isfinite(d->coef[k])) return 1;
     } else {
         return 1;
     }
@@ -454,8 +498,11 @@ static int sweep_grid(const oracle_desc* d, const real* q, const real* aux, int 
 
     cfg.system = d->system;
     cfg.meqn = meqn;
-    cfg.mwaves = d->system == ORC_ACOUSTICS ? 2 : 3;
-    cfg.nrm = 1 + dir;
+    cfg.mwaves = d->system == ORC_ACOUSTICS ? 2 : (d->system == ORC_SHALLOW_WATER ? 3 : 1);
+    /* the field that changes sign at a wall: the normal velocity / momentum;
+     * a scalar law has none (a wall mirrors it) */
+    cfg.nrm = d->system == ORC_BURGERS ? -1 : 1 + dir;
+    cfg.coef = d->system == ORC_BURGERS ? (real)d->coef[dir] : 0;
     cfg.limiter = d->limiter;
     cfg.efix = d->efix;
     cfg.has_aux = d->system == ORC_ACOUSTICS && d->has_aux;
@@ -493,7 +540,7 @@ static int sweep_grid(const oracle_desc* d, const real* q, const real* aux, int 
                 long idx = base + src * stride;
                 real* P = w.P + (j + NG) * MAXEQ;
                 for (e = 0; e < meqn; e++) P[e] = q[e * ncell + idx];
-                if (flip) P[cfg.nrm] = -P[cfg.nrm];
+                if (flip && cfg.nrm >= 0) P[cfg.nrm] = -P[cfg.nrm];
                 if (cfg.has_aux) {
                     real rho = aux[idx], K = aux[ncell + idx];
                     w.Zp[j + NG] = sqrt(rho * K);

@@ -6,7 +6,9 @@
  * (section 3: the Godunov-split update, equation LW-update; the Riemann solve
  * and the wave limiter described right after it; the CFL condition, equation
  * CFL-condition; the acoustics and shallow-water systems, equations
- * eq:acoustics and eq:SW; the revert-and-redo rule of section 4.1).  Where the
+ * eq:acoustics and eq:SW; the revert-and-redo rule of section 4.1), plus a
+ * scalar Burgers-type law as the example of a user-supplied point-wise
+ * Riemann solver (section 4.2).  Where the
  * paper leaves a formula unstated the textbook definition it cites for the
  * method (LeVeque, Finite Volume Methods for Hyperbolic Problems, 2002) is
  * written out instead; each such reading is named in the source.
@@ -29,7 +31,7 @@
 extern "C" {
 #endif
 
-enum { ORC_ACOUSTICS = 0, ORC_SHALLOW_WATER = 1 };
+enum { ORC_ACOUSTICS = 0, ORC_SHALLOW_WATER = 1, ORC_BURGERS = 2 };
 enum { ORC_BC_EXTRAP = 0, ORC_BC_WALL = 1, ORC_BC_PERIODIC = 2 };
 enum { ORC_LIM_MC = 0, ORC_LIM_NONE = 1 /* phi = 1: Lax-Wendroff */, ORC_FIRST_ORDER = 2,
        ORC_LIM_MINMOD = 3, ORC_LIM_SUPERBEE = 4, ORC_LIM_VANLEER = 5 };
@@ -39,8 +41,8 @@ typedef struct {
     long n[3];           /* cells per direction, n[2] = 1 in 2D */
     double lower[3];
     double upper[3];
-    int meqn;            /* acoustics: 1 + ndim; shallow water: 3 */
-    int system;          /* ORC_ACOUSTICS or ORC_SHALLOW_WATER */
+    int meqn;            /* acoustics: 1 + ndim; shallow water: 3; Burgers: 1 */
+    int system;          /* ORC_ACOUSTICS, ORC_SHALLOW_WATER or ORC_BURGERS */
     int limiter;         /* ORC_LIM_* */
     int efix;            /* shallow water: 1 = Harten-Hyman entropy fix */
     int bc_lo[3];
@@ -50,6 +52,7 @@ typedef struct {
     double grav;         /* shallow water gravity */
     int splitting;       /* ORC_GODUNOV: x, y (, z) sweeps of dt; ORC_STRANG: half-step
                             sweeps around a full step of the last direction */
+    double coef[3];      /* Burgers: flux coef[d] q^2 / 2 along direction d */
 } oracle_desc;
 
 enum { ORC_GODUNOV = 0, ORC_STRANG = 1 };
@@ -63,6 +66,13 @@ int oracle_riemann_acoustics(const double* ql, const double* qr, double Zl, doub
                              double* s, double* amdq, double* apdq);
 int oracle_riemann_sw(const double* ql, const double* qr, double grav, int normal,
                       int efix, double* W, double* s, double* amdq, double* apdq);
+
+/* Scalar Burgers-type law q_t + sum_d (coef_d q^2 / 2)_{x_d} = 0 along one
+ * direction with coefficient c: one wave qr - ql at the Rankine-Hugoniot speed
+ * c (ql + qr) / 2; a transonic rarefaction (c ql < 0 < c qr) splits its flux
+ * difference at q = 0.  Returns 5 for a non-finite state. */
+int oracle_riemann_burgers(double ql, double qr, double c, double* W, double* s, double* amdq,
+                           double* apdq);
 
 /* MC limiter function phi(theta). */
 double oracle_mc_phi(double theta);

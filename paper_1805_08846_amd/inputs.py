@@ -14,8 +14,13 @@ rounded values.
 The problem description is a dict:
 
     ndim, n (nx, ny, nz), lower, upper           grid (x fastest in memory)
-    system   "acoustics" | "shallow_water"
-    meqn     acoustics 1 + ndim (p, u, v[, w]); shallow water 3 (h, hu, hv)
+    system   "acoustics" | "shallow_water" | "burgers"
+    meqn     acoustics 1 + ndim (p, u, v[, w]); shallow water 3 (h, hu, hv);
+             Burgers 1
+    coef     Burgers: flux coefficient per direction (flux coef_d q^2 / 2)
+    solver   "builtin" (default) or "generic": the GPU library solves shallow
+             water through its point-wise plug-in interface instead of its
+             specialised sweep
     limiter  "mc" | "none" (phi = 1) | "first_order"
     efix     shallow water entropy fix on/off
     bc_lo, bc_hi   per direction "extrap" | "wall" | "periodic"
@@ -168,6 +173,43 @@ def sw_hump(n=1024, seed=0, dtype="f32", nsteps=500):
     return prob, round_to(q, dtype), None
 
 
+def burgers2d(n=1024, seed=0, dtype="f64", nsteps=200, coef=(1.0, 0.5), bc="periodic",
+              nbumps=4):
+    """2D scalar Burgers-type law q_t + (c_x q^2/2)_x + (c_y q^2/2)_y = 0 on
+    [0,1]^2, periodic, MC, CFL 0.9: q0 = 0.1 + sum of nbumps Gaussians
+    A exp(-r^2 / w^2) with A ~ U[-1, 1], centre ~ U[0.2, 0.8]^2,
+    w ~ U[0.05, 0.15], drawn from default_rng(seed) in that order per bump.
+    Signs of q change across the domain, so shocks, rarefactions and transonic
+    rarefactions all occur."""
+    prob = _base(2, (n, n), (0, 0), (1, 1), "burgers", 1, bc, coef=tuple(float(c) for c in coef)
+                 + (0.0,) * (3 - len(coef)), nsteps=nsteps, dtype=dtype, name="burgers2d", seed=seed)
+    rng = np.random.default_rng(seed)
+    x, y, _ = cell_centers(prob)
+    q = np.full((1,) + x.shape, 0.1)
+    for _ in range(nbumps):
+        a = rng.uniform(-1.0, 1.0)
+        c = rng.uniform(0.2, 0.8, size=2)
+        w = rng.uniform(0.05, 0.15)
+        q[0] += a * np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2) / w ** 2)
+    return prob, round_to(q, dtype), None
+
+
+def burgers3d(n=64, seed=0, dtype="f64", nsteps=50, coef=(1.0, 0.5, -0.75), bc="periodic"):
+    """The 3D analogue of burgers2d on [0,1]^3 with three signed bumps."""
+    prob = _base(3, (n, n, n), (0, 0, 0), (1, 1, 1), "burgers", 1, bc,
+                 coef=tuple(float(c) for c in coef), nsteps=nsteps, dtype=dtype, name="burgers3d",
+                 seed=seed)
+    rng = np.random.default_rng(seed)
+    x, y, z = cell_centers(prob)
+    q = np.full((1,) + x.shape, 0.1)
+    for _ in range(3):
+        a = rng.uniform(-1.0, 1.0)
+        c = rng.uniform(0.2, 0.8, size=3)
+        w = rng.uniform(0.08, 0.2)
+        q[0] += a * np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) / w ** 2)
+    return prob, round_to(q, dtype), None
+
+
 def lc_init_params(seed=0, hidden=64, nin=12, nout=3, out_gain=0.1):
     """Seeded initial parameters of the two correction networks (x faces,
     then y faces), each 12-64-64-3 and flat in the order W1 (64, 12), b1,
@@ -205,6 +247,8 @@ CONFIGS = {
     "acoustics2d_pulse": acoustics2d_pulse,
     "sw_radial_dam": sw_radial_dam,
     "acoustics3d_layers": acoustics3d_layers,
+    "burgers2d": burgers2d,
+    "burgers3d": burgers3d,
 }
 
 
