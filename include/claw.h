@@ -23,7 +23,7 @@
  *
  * Layouts (device memory, dtype per the descriptor):
  *   q   [meqn][nz][ny][nx], x fastest, no ghost cells.  Acoustics fields
- *       (p, u, v[, w]); shallow water (h, hu, hv).
+ *       (p, u, v[, w]); shallow water (h, hu, hv); Burgers (q).
  *   aux [2][nz][ny][nx]: density rho and bulk modulus K per cell (acoustics
  *       with variable coefficients, maux = 2); NULL when maux = 0.
  * q is rotation buffer 0.  Between calls the current state may live in a
@@ -70,8 +70,25 @@ typedef enum {
 typedef enum { CLAW_FP32 = 0, CLAW_FP64 = 1 } claw_dtype;
 /* Riemann solvers: linear acoustics (eq:acoustics, generalised to density
  * rho and bulk modulus K) and shallow water (eq:SW) with the Roe solver and
- * the Harten-Hyman entropy fix. */
-typedef enum { CLAW_RP_ACOUSTICS = 0, CLAW_RP_SHALLOW_WATER = 1 } claw_riemann;
+ * the Harten-Hyman entropy fix, both with specialised sweeps; and point-wise
+ * solvers compiled in through the plug-in interface (section 4.2: the user
+ * supplies the Riemann solver of one interface, the library runs it inside
+ * its generic sweeps), ids from CLAW_RP_PLUGIN_BASE on:
+ *   CLAW_RP_BURGERS              scalar q_t + sum_d (c_d q^2 / 2)_{x_d} = 0,
+ *                                meqn = mwaves = 1, 2D or 3D, c_d = param[d],
+ *                                transonic entropy fix;
+ *   CLAW_RP_SHALLOW_WATER_GENERIC  the shallow-water solver written as a
+ *                                plug-in (param[0] = g, param[1] != 0: entropy
+ *                                fix), same results to rounding as the
+ *                                specialised sweep.
+ * claw_plugin_info() describes a plug-in id. */
+typedef enum {
+    CLAW_RP_ACOUSTICS = 0,
+    CLAW_RP_SHALLOW_WATER = 1,
+    CLAW_RP_PLUGIN_BASE = 16,
+    CLAW_RP_BURGERS = 16,
+    CLAW_RP_SHALLOW_WATER_GENERIC = 17
+} claw_riemann;
 /* Ghost-cell rules (2 ghost cells per side): zero-order extrapolation,
  * reflecting wall (normal velocity / momentum negated), periodic. */
 typedef enum { CLAW_BC_EXTRAP = 0, CLAW_BC_WALL = 1, CLAW_BC_PERIODIC = 2 } claw_bc;
@@ -109,11 +126,20 @@ typedef struct {
     double cfl_desired;  /* target Courant number for the next step (0.9) */
     double cfl_max;      /* largest accepted Courant number (1.0) */
     double dt_max;       /* upper bound on dt (+inf for none) */
+    double param[4];     /* plug-in solvers: their parameters (see claw_riemann) */
 } claw_desc;
 
 /* Fills *d with defaults (MC limiter, entropy fix on, 2 ghosts, CFL 0.9 / 1.0,
  * dt_max = +inf); the caller then sets grid, system and boundary conditions. */
 void claw_desc_init(claw_desc* d);
+
+/* Plug-in solver id (claw_desc.riemann >= CLAW_RP_PLUGIN_BASE): its field
+ * and wave counts, the largest ndim it runs in, the first field of the vector
+ * that rotates with the sweep direction (-1 if none; a wall negates its normal
+ * component) and a static name.  Any output pointer may be NULL.
+ * CLAW_E_INVALID if id names no compiled plug-in. */
+claw_status claw_plugin_info(int32_t id, int32_t* meqn, int32_t* mwaves, int32_t* ndim_max,
+                             int32_t* vec_field, const char** name);
 
 /* Workspace size in bytes for descriptor d (two scratch state buffers, the
  * derived acoustic coefficients and the control block).  CLAW_E_INVALID for a

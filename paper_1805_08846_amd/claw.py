@@ -19,6 +19,8 @@ CLAW_OK, CLAW_E_INVALID, CLAW_E_UNSUPPORTED, CLAW_E_HIP, CLAW_E_CFL, CLAW_E_NONP
     CLAW_E_STATE = range(7)
 CLAW_FP32, CLAW_FP64 = 0, 1
 CLAW_RP_ACOUSTICS, CLAW_RP_SHALLOW_WATER = 0, 1
+CLAW_RP_PLUGIN_BASE = 16
+CLAW_RP_BURGERS, CLAW_RP_SHALLOW_WATER_GENERIC = 16, 17  # plug-in solvers
 CLAW_BC_EXTRAP, CLAW_BC_WALL, CLAW_BC_PERIODIC = 0, 1, 2
 CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER, CLAW_LIM_MINMOD, CLAW_LIM_SUPERBEE, CLAW_LIM_VANLEER = range(6)
 CLAW_FLAG_FUSED_STEP = 1
@@ -28,7 +30,7 @@ _BC = {"extrap": CLAW_BC_EXTRAP, "wall": CLAW_BC_WALL, "periodic": CLAW_BC_PERIO
 _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER, "minmod": CLAW_LIM_MINMOD,
         "superbee": CLAW_LIM_SUPERBEE, "vanleer": CLAW_LIM_VANLEER}
 
-EXPORTED = ["claw_desc_init", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
+EXPORTED = ["claw_desc_init", "claw_plugin_info", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
             "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
             "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
             "claw_batch_workspace_bytes", "claw_batch_create", "claw_batch_tune",
@@ -64,6 +66,7 @@ class claw_desc(ctypes.Structure):
         ("cfl_desired", ctypes.c_double),
         ("cfl_max", ctypes.c_double),
         ("dt_max", ctypes.c_double),
+        ("param", ctypes.c_double * 4),
     ]
 
 
@@ -100,6 +103,7 @@ def _load():
     P = ctypes.POINTER
     sig = {
         "claw_desc_init": (None, [P(claw_desc)]),
+        "claw_plugin_info": (i32, [i32, P(i32), P(i32), P(i32), P(i32), P(ctypes.c_char_p)]),
         "claw_workspace_bytes": (i32, [P(claw_desc), P(ctypes.c_size_t)]),
         "claw_create": (i32, [P(claw_desc), vp, vp, vp, ctypes.c_size_t, vp, P(vp)]),
         "claw_cfl": (i32, [vp, P(dbl), P(dbl)]),
@@ -162,6 +166,16 @@ def claw_desc_init():
     d = claw_desc()
     _lib.claw_desc_init(ctypes.byref(d))
     return d
+
+
+def claw_plugin_info(pid):
+    """dict(meqn, mwaves, ndim_max, vec_field, name) of a compiled plug-in solver."""
+    v = [ctypes.c_int32(0) for _ in range(4)]
+    name = ctypes.c_char_p()
+    _check(_lib.claw_plugin_info(int(pid), *[ctypes.byref(x) for x in v], ctypes.byref(name)),
+           "claw_plugin_info")
+    return {"meqn": v[0].value, "mwaves": v[1].value, "ndim_max": v[2].value,
+            "vec_field": v[3].value, "name": name.value.decode()}
 
 
 def claw_workspace_bytes(desc):
@@ -468,6 +482,19 @@ def desc_from_problem(prob):
         d.riemann = CLAW_RP_ACOUSTICS
         d.mwaves = 2
         d.maux = 2 if prob.get("has_aux", False) else 0
+    elif prob["system"] == "burgers":
+        d.riemann = CLAW_RP_BURGERS
+        d.mwaves = 1
+        d.maux = 0
+        coef = tuple(prob.get("coef", (1.0, 1.0, 1.0))) + (0.0,) * 4
+        for k in range(4):
+            d.param[k] = float(coef[k]) if k < 3 else 0.0
+    elif prob.get("solver", "builtin") == "generic":
+        d.riemann = CLAW_RP_SHALLOW_WATER_GENERIC
+        d.mwaves = 3
+        d.maux = 0
+        d.param[0] = float(prob.get("grav", 1.0))
+        d.param[1] = 1.0 if prob.get("efix", True) else 0.0
     else:
         d.riemann = CLAW_RP_SHALLOW_WATER
         d.mwaves = 3

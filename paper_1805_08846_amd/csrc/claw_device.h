@@ -28,8 +28,15 @@ namespace claw {
 enum { BC_EXTRAP = 0, BC_WALL = 1, BC_PERIODIC = 2 };
 enum { LIM_MC = 0, LIM_NONE = 1, LIM_FIRST = 2, LIM_MINMOD = 3, LIM_SUPERBEE = 4, LIM_VANLEER = 5 };
 // system kinds as compiled: constant-coefficient acoustics, acoustics with
-// per-cell coefficients, shallow water
-enum { SYS_AC = 0, SYS_ACV = 1, SYS_SW = 2 };
+// per-cell coefficients, shallow water; ids from SYS_PLUGIN up name
+// point-wise solvers of the plug-in interface (plugins.h)
+enum { SYS_AC = 0, SYS_ACV = 1, SYS_SW = 2, SYS_PLUGIN = 16 };
+constexpr bool is_plugin(int sys) { return sys >= SYS_PLUGIN; }
+// PluginOf<id>::type<R> is the plug-in class of id (specialised in plugins.h)
+template <int SYS>
+struct PluginOf;
+template <typename R, int SYS>
+using Plug = typename PluginOf<SYS>::template type<R>;
 
 // Step state a trial step runs with.  The control block keeps one copy per
 // trial parity: the first sweep of trial k decides trial k-1 from copy
@@ -97,6 +104,7 @@ struct SweepArgs {
     R grav;
     R sqrt_grav;
     R Z0, c0;           // constant-coefficient acoustics
+    R prm[4];           // plug-in solvers: the problem's parameters
 };
 
 // Rotation buffer i (0..2) chosen by selects rather than by indexing the
@@ -166,8 +174,11 @@ __device__ __forceinline__ int ghost_idx(int i, int m, int bc_lo, int bc_hi, boo
 // ---------------------------------------------------------------------------
 // Cells and interfaces
 // ---------------------------------------------------------------------------
+// Plug-in systems: the fields in the sweep's normal frame.
 template <typename R, int SYS>
-struct Cell;
+struct Cell {
+    R q[Plug<R, SYS>::MEQN];
+};
 
 // acoustics: pressure and normal velocity; tangential components are copied
 // through by the caller (a normal sweep never changes them)
@@ -209,14 +220,31 @@ struct Cell<R, SYS_SW> {
     }
 };
 
-template <typename R, int SYS>
-struct Iface {
-    static constexpr int MW = SYS == SYS_SW ? 3 : 2;
+// Built-in systems: the compact wave form above.
+template <typename R, int NW>
+struct CompactIface {
+    static constexpr int MW = NW;
     R alpha[MW];
     R s[MW];
     R am[MW];  // left-going speed share a_p
     R e0, e1;
 };
+// Plug-in systems: full waves, speeds and fluctuations as the solver returns them.
+template <typename R, int SYS>
+struct Iface {
+    static constexpr int MW = Plug<R, SYS>::MWAVES;
+    static constexpr int ME = Plug<R, SYS>::MEQN;
+    R W[MW][ME];
+    R s[MW];
+    R amdq[ME];
+    R apdq[ME];
+};
+template <typename R>
+struct Iface<R, SYS_AC> : CompactIface<R, 2> {};
+template <typename R>
+struct Iface<R, SYS_ACV> : CompactIface<R, 2> {};
+template <typename R>
+struct Iface<R, SYS_SW> : CompactIface<R, 3> {};
 
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_AC>& l, const Cell<R, SYS_AC>& r,
@@ -321,7 +349,14 @@ __device__ __forceinline__ R iface_smax(const Iface<R, SYS_SW>& k) {
 }
 template <typename R, int SYS>
 __device__ __forceinline__ R iface_smax(const Iface<R, SYS>& k) {
-    return rmax(rabs(k.s[0]), rabs(k.s[1]));
+    if constexpr (is_plugin(SYS)) {
+        R m = rabs(k.s[0]);
+#pragma unroll
+        for (int p = 1; p < Iface<R, SYS>::MW; ++p) m = rmax(m, rabs(k.s[p]));
+        return m;
+    } else {
+        return rmax(rabs(k.s[0]), rabs(k.s[1]));
+    }
 }
 
 // Limited wave strength phi(theta) * alpha of the MC limiter without forming
@@ -363,12 +398,69 @@ __device__ __forceinline__ R wave_limited(R alpha, R n_over_r2, int lim) {
 
 // Output of one limited interface: contributions to its left and right cell
 // in the interface's normal frame.  Shallow water: (h, m_n, m_t); acoustics:
-// (p, u_n) in slots 0, 1.
-template <typename R>
+// (p, u_n) in slots 0, 1; plug-ins: their MEQN fields.
+template <typename R, int N = 3>
 struct Contrib {
-    R L[3];
-    R Rr[3];
+    R L[N];
+    R Rr[N];
 };
+template <int SYS>
+constexpr int contrib_width() {
+    if constexpr (is_plugin(SYS)) return Plug<float, SYS>::MEQN;
+    else return 3;
+}
+
+// phi(theta) of a limiter for theta = n / d (d = |W|^2 > 0), the classical
+// forms (LeVeque 2002, section 6.12); used by plug-in systems, whose waves
+// are general vectors.
+template <typename R>
+__device__ __forceinline__ R phi_of_ratio(R n, R d, int lim) {
+    if (!(d > R(0))) return R(0);  // a wave of zero length has no correction
+    const R th = fdiv(n, d);
+    if (lim == LIM_MC) return rmax(R(0), rmin(R(0.5) * (R(1) + th), rmin(R(2), th + th)));
+    if (lim == LIM_MINMOD) return rmax(R(0), rmin(R(1), th));
+    if (lim == LIM_SUPERBEE) return rmax(R(0), rmax(rmin(R(1), th + th), rmin(R(2), th)));
+    if (lim == LIM_VANLEER) {
+        const R a = rabs(th);
+        return fdiv(th + a, R(1) + a);
+    }
+    return R(1);  // LIM_NONE
+}
+
+// Plug-in interface k with neighbours km, kp: L = A-dQ + F~, Rr = A+dQ - F~.
+template <typename R, int SYS, int N>
+__device__ __forceinline__ void plugin_contrib(const Iface<R, SYS>& k, const Iface<R, SYS>& km,
+                                               const Iface<R, SYS>& kp, R nu, int limiter,
+                                               Contrib<R, N>& out) {
+    constexpr int MW = Iface<R, SYS>::MW, ME = Iface<R, SYS>::ME;
+    static_assert(N == ME, "contribution width is the plug-in's field count");
+#pragma unroll
+    for (int i = 0; i < ME; ++i) {
+        out.L[i] = k.amdq[i];
+        out.Rr[i] = k.apdq[i];
+    }
+    if (limiter == LIM_FIRST) return;
+#pragma unroll
+    for (int p = 0; p < MW; ++p) {
+        const bool right = k.s[p] > R(0);  // upwind interface: k - 1 for s > 0, else k + 1
+        R d = R(0), n = R(0);
+#pragma unroll
+        for (int i = 0; i < ME; ++i) {
+            const R w = k.W[p][i];
+            d += w * w;
+            n += (right ? km.W[p][i] : kp.W[p][i]) * w;
+        }
+        const R phi = limiter == LIM_NONE ? R(1) : phi_of_ratio(n, d, limiter);
+        const R as = rabs(k.s[p]);
+        const R cw = R(0.5) * as * (R(1) - nu * as) * phi;
+#pragma unroll
+        for (int i = 0; i < ME; ++i) {
+            const R f = cw * k.W[p][i];
+            out.L[i] += f;
+            out.Rr[i] -= f;
+        }
+    }
+}
 
 // Limited strengths phi_p alpha_p of interface k given its neighbours km
 // (k - 1) and kp (k + 1).
@@ -451,10 +543,10 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<
 
 // Limits interface k and forms its contributions to the left cell
 // (A-dQ + F~) and the right cell (A+dQ - F~).  nu = dt / dx.
-template <typename R, int SYS>
-__device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Iface<R, SYS>& km,
-                                              const Iface<R, SYS>& kp, R nu, int limiter,
-                                              Contrib<R>& out) {
+template <typename R, int SYS, int N>
+__device__ __forceinline__ void compact_contrib(const Iface<R, SYS>& k, const Iface<R, SYS>& km,
+                                                const Iface<R, SYS>& kp, R nu, int limiter,
+                                                Contrib<R, N>& out) {
     constexpr int MW = Iface<R, SYS>::MW;
     R w[MW];
     if (limiter == LIM_FIRST) {
@@ -492,6 +584,14 @@ __device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Ifac
     }
 }
 
+template <typename R, int SYS, int N>
+__device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Iface<R, SYS>& km,
+                                              const Iface<R, SYS>& kp, R nu, int limiter,
+                                              Contrib<R, N>& out) {
+    if constexpr (is_plugin(SYS)) plugin_contrib(k, km, kp, nu, limiter, out);
+    else compact_contrib(k, km, kp, nu, limiter, out);
+}
+
 // ---------------------------------------------------------------------------
 // Wave-level helpers
 // ---------------------------------------------------------------------------
@@ -511,23 +611,41 @@ __device__ __forceinline__ double lane_next(double v) {
 // neighbour data a limiter needs: strengths, speeds and eigenvector numbers
 template <typename R, int SYS>
 __device__ __forceinline__ void iface_prev(const Iface<R, SYS>& in, Iface<R, SYS>& out) {
+    if constexpr (is_plugin(SYS)) {
 #pragma unroll
-    for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
-        out.alpha[p] = lane_prev(in.alpha[p]);
-        if constexpr (SYS == SYS_SW) out.s[p] = lane_prev(in.s[p]);
+        for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
+            out.s[p] = lane_prev(in.s[p]);
+#pragma unroll
+            for (int i = 0; i < Iface<R, SYS>::ME; ++i) out.W[p][i] = lane_prev(in.W[p][i]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
+            out.alpha[p] = lane_prev(in.alpha[p]);
+            if constexpr (SYS == SYS_SW) out.s[p] = lane_prev(in.s[p]);
+        }
+        if constexpr (SYS != SYS_AC) out.e0 = lane_prev(in.e0);
+        if constexpr (SYS == SYS_ACV) out.e1 = lane_prev(in.e1);
     }
-    if constexpr (SYS != SYS_AC) out.e0 = lane_prev(in.e0);
-    if constexpr (SYS == SYS_ACV) out.e1 = lane_prev(in.e1);
 }
 template <typename R, int SYS>
 __device__ __forceinline__ void iface_next(const Iface<R, SYS>& in, Iface<R, SYS>& out) {
+    if constexpr (is_plugin(SYS)) {
 #pragma unroll
-    for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
-        out.alpha[p] = lane_next(in.alpha[p]);
-        if constexpr (SYS == SYS_SW) out.s[p] = lane_next(in.s[p]);
+        for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
+            out.s[p] = lane_next(in.s[p]);
+#pragma unroll
+            for (int i = 0; i < Iface<R, SYS>::ME; ++i) out.W[p][i] = lane_next(in.W[p][i]);
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < Iface<R, SYS>::MW; ++p) {
+            out.alpha[p] = lane_next(in.alpha[p]);
+            if constexpr (SYS == SYS_SW) out.s[p] = lane_next(in.s[p]);
+        }
+        if constexpr (SYS != SYS_AC) out.e0 = lane_next(in.e0);
+        if constexpr (SYS == SYS_ACV) out.e1 = lane_next(in.e1);
     }
-    if constexpr (SYS != SYS_AC) out.e0 = lane_next(in.e0);
-    if constexpr (SYS == SYS_ACV) out.e1 = lane_next(in.e1);
 }
 
 template <typename R>
@@ -731,3 +849,5 @@ __device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v
 }
 
 }  // namespace claw
+
+#include "plugins.h"

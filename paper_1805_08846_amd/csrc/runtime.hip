@@ -86,6 +86,16 @@ claw_status validate(const claw_desc* d) {
         if (d->meqn != 3 || d->mwaves != 3) return fail(CLAW_E_INVALID, "shallow water has meqn = mwaves = 3");
         if (d->maux != 0) return fail(CLAW_E_INVALID, "shallow water takes no aux");
         if (!(d->grav > 0)) return fail(CLAW_E_INVALID, "grav must be positive");
+    } else if (d->riemann >= CLAW_RP_PLUGIN_BASE) {
+        int32_t meqn = 0, mwaves = 0, ndim_max = 0;
+        if (claw_plugin_info(d->riemann, &meqn, &mwaves, &ndim_max, nullptr, nullptr) != CLAW_OK)
+            return fail(CLAW_E_INVALID, "unknown Riemann solver %d", d->riemann);
+        if (d->meqn != meqn || d->mwaves != mwaves)
+            return fail(CLAW_E_INVALID, "plug-in %d has meqn = %d, mwaves = %d", d->riemann, meqn, mwaves);
+        if (d->ndim > ndim_max) return fail(CLAW_E_UNSUPPORTED, "plug-in %d runs up to %dD", d->riemann, ndim_max);
+        if (d->maux != 0) return fail(CLAW_E_INVALID, "plug-in solvers take no aux");
+        for (int k = 0; k < 4; ++k)
+            if (!isfinite(d->param[k])) return fail(CLAW_E_INVALID, "param[%d] is not finite", k);
     } else {
         return fail(CLAW_E_INVALID, "unknown Riemann solver %d", d->riemann);
     }
@@ -182,6 +192,7 @@ SweepArgs<R> grid_args(const claw_desc& d, int sys, int64_t ncell, void* const* 
         a.Z0 = (R)sqrt(d.rho * d.bulk);
         a.c0 = (R)sqrt(d.bulk / d.rho);
     }
+    for (int k = 0; k < 4; ++k) a.prm[k] = (R)d.param[k];
     if (dir == 0) {
         a.m = (int32_t)nx;
         a.stride = 1;
@@ -384,6 +395,22 @@ claw_status ensure_graph(claw_solver* h) {
 
 extern "C" {
 
+claw_status claw_plugin_info(int32_t id, int32_t* meqn, int32_t* mwaves, int32_t* ndim_max,
+                             int32_t* vec_field, const char** name) {
+#define CLAW_PLUGIN_INFO(pid, P)                             \
+    if (id == pid) {                                         \
+        if (meqn) *meqn = P<double>::MEQN;                   \
+        if (mwaves) *mwaves = P<double>::MWAVES;             \
+        if (ndim_max) *ndim_max = P<double>::NDIM_MAX;       \
+        if (vec_field) *vec_field = P<double>::VEC;          \
+        if (name) *name = P<double>::name();                 \
+        return CLAW_OK;                                      \
+    }
+    CLAW_PLUGINS(CLAW_PLUGIN_INFO)
+#undef CLAW_PLUGIN_INFO
+    return fail(CLAW_E_INVALID, "no plug-in solver with id %d", id);
+}
+
 void claw_desc_init(claw_desc* d) {
     if (!d) return;
     memset(d, 0, sizeof *d);
@@ -427,7 +454,8 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
     h->d = *d;
     h->plan = p;
     h->fp32 = d->dtype == CLAW_FP32;
-    h->sys = d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC);
+    h->sys = d->riemann >= CLAW_RP_PLUGIN_BASE ? d->riemann
+             : (d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC));
     h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
     h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && !h->strang && h->sys == SYS_SW && d->ndim == 2 &&
                d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;

@@ -38,10 +38,58 @@ struct VecOf {
     typedef R type __attribute__((ext_vector_type(CPL)));
 };
 
+// Field of a plug-in's state that holds frame component f (0 <= f < MEQN) in
+// the frame of direction dir: the vector's components are rotated so that
+// its normal component comes first.
+template <typename P>
+__device__ __forceinline__ constexpr int frame_field(int f, int dir) {
+    if constexpr (P::VEC < 0) {
+        return f;
+    } else {
+        return (f < P::VEC || f >= P::VEC + P::NVEC) ? f : P::VEC + (f - P::VEC + dir) % P::NVEC;
+    }
+}
+
+// Field negated in a wall ghost cell of direction dir (-1: none): the normal
+// velocity / momentum, which is field dir + 1 for the built-in systems.
+template <int SYS>
+__device__ __forceinline__ constexpr int wall_field(int dir) {
+    if constexpr (is_plugin(SYS)) {
+        using P = Plug<float, SYS>;
+        return P::VEC < 0 ? -1 : P::VEC + dir;
+    } else {
+        return dir + 1;
+    }
+}
+template <int SYS, typename R, int MEQN>
+__device__ __forceinline__ void wall_flip(R (&q)[MEQN], int dir) {
+    const int f = wall_field<SYS>(dir);
+#pragma unroll
+    for (int e = 0; e < MEQN; ++e)
+        if (e == f) q[e] = -q[e];
+}
+
+// Riemann problem between cells l and r of a sweep in direction DIR.
+template <typename R, int SYS, int DIR>
+__device__ __forceinline__ void solve_iface(const Cell<R, SYS>& l, const Cell<R, SYS>& r,
+                                            const SweepArgs<R>& a, R inv2Z, Iface<R, SYS>& o) {
+    if constexpr (is_plugin(SYS)) {
+        Plug<R, SYS>::template solve<DIR>(l.q, r.q, a.prm, o.W, o.s, o.amdq, o.apdq);
+    } else {
+        riemann(l, r, a.Z0, a.c0, inv2Z, a.grav, a.efix, o);
+    }
+}
+
+// nrm, tng: the normal and tangential fields of the sweep (nrm = dir + 1).
 template <typename R, int SYS, int MEQN>
 __device__ __forceinline__ void make_cell(const R (&q)[MEQN], const R (&zc)[2], int nrm, int tng,
                                           R sg, bool& bad, Cell<R, SYS>& c) {
-    if constexpr (SYS == SYS_SW) {
+    if constexpr (is_plugin(SYS)) {
+        using P = Plug<R, SYS>;
+#pragma unroll
+        for (int f = 0; f < MEQN; ++f) c.q[f] = q[frame_field<P>(f, nrm - 1)];
+        bad = bad || !P::admissible(c.q);
+    } else if constexpr (SYS == SYS_SW) {
         c.h = q[0];
         c.mn = q[nrm];
         c.mt = q[tng];
@@ -59,7 +107,10 @@ __device__ __forceinline__ void make_cell(const R (&q)[MEQN], const R (&zc)[2], 
 
 template <typename R, int SYS>
 __device__ __forceinline__ void cell_prev(const Cell<R, SYS>& in, Cell<R, SYS>& out) {
-    if constexpr (SYS == SYS_SW) {
+    if constexpr (is_plugin(SYS)) {
+#pragma unroll
+        for (int f = 0; f < Plug<R, SYS>::MEQN; ++f) out.q[f] = lane_prev(in.q[f]);
+    } else if constexpr (SYS == SYS_SW) {
         out.h = lane_prev(in.h);
         out.mn = lane_prev(in.mn);
         out.mt = lane_prev(in.mt);
@@ -79,12 +130,20 @@ __device__ __forceinline__ void cell_prev(const Cell<R, SYS>& in, Cell<R, SYS>& 
 }
 
 // Applies the two contributions to a cell's fields (normal frame -> fields).
-template <typename R, int SYS, int MEQN>
-__device__ __forceinline__ void apply_update(R (&q)[MEQN], const R (&Rl)[3], const R (&Lr)[3],
+template <typename R, int SYS, int MEQN, int NC>
+__device__ __forceinline__ void apply_update(R (&q)[MEQN], const R (&Rl)[NC], const R (&Lr)[NC],
                                              R nu, int nrm, int tng) {
-    q[0] = q[0] - nu * (Rl[0] + Lr[0]);
-    q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
-    if constexpr (SYS == SYS_SW) q[tng] = q[tng] - nu * (Rl[2] + Lr[2]);
+    if constexpr (is_plugin(SYS)) {
+#pragma unroll
+        for (int f = 0; f < MEQN; ++f) {
+            const int e = frame_field<Plug<R, SYS>>(f, nrm - 1);
+            q[e] = q[e] - nu * (Rl[f] + Lr[f]);
+        }
+    } else {
+        q[0] = q[0] - nu * (Rl[0] + Lr[0]);
+        q[nrm] = q[nrm] - nu * (Rl[1] + Lr[1]);
+        if constexpr (SYS == SYS_SW) q[tng] = q[tng] - nu * (Rl[2] + Lr[2]);
+    }
 }
 
 template <typename R, int SYS>
@@ -117,6 +176,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     const bool interior = vec_ok && xl >= 0 && xl + CPL <= nx;
     const R inv2Z = ac_inv2Z<R, SYS>(a);
     constexpr int nrm = 1, tng = 2;
+    constexpr int NC = contrib_width<SYS>();
 
     // load the lane's cells (ghost cells synthesised at the row ends)
     R q[CPL][MEQN];
@@ -144,7 +204,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
                 const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
 #pragma unroll
                 for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
-                if (flip) q[c][nrm] = -q[c][nrm];
+                if (flip) wall_flip<SYS>(q[c], 0);
                 if constexpr (SYS == SYS_ACV) {
                     zc[c][0] = a.zc[sidx];
                     zc[c][1] = a.zc[(size_t)a.ncell + sidx];
@@ -170,9 +230,9 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     C left;
     cell_prev(cell[CPL - 1], left);
     I f[CPL];
-    riemann(left, cell[0], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[0]);
+    solve_iface<R, SYS, 0>(left, cell[0], a, inv2Z, f[0]);
 #pragma unroll
-    for (int c = 1; c < CPL; ++c) riemann(cell[c - 1], cell[c], a.Z0, a.c0, inv2Z, a.grav, a.efix, f[c]);
+    for (int c = 1; c < CPL; ++c) solve_iface<R, SYS, 0>(cell[c - 1], cell[c], a, inv2Z, f[c]);
 
     // largest speed over the interfaces j = x, 0 <= j <= nx, owned by lanes 1..62
     // (and by lane 63 for j = nx when the row ends exactly at its first cell)
@@ -191,16 +251,16 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
         I fprev, fnext;
         iface_prev(f[CPL - 1], fprev);
         iface_next(f[0], fnext);
-        Contrib<R> k[CPL];
+        Contrib<R, NC> k[CPL];
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const I& km = c == 0 ? fprev : f[c - 1];
             const I& kp = c == CPL - 1 ? fnext : f[c + 1];
             limit_contrib(f[c], km, kp, nu, a.limiter, k[c]);
         }
-        R Lnext[3];
+        R Lnext[NC];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) Lnext[i] = lane_next(k[0].L[i]);
+        for (int i = 0; i < NC; ++i) Lnext[i] = lane_next(k[0].L[i]);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nu, nrm, tng);
@@ -247,7 +307,7 @@ __device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __r
     const unsigned off = (unsigned)(colbase + ghost_idx(y, a.m, a.bc_lo, a.bc_hi, flip) * a.stride);
 #pragma unroll
     for (int e = 0; e < MEQN; ++e) out.q[e] = src[(size_t)e * a.ncell + off];
-    if (flip) out.q[NRM] = -out.q[NRM];
+    if (flip) wall_flip<SYS>(out.q, NRM - 1);
     if constexpr (SYS == SYS_ACV) {
         out.zc[0] = zcg[off];
         out.zc[1] = zcg[(size_t)a.ncell + off];
@@ -263,6 +323,7 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     using CC = ColCell<R, SYS, MEQN>;
     constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
     constexpr int dir = NRM - 1;  // the normal component of direction d is q[d + 1]
+    constexpr int NC = contrib_width<SYS>();
     const Trial<R> tr = open_trial(a, dir, lead);
     if (tr.done && !SPEEDS) return;
     const R* __restrict__ src = pick_buf(a, (tr.cur + a.src_off) % 3);
@@ -285,7 +346,7 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     CC w0, w1;  // cells y and y+1 of the window
     C c1;
     I fb, fc;   // interfaces j = y and j = y + 1
-    R Rb[3];    // right-cell contribution of interface j = y
+    R Rb[NC];   // right-cell contribution of interface j = y
     {
         CC wm2, wm1;
         C cm2, cm1, c0;
@@ -298,15 +359,15 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
         make_cell<R, SYS, MEQN>(w0.q, w0.zc, NRM, TNG, a.sqrt_grav, bad, c0);
         make_cell<R, SYS, MEQN>(w1.q, w1.zc, NRM, TNG, a.sqrt_grav, bad, c1);
         I fa;
-        riemann(cm2, cm1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fa);
-        riemann(cm1, c0, a.Z0, a.c0, inv2Z, a.grav, a.efix, fb);
-        riemann(c0, c1, a.Z0, a.c0, inv2Z, a.grav, a.efix, fc);
+        solve_iface<R, SYS, dir>(cm2, cm1, a, inv2Z, fa);
+        solve_iface<R, SYS, dir>(cm1, c0, a, inv2Z, fb);
+        solve_iface<R, SYS, dir>(c0, c1, a, inv2Z, fc);
         if (y0 == 0) sm = iface_smax(fb);
         if constexpr (!SPEEDS) {
-            Contrib<R> kb;
+            Contrib<R, NC> kb;
             limit_contrib(fb, fa, fc, nu, a.limiter, kb);
 #pragma unroll
-            for (int i = 0; i < 3; ++i) Rb[i] = kb.Rr[i];
+            for (int i = 0; i < NC; ++i) Rb[i] = kb.Rr[i];
         }
     }
 
@@ -328,10 +389,10 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
         C c2;
         make_cell<R, SYS, MEQN>(w2.q, w2.zc, NRM, TNG, a.sqrt_grav, bad, c2);
         I fd;
-        riemann(c1, c2, a.Z0, a.c0, inv2Z, a.grav, a.efix, fd);
+        solve_iface<R, SYS, dir>(c1, c2, a, inv2Z, fd);
         sm = rmax(sm, iface_smax(fc));
         if constexpr (!SPEEDS) {
-            Contrib<R> kc;
+            Contrib<R, NC> kc;
             limit_contrib(fc, fb, fd, nu, a.limiter, kc);
             apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
             if (xin) {
@@ -340,7 +401,7 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
                 for (int e = 0; e < MEQN; ++e) dst[(size_t)e * a.ncell + off] = w0.q[e];
             }
 #pragma unroll
-            for (int i = 0; i < 3; ++i) Rb[i] = kc.Rr[i];
+            for (int i = 0; i < NC; ++i) Rb[i] = kc.Rr[i];
         }
         fb = fc;
         fc = fd;

@@ -42,11 +42,18 @@ static hipError_t launch_col(const SweepArgs<R>& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// whether a system has a z sweep: 3D acoustics, plug-ins that allow 3D
+template <typename R, int SYS, int MEQN>
+constexpr bool has_z() {
+    if constexpr (is_plugin(SYS)) return Plug<R, SYS>::NDIM_MAX == 3;
+    else return MEQN == 4;
+}
+
 template <typename R, int SYS, int MEQN, bool SPEEDS>
 static hipError_t launch_dir(const SweepArgs<R>& a, hipStream_t s) {
     if (a.dir == 0) return launch_row<R, SYS, MEQN, SPEEDS>(a, s);
     if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, SPEEDS>(a, s);
-    if constexpr (MEQN == 4) return launch_col<R, SYS, MEQN, 3, SPEEDS>(a, s);
+    if constexpr (has_z<R, SYS, MEQN>()) return launch_col<R, SYS, MEQN, 3, SPEEDS>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -62,6 +69,10 @@ hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds, h
     if (sys == SYS_AC && meqn == 4) return launch_kind<R, SYS_AC, 4>(a, speeds, s);
     if (sys == SYS_ACV && meqn == 3) return launch_kind<R, SYS_ACV, 3>(a, speeds, s);
     if (sys == SYS_ACV && meqn == 4) return launch_kind<R, SYS_ACV, 4>(a, speeds, s);
+#define CLAW_PLUGIN_LAUNCH(id, P) \
+    if (sys == id && meqn == P<R>::MEQN) return launch_kind<R, id, P<R>::MEQN>(a, speeds, s);
+    CLAW_PLUGINS(CLAW_PLUGIN_LAUNCH)
+#undef CLAW_PLUGIN_LAUNCH
     return hipErrorInvalidValue;
 }
 

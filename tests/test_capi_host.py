@@ -105,6 +105,48 @@ def test_bad_grid_and_bc(claw):
     assert e.value.status == claw.CLAW_E_UNSUPPORTED
 
 
+def _burgers_desc(claw, ndim=2):
+    from paper_1805_08846_amd import inputs
+    prob, _, _ = (inputs.burgers2d(n=32) if ndim == 2 else inputs.burgers3d(n=16))
+    return claw.desc_from_problem(prob)
+
+
+def test_plugin_descriptors(claw):
+    for ndim in (2, 3):
+        d = _burgers_desc(claw, ndim)
+        assert d.riemann == claw.CLAW_RP_BURGERS and d.meqn == d.mwaves == 1
+        # one field, two scratch buffers
+        assert claw.claw_workspace_bytes(d) >= 2 * d.n[0] * d.n[1] * d.n[2] * 8
+    for field, value in [("meqn", 3), ("mwaves", 2), ("maux", 2)]:
+        d = _burgers_desc(claw)
+        setattr(d, field, value)
+        with pytest.raises(claw.ClawError) as e:
+            claw.claw_workspace_bytes(d)
+        assert e.value.status == claw.CLAW_E_INVALID
+    d = _burgers_desc(claw)
+    d.param[1] = float("nan")
+    with pytest.raises(claw.ClawError):
+        claw.claw_workspace_bytes(d)
+    # the shallow-water plug-in runs in 2D only; unknown plug-in ids fail
+    d = _sw_desc(claw)
+    d.riemann = claw.CLAW_RP_SHALLOW_WATER_GENERIC
+    d.param[0] = 1.0
+    claw.claw_workspace_bytes(d)
+    d.ndim = 3
+    d.n[2] = 4
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    d = _sw_desc(claw)
+    d.riemann = 40
+    with pytest.raises(claw.ClawError):
+        claw.claw_workspace_bytes(d)
+    with pytest.raises(claw.ClawError):
+        claw.claw_plugin_info(40)
+    info = claw.claw_plugin_info(claw.CLAW_RP_BURGERS)
+    assert info == {"meqn": 1, "mwaves": 1, "ndim_max": 3, "vec_field": -1, "name": "burgers"}
+
+
 def test_create_rejects_null_buffers_before_touching_the_gpu(claw):
     d = _sw_desc(claw)
     h = ctypes.c_void_p(None)

@@ -1,0 +1,242 @@
+"""Parity of the plug-in solver path (generic sweep bodies running a
+point-wise Riemann solver) with the CPU oracle, through the C ABI.
+
+Two plug-ins are compiled in: the scalar Burgers-type law (one wave, no
+rotating vector, 2D and 3D) and shallow water written as a plug-in (three
+waves as full vectors, the momentum rotating with the sweep).  Tolerances as
+for the built-in systems: FP64 1e-12 and FP32 1e-5 relative L-infinity per
+field against the FP64 oracle; single sweeps 1e-13 / 2e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_08846_amd import inputs
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+TOL_SWEEP = {"f64": 1e-13, "f32": 2e-6}
+T_REL = {"f64": 1e-12, "f32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def claw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+def _solver(claw, prob, q0):
+    dt = torch.float64 if prob["dtype"] == "f64" else torch.float32
+    q = torch.tensor(np.ascontiguousarray(q0), dtype=dt, device="cuda").contiguous()
+    return claw.Solver(prob, q), q
+
+
+def _host(q):
+    torch.cuda.synchronize()
+    return q.double().cpu().numpy()
+
+
+def _burgers(n, dtype, coef=(0.8, -1.1), bc="periodic", **kw):
+    return inputs._base(len(n), n, (0,) * len(n), (1.0, 1.5, 0.7)[:len(n)], "burgers", 1, bc,
+                        coef=tuple(coef) + (0.0,) * (3 - len(coef)), dtype=dtype, **kw)
+
+
+def test_plugin_registry(claw):
+    b = claw.claw_plugin_info(claw.CLAW_RP_BURGERS)
+    assert (b["meqn"], b["mwaves"], b["ndim_max"], b["vec_field"]) == (1, 1, 3, -1)
+    g = claw.claw_plugin_info(claw.CLAW_RP_SHALLOW_WATER_GENERIC)
+    assert (g["meqn"], g["mwaves"], g["ndim_max"], g["vec_field"]) == (3, 3, 2, 1)
+
+
+# ---------------------------------------------------------------------------
+# single sweeps on random states, ragged sizes, every boundary rule
+# ---------------------------------------------------------------------------
+
+SIZES = [(3, 3), (1, 9), (9, 1), (127, 129), (300, 70), (70, 300), (251, 5)]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_burgers_single_sweep_random_states(claw, n, dtype, direction):
+    rng = np.random.default_rng(hash((n, dtype, direction, "burgers")) % 2 ** 32)
+    bcs = ["extrap", "wall", "periodic"]
+    prob = _burgers(n, dtype)
+    prob["bc_lo"] = tuple(rng.choice(bcs) for _ in range(3))
+    prob["bc_hi"] = tuple(rng.choice(bcs) for _ in range(3))
+    q0 = inputs.round_to(rng.uniform(-1, 1, (1, 1, n[1], n[0])), dtype)
+    dx = (prob["upper"][direction] - prob["lower"][direction]) / n[direction]
+    dt = 0.7 * dx / 1.1
+    s, q = _solver(claw, prob, q0)
+    sm = s.sweep(direction, dt)
+    s.sync_state()
+    ref, sm_ref = oracle.sweep(prob, q0, None, direction, dt)
+    err, per = rel_linf(_host(q), ref)
+    assert err <= TOL_SWEEP[dtype], per
+    assert sm == pytest.approx(sm_ref, rel=1e-14 if dtype == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("n", [(3, 3), (127, 129), (300, 70), (70, 300)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("direction", [0, 1])
+def test_generic_shallow_water_single_sweep_random_states(claw, n, dtype, direction):
+    rng = np.random.default_rng(hash((n, dtype, direction, "swg")) % 2 ** 32)
+    bcs = ["extrap", "wall", "periodic"]
+    prob = inputs._base(2, n, (0, 0), (1.0, 1.5), "shallow_water", 3, "extrap", dtype=dtype,
+                        grav=1.3, solver="generic")
+    prob["bc_lo"] = tuple(rng.choice(bcs) for _ in range(3))
+    prob["bc_hi"] = tuple(rng.choice(bcs) for _ in range(3))
+    q0 = inputs.random_states("shallow_water", n[0] * n[1], seed=4).T.reshape(3, 1, n[1], n[0])
+    q0 = inputs.round_to(q0, dtype)
+    dx = (prob["upper"][direction] - prob["lower"][direction]) / n[direction]
+    dt = 0.7 * dx / (0.5 + math.sqrt(1.3 * 2.0))
+    s, q = _solver(claw, prob, q0)
+    sm = s.sweep(direction, dt)
+    s.sync_state()
+    ref, sm_ref = oracle.sweep(prob, q0, None, direction, dt)
+    err, per = rel_linf(_host(q), ref)
+    assert err <= TOL_SWEEP[dtype], per
+    assert sm == pytest.approx(sm_ref, rel=1e-14 if dtype == "f64" else 1e-6)
+
+
+# ---------------------------------------------------------------------------
+# whole adaptive runs (step control, revert, CFL reduction on plug-in speeds)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_burgers2d_adaptive(claw, dtype):
+    prob, q0, _ = inputs.burgers2d(n=250, seed=3, dtype=dtype, nsteps=80)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(80)
+    ref = oracle.advance(prob, q0, None, 80)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers 250^2 {dtype}: rel {err:.2e} t {t} rej {nrej}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=T_REL[dtype])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_burgers3d_adaptive(claw, dtype):
+    prob, q0, _ = inputs.burgers3d(n=40, seed=2, dtype=dtype, nsteps=20)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(20)
+    ref = oracle.advance(prob, q0, None, 20)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers 40^3 {dtype}: rel {err:.2e}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=T_REL[dtype])
+
+
+def test_burgers3d_ragged_walls_fixed_steps(claw):
+    prob = _burgers((37, 29, 23), "f64", coef=(1.0, -0.6, 0.9), bc="wall")
+    prob["bc_hi"] = ("extrap", "periodic", "wall")
+    rng = np.random.default_rng(9)
+    q0 = rng.uniform(-1, 1, (1, 23, 29, 37))
+    sig = oracle.sigma(prob, q0, None)
+    dts = np.full(8, 0.6 / sig)
+    s, q = _solver(claw, prob, q0)
+    cfl = s.advance_fixed(dts)
+    qf, cfl_ref = oracle.advance_fixed(prob, q0, None, dts)
+    assert rel_linf(_host(q), qf)[0] <= TOL["f64"]
+    assert np.allclose(cfl, cfl_ref, rtol=1e-12)
+
+
+@pytest.mark.parametrize("limiter", ["mc", "none", "first_order", "minmod", "superbee", "vanleer"])
+def test_burgers_limiters(claw, limiter):
+    prob, q0, _ = inputs.burgers2d(n=140, seed=5, dtype="f64", nsteps=40)
+    prob["limiter"] = limiter
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(40)
+    ref = oracle.advance(prob, q0, None, 40)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers {limiter}: rel {err:.2e}")
+    assert err <= TOL["f64"]
+    assert nrej == ref["nreject"]
+
+
+@pytest.mark.parametrize("bc", ["wall", "extrap"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_burgers_boundaries_and_strang(claw, bc, dtype):
+    prob, q0, _ = inputs.burgers2d(n=180, seed=6, dtype=dtype, nsteps=50, bc=bc)
+    prob["splitting"] = "strang"
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(50)
+    ref = oracle.advance(prob, q0, None, 50)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers strang {bc} {dtype}: rel {err:.2e}")
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=T_REL[dtype])
+    ms, cnt = s.advance_timed(2)
+    assert cnt[0] == 2 * cnt[1] > 0
+
+
+def test_burgers_periodic_conservation_fp64(claw):
+    prob, q0, _ = inputs.burgers2d(n=256, seed=7, dtype="f64", nsteps=100)
+    s, q = _solver(claw, prob, q0)
+    s.advance(100)
+    out = _host(q)
+    assert abs(out.sum() - q0.sum()) <= 1e-11 * np.abs(q0).sum()
+
+
+def test_burgers_non_finite_state_reported(claw):
+    prob, q0, _ = inputs.burgers2d(n=64, seed=1, dtype="f64")
+    q0 = q0.copy()
+    q0[0, 0, 30, 17] = np.nan
+    s, q = _solver(claw, prob, q0)
+    with pytest.raises(claw.ClawError) as e:
+        s.advance(3, dt0=1e-3)
+    assert e.value.status == claw.CLAW_E_NONPHYSICAL
+    s.sync_state()
+    assert np.array_equal(_host(q), q0, equal_nan=True)
+
+
+def test_burgers_graph_path_equals_eager_path_bitwise(claw):
+    prob, q0, _ = inputs.burgers2d(n=150, seed=8, dtype="f32")
+    s1, q1 = _solver(claw, prob, q0)
+    s1.advance(60)
+    s2, q2 = _solver(claw, prob, q0)
+    s2.advance_timed(60)
+    assert np.array_equal(_host(q1), _host(q2))
+
+
+def test_burgers2d_1024_fp32_against_oracle(claw):
+    prob, q0, _ = inputs.burgers2d(n=1024, seed=0, dtype="f32", nsteps=20)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(20)
+    ref = oracle.advance(prob, q0, None, 20)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers 1024^2 fp32: rel {err:.2e}")
+    assert err <= TOL["f32"]
+    assert t == pytest.approx(ref["t"], rel=T_REL["f32"])
+
+
+# ---------------------------------------------------------------------------
+# shallow water through the plug-in path
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_generic_shallow_water_dam_break(claw, dtype):
+    prob, q0, _ = inputs.sw_radial_dam(n=200, dtype=dtype, nsteps=100, seed=5)
+    gen = dict(prob, solver="generic")
+    s, q = _solver(claw, gen, q0)
+    t, nrej = s.advance(100)
+    ref = oracle.advance(prob, q0, None, 100)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"generic sw 200^2 {dtype}: rel {err:.2e}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL[dtype]
+    assert t == pytest.approx(ref["t"], rel=T_REL[dtype])
+    # and the specialised sweep on the same input
+    sb, qb = _solver(claw, prob, q0)
+    sb.advance(100)
+    assert rel_linf(_host(q), _host(qb))[0] <= TOL[dtype]
