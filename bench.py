@@ -42,9 +42,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(path, kernel_class, source_hash):
-    """HBM bytes per launch of a kernel class from a committed rocprofv3 PMC
-    summary, or None if missing or taken on other kernel sources."""
+def load_pmc(path, kernel_class, quantity, source_hash):
+    """A per-launch figure (quantity: "hbm_bytes", "valu_insts") of a kernel
+    class from a committed rocprofv3 PMC summary, or None if missing or taken
+    on other kernel sources."""
     if not path or not os.path.exists(path):
         return None
     vals = {}
@@ -56,11 +57,21 @@ def load_traffic(path, kernel_class, source_hash):
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_source_hash") != source_hash:
         return None
-    key = f"{kernel_class}_hbm_bytes_per_launch"
+    key = f"{kernel_class}_{quantity}_per_launch"
     try:
         return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def load_traffic(path, kernel_class, source_hash):
+    """HBM bytes per launch of a kernel class (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    return load_pmc(path, kernel_class, "hbm_bytes", source_hash)
+
+
+# VALU issue peak of MI355X without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
+# per clock x 2.4 GHz (a wave64 instruction occupies a SIMD for 4 clocks).
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def cpu_baseline(prob, q0, steps):
@@ -204,6 +215,68 @@ def bench_learned(args, torch, claw, inputs):
     }
 
 
+def _timed_run(torch, claw, prob, q0, steps, warmup, timed_steps):
+    """Throughput (Gcell-updates/s) of claw_advance on one grid and per-kernel
+    average durations (us) from the event-timed path."""
+    ncell = prob["n"][0] * prob["n"][1] * prob["n"][2]
+    tdt = torch.float32 if prob["dtype"] == "f32" else torch.float64
+    q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
+    solver = claw.Solver(prob, q, None)
+    if warmup > 0:
+        solver.advance(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, nrej = solver.advance(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, cnt = solver.advance_timed(timed_steps)
+    avg_us = {n: (ms[k] / cnt[k] * 1e3 if cnt[k] else None)
+              for k, n in enumerate(["x_sweep", "y_sweep", "z_sweep", "control"])}
+    solver.close()
+    del q
+    return {"value": ncell * steps / elapsed / 1e9, "ms_per_step": elapsed / steps * 1e3,
+            "kernel_avg_us": avg_us, "rejected_trials": nrej}
+
+
+def bench_plugin(args, torch, claw, inputs):
+    """Point-wise solver plug-ins at 2048^2 FP32: the scalar Burgers-type law
+    (one field, one wave), and shallow water through the plug-in path next to
+    the specialised shallow-water sweep on the same dam break."""
+    n = args.n
+    steps, warmup = args.steps, args.warmup
+    prob, q0, _ = inputs.burgers2d(n=n, seed=0, dtype=args.dtype, nsteps=steps)
+    print(f"# burgers {n}^2 {args.dtype}", file=sys.stderr, flush=True)
+    bur = _timed_run(torch, claw, prob, q0, steps, warmup, args.timed_steps)
+    real_bytes = 4 if args.dtype == "f32" else 8
+    ncell = n * n
+    alg_bytes = 2 * 1 * real_bytes * ncell  # one field read and written per sweep
+    dom = max(("x_sweep", "y_sweep"), key=lambda k: bur["kernel_avg_us"][k])
+    achieved = alg_bytes / (bur["kernel_avg_us"][dom] * 1e-6) / 1e9
+    swp, swq0, _ = inputs.sw_radial_dam(n=n, dtype=args.dtype, nsteps=steps)
+    print(f"# shallow water {n}^2 {args.dtype}: specialised, then plug-in", file=sys.stderr, flush=True)
+    spec = _timed_run(torch, claw, swp, swq0, steps, warmup, args.timed_steps)
+    gen = _timed_run(torch, claw, dict(swp, solver="generic"), swq0, steps, warmup, args.timed_steps)
+    line = {
+        "metric": "Gcell-updates/s", "value": bur["value"], "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": bur["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic (seeded signed Gaussian bumps on 0.1; seeded radial dam break)",
+        "config": {"workload": "plug-in Riemann solvers: 2D Burgers-type law (c = (1, 0.5)), MC, "
+                               "periodic, CFL 0.9; shallow water as a plug-in vs specialised",
+                   "grid": [n, n], "cells": ncell, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": "burgers_" + dom,
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": bur["kernel_avg_us"][dom]},
+        "burgers": bur,
+        "shallow_water_specialised": spec,
+        "shallow_water_plugin": gen,
+        "plugin_over_specialised": gen["value"] / spec["value"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,7 +292,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
-    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned"])
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin"])
     ap.add_argument("--fused-step", action="store_true",
                     help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) instead of x and y sweeps")
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
@@ -245,6 +318,9 @@ def main():
         return
     if args.workload == "learned":
         print(json.dumps(bench_learned(args, torch, claw, inputs)), flush=True)
+        return
+    if args.workload == "plugin":
+        print(json.dumps(bench_plugin(args, torch, claw, inputs)), flush=True)
         return
 
     prob, q0, _ = inputs.sw_radial_dam(n=args.n, dtype=args.dtype, nsteps=args.steps)
@@ -279,8 +355,9 @@ def main():
     alg_bytes = 2 * 3 * real_bytes * ncell
     dom_s = ms[dom] / cnt[dom] * 1e-3
     achieved = alg_bytes / dom_s / 1e9
-    traffic = load_traffic(args.traffic_file or os.path.join(
-        ROOT, "profiles", f"pmc_sweeps_sw{args.n}_{args.dtype}.txt"), names[dom], kernel_source_hash())
+    pmc_file = args.traffic_file or os.path.join(ROOT, "profiles", f"pmc_sweeps_sw{args.n}_{args.dtype}.txt")
+    traffic = load_traffic(pmc_file, names[dom], kernel_source_hash())
+    valu = load_pmc(pmc_file, names[dom], "valu_insts", kernel_source_hash())
     print(f"# kernel averages (us): {avg_us}", file=sys.stderr, flush=True)
 
     line = {
@@ -304,6 +381,12 @@ def main():
                      "kernel": names[dom], "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": dom_s * 1e6},
         "kernel_avg_us": avg_us,
+        # the same kernel against the VALU issue rate: SQ_INSTS_VALU (wave
+        # instructions per launch, committed PMC summary) x 64 lanes over the
+        # live launch time
+        "valu_issue": None if valu is None else {
+            "wave_insts_per_launch": valu, "lane_ops_per_s": valu * 64 / dom_s,
+            "peak": VALU_LANE_OPS_PEAK, "frac": valu * 64 / dom_s / VALU_LANE_OPS_PEAK},
         "hbm_frac_whole_step": value * 1e9 * sum(1 for k in range(4) if cnt[k]) * alg_bytes / ncell /
         (HBM_PEAK_GBPS * 1e9),
         "rejected_trials": nrej,

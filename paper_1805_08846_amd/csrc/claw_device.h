@@ -597,8 +597,8 @@ __device__ __forceinline__ void limit_contrib(const Iface<R, SYS>& k, const Ifac
 // ---------------------------------------------------------------------------
 // DPP wave shifts: lane_prev gives lane i the value of lane i - 1, lane_next
 // the value of lane i + 1 (lane 0 / lane 63 receive 0).
-__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shr1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_shl1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, true); }
 __device__ __forceinline__ float lane_prev(float v) { return __int_as_float(dpp_shr1(__float_as_int(v))); }
 __device__ __forceinline__ float lane_next(float v) { return __int_as_float(dpp_shl1(__float_as_int(v))); }
 __device__ __forceinline__ double lane_prev(double v) {
