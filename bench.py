@@ -277,6 +277,41 @@ def bench_plugin(args, torch, claw, inputs):
     return line
 
 
+def bench_dpsp(args, torch, claw, inputs):
+    """Double and single precision at 1024^2 (the radial dam break): the GPU
+    path against the oracle on the host cores, each precision (the oracle's
+    FP32 instantiation is the same source with real = float)."""
+    import oracle
+    n = 1024
+    steps = args.steps if args.steps_given else 500
+    warmup = args.warmup if args.warmup_given else 1500
+    out = {}
+    for dt in ("f64", "f32"):
+        prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=dt, nsteps=steps)
+        print(f"# dpsp {n}^2 {dt}: gpu", file=sys.stderr, flush=True)
+        g = _timed_run(torch, claw, prob, q0, steps, warmup, args.timed_steps)
+        print(f"# dpsp {n}^2 {dt}: oracle {args.cpu_steps} steps", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        oracle.advance(prob, q0, None, args.cpu_steps, precision=dt)
+        el = time.perf_counter() - t0
+        cpu = n * n * args.cpu_steps / el / 1e9
+        out[dt] = {"gpu_Gcell_per_s": g["value"], "gpu_kernel_avg_us": g["kernel_avg_us"],
+                   "oracle_Gcell_per_s": cpu, "oracle_seconds": el, "gpu_over_oracle": g["value"] / cpu}
+    return {
+        "metric": "GPU over CPU oracle, FP64 and FP32 (1024^2 shallow water)",
+        "value": out["f64"]["gpu_over_oracle"], "unit": "x (FP64)", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 and f32",
+        "data": "synthetic (seeded radial dam break + U(-1e-3,1e-3) noise on h)",
+        "config": {"workload": "2D shallow water radial dam break at 1024^2, walls, MC, CFL 0.9",
+                   "grid": [n, n], "parallelism": "single GPU; oracle on the host cores"},
+        "results": out,
+        "fp32_over_fp64_gpu": out["f32"]["gpu_Gcell_per_s"] / out["f64"]["gpu_Gcell_per_s"],
+        "cpu_cores": oracle.num_threads(),
+        "cpu_sample": f"first {args.cpu_steps} adaptive steps of each precision",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -292,7 +327,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
-    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin"])
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp"])
     ap.add_argument("--fused-step", action="store_true",
                     help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) instead of x and y sweeps")
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
@@ -321,6 +356,9 @@ def main():
         return
     if args.workload == "plugin":
         print(json.dumps(bench_plugin(args, torch, claw, inputs)), flush=True)
+        return
+    if args.workload == "dpsp":
+        print(json.dumps(bench_dpsp(args, torch, claw, inputs)), flush=True)
         return
 
     prob, q0, _ = inputs.sw_radial_dam(n=args.n, dtype=args.dtype, nsteps=args.steps)

@@ -220,6 +220,20 @@ def test_burgers2d_1024_fp32_against_oracle(claw):
     assert t == pytest.approx(ref["t"], rel=T_REL["f32"])
 
 
+def test_burgers2d_2048_fp32_bench_configuration(claw):
+    # the plug-in bench's workload (burgers2d(n=2048, seed=0), FP32, adaptive
+    # graph path) against the oracle after 40 accepted steps
+    prob, q0, _ = inputs.burgers2d(n=2048, seed=0, dtype="f32", nsteps=40)
+    s, q = _solver(claw, prob, q0)
+    t, nrej = s.advance(40)
+    ref = oracle.advance(prob, q0, None, 40)
+    err, per = rel_linf(_host(q), ref["q"])
+    print(f"burgers 2048^2 fp32: rel {err:.2e}")
+    assert nrej == ref["nreject"]
+    assert err <= TOL["f32"]
+    assert t == pytest.approx(ref["t"], rel=T_REL["f32"])
+
+
 # ---------------------------------------------------------------------------
 # shallow water through the plug-in path
 # ---------------------------------------------------------------------------
