@@ -10,7 +10,7 @@
 
 namespace claw {
 
-template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK>
 __global__ __launch_bounds__(256) void k_batch_row(BatchLaunch<R> L) {
     const BatchBlock bb = L.blocks[blockIdx.x];
     SweepArgs<R> a = L.args[bb.inst * 2 + 0];
@@ -18,10 +18,10 @@ __global__ __launch_bounds__(256) void k_batch_row(BatchLaunch<R> L) {
     a.parity = L.parity;
     a.first = L.first;
     a.last = L.last;
-    row_body<R, SYS, MEQN, CPL, SPEEDS>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
+    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
 }
 
-template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS, int LIMK>
 __global__ __launch_bounds__(256) void k_batch_col(BatchLaunch<R> L) {
     const BatchBlock bb = L.blocks[blockIdx.x];
     SweepArgs<R> a = L.args[bb.inst * 2 + 1];
@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_batch_col(BatchLaunch<R> L) {
     a.parity = L.parity;
     a.first = L.first;
     a.last = L.last;
-    col_body<R, SYS, MEQN, NRM, PF, SPEEDS>(a, bb.x, bb.y, bb.z, bb.x == 0 && bb.y == 0 && bb.z == 0);
+    col_body<R, SYS, MEQN, NRM, PF, SPEEDS, LIMK>(a, bb.x, bb.y, bb.z, bb.x == 0 && bb.y == 0 && bb.z == 0);
 }
 
 // One thread per instance: step-state operations on copy q of every control block.
@@ -95,24 +95,26 @@ __global__ void k_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, doubl
     }
 }
 
-template <typename R, int SYS, int MEQN, bool SPEEDS>
+template <typename R, int SYS, int MEQN, bool SPEEDS, int LIMK>
 static hipError_t launch_batch_kind(const BatchLaunch<R>& L, int dir, int nblocks, hipStream_t s) {
     if (nblocks <= 0) return hipSuccess;
     if (dir == 0) {
         constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
-        hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS>), dim3(nblocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS, LIMK>), dim3(nblocks), dim3(256), 0, s, L);
     } else {
-        hipLaunchKernelGGL((k_batch_col<R, SYS, MEQN, 2, 4, SPEEDS>), dim3(nblocks), dim3(256), 0, s, L);
+        hipLaunchKernelGGL((k_batch_col<R, SYS, MEQN, 2, 4, SPEEDS, LIMK>), dim3(nblocks), dim3(256), 0, s, L);
     }
     return hipGetLastError();
 }
 
+// MC across the whole batch runs the kernels specialised for it.
 template <typename R>
 hipError_t launch_batch_sweep(const BatchLaunch<R>& L, int sys, int dir, int nblocks, bool speeds,
                               hipStream_t s) {
     if (sys != SYS_SW) return hipErrorInvalidValue;
-    return speeds ? launch_batch_kind<R, SYS_SW, 3, true>(L, dir, nblocks, s)
-                  : launch_batch_kind<R, SYS_SW, 3, false>(L, dir, nblocks, s);
+    if (speeds) return launch_batch_kind<R, SYS_SW, 3, true, LIM_RUNTIME>(L, dir, nblocks, s);
+    if (L.limiter == LIM_MC) return launch_batch_kind<R, SYS_SW, 3, false, LIM_MC>(L, dir, nblocks, s);
+    return launch_batch_kind<R, SYS_SW, 3, false, LIM_RUNTIME>(L, dir, nblocks, s);
 }
 
 hipError_t launch_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, double dt, int mode,

@@ -46,7 +46,8 @@ template <typename R>
 struct BatchLaunch {
     const BatchBlock* blocks;
     const SweepArgs<R>* args;
-    int parity, first, last, pad;
+    int parity, first, last;
+    int limiter;  // the limiter every instance uses, or -1 if they differ
 };
 enum { BOP_COMMIT = 0, BOP_ZERO_SPEEDS = 1, BOP_BEGIN_FIXED = 2, BOP_BEGIN_ADAPT = 3 };
 template <typename R>

@@ -932,7 +932,9 @@ hipError_t batch_sweep(claw_batch* b, int dir, bool speeds, int parity, bool fir
     L.parity = parity;
     L.first = first ? 1 : 0;
     L.last = last ? 1 : 0;
-    L.pad = 0;
+    L.limiter = b->d[0].limiter;
+    for (const claw_desc& d : b->d)
+        if (d.limiter != L.limiter) L.limiter = -1;
     return launch_batch_sweep<R>(L, SYS_SW, dir, dir == 0 ? b->n_row_blocks : b->n_col_blocks, speeds, s);
 }
 

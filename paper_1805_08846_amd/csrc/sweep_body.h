@@ -146,6 +146,16 @@ __device__ __forceinline__ void apply_update(R (&q)[MEQN], const R (&Rl)[NC], co
     }
 }
 
+// Limiter of a sweep: fixed at compile time (LIMK >= 0: the kernel is
+// specialised for it and every limiter branch folds) or read from the
+// arguments (LIM_RUNTIME).
+enum { LIM_RUNTIME = -1 };
+template <int LIMK, typename R>
+__device__ __forceinline__ int limiter_of(const SweepArgs<R>& a) {
+    if constexpr (LIMK >= 0) return LIMK;
+    else return a.limiter;
+}
+
 template <typename R, int SYS>
 __device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
     if constexpr (SYS == SYS_AC) return frcp(a.Z0 + a.Z0);
@@ -156,7 +166,7 @@ __device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
 // Row kernel: x sweep
 // ---------------------------------------------------------------------------
 // bx: segment of the row; by: group of four rows; lead: block (0, 0, 0).
-template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK = LIM_RUNTIME>
 __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, bool lead) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
@@ -256,7 +266,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
         for (int c = 0; c < CPL; ++c) {
             const I& km = c == 0 ? fprev : f[c - 1];
             const I& kp = c == CPL - 1 ? fnext : f[c + 1];
-            limit_contrib(f[c], km, kp, nu, a.limiter, k[c]);
+            limit_contrib(f[c], km, kp, nu, limiter_of<LIMK>(a), k[c]);
         }
         R Lnext[NC];
 #pragma unroll
@@ -316,7 +326,7 @@ __device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __r
 
 // bx: group of four 64-column strips; by: chunk along the sweep; bz: outer
 // plane; lead: block (0, 0, 0).
-template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS, int LIMK = LIM_RUNTIME>
 __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, int bz, bool lead) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
@@ -365,7 +375,7 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
         if (y0 == 0) sm = iface_smax(fb);
         if constexpr (!SPEEDS) {
             Contrib<R, NC> kb;
-            limit_contrib(fb, fa, fc, nu, a.limiter, kb);
+            limit_contrib(fb, fa, fc, nu, limiter_of<LIMK>(a), kb);
 #pragma unroll
             for (int i = 0; i < NC; ++i) Rb[i] = kb.Rr[i];
         }
@@ -393,7 +403,7 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
         sm = rmax(sm, iface_smax(fc));
         if constexpr (!SPEEDS) {
             Contrib<R, NC> kc;
-            limit_contrib(fc, fb, fd, nu, a.limiter, kc);
+            limit_contrib(fc, fb, fd, nu, limiter_of<LIMK>(a), kc);
             apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
             if (xin) {
                 const unsigned off = (unsigned)(colbase + yy * a.stride);

@@ -5,17 +5,18 @@
 
 namespace claw {
 
-template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS>
+// LIMK: limiter fixed at compile time (the MC kernels) or LIM_RUNTIME
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK>
 __global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
     const int by = (int)(blockIdx.y + blockIdx.z * gridDim.y);
-    row_body<R, SYS, MEQN, CPL, SPEEDS>(a, (int)blockIdx.x, by,
-                                        blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
+    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK>(a, (int)blockIdx.x, by,
+                                              blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
 }
 
-template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS, int LIMK>
 __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
-    col_body<R, SYS, MEQN, NRM, PF, SPEEDS>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z,
-                                            blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
+    col_body<R, SYS, MEQN, NRM, PF, SPEEDS, LIMK>(a, (int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z,
+                                                  blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -23,22 +24,22 @@ __global__ __launch_bounds__(256) void k_sweep_col(SweepArgs<R> a) {
 // ---------------------------------------------------------------------------
 static inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-template <typename R, int SYS, int MEQN, bool SPEEDS>
+template <typename R, int SYS, int MEQN, bool SPEEDS, int LIMK>
 static hipError_t launch_row(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
     const int segs = ceil_div(a.nx, 62 * CPL);
     const int groups = ceil_div(a.nrows, 4);
     const int gy = groups < 32768 ? groups : 32768;
     const int gz = ceil_div(groups, gy);
-    hipLaunchKernelGGL((k_sweep_row<R, SYS, MEQN, CPL, SPEEDS>), dim3(segs, gy, gz), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep_row<R, SYS, MEQN, CPL, SPEEDS, LIMK>), dim3(segs, gy, gz), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename R, int SYS, int MEQN, int NRM, bool SPEEDS>
+template <typename R, int SYS, int MEQN, int NRM, bool SPEEDS, int LIMK>
 static hipError_t launch_col(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int PF = 4;
     const dim3 grid(ceil_div(ceil_div(a.nx, 64), 4), ceil_div(a.m, a.chunk), a.nlines_o);
-    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, SPEEDS>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sweep_col<R, SYS, MEQN, NRM, PF, SPEEDS, LIMK>), grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -49,17 +50,22 @@ constexpr bool has_z() {
     else return MEQN == 4;
 }
 
-template <typename R, int SYS, int MEQN, bool SPEEDS>
+template <typename R, int SYS, int MEQN, bool SPEEDS, int LIMK>
 static hipError_t launch_dir(const SweepArgs<R>& a, hipStream_t s) {
-    if (a.dir == 0) return launch_row<R, SYS, MEQN, SPEEDS>(a, s);
-    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, SPEEDS>(a, s);
-    if constexpr (has_z<R, SYS, MEQN>()) return launch_col<R, SYS, MEQN, 3, SPEEDS>(a, s);
+    if (a.dir == 0) return launch_row<R, SYS, MEQN, SPEEDS, LIMK>(a, s);
+    if (a.dir == 1) return launch_col<R, SYS, MEQN, 2, SPEEDS, LIMK>(a, s);
+    if constexpr (has_z<R, SYS, MEQN>()) return launch_col<R, SYS, MEQN, 3, SPEEDS, LIMK>(a, s);
     return hipErrorInvalidValue;
 }
 
+// The MC limiter (the default) runs kernels specialised for it; the others
+// share kernels that read the limiter from the arguments.  Speed passes form
+// no correction.
 template <typename R, int SYS, int MEQN>
 static hipError_t launch_kind(const SweepArgs<R>& a, bool speeds, hipStream_t s) {
-    return speeds ? launch_dir<R, SYS, MEQN, true>(a, s) : launch_dir<R, SYS, MEQN, false>(a, s);
+    if (speeds) return launch_dir<R, SYS, MEQN, true, LIM_RUNTIME>(a, s);
+    if (a.limiter == LIM_MC) return launch_dir<R, SYS, MEQN, false, LIM_MC>(a, s);
+    return launch_dir<R, SYS, MEQN, false, LIM_RUNTIME>(a, s);
 }
 
 template <typename R>
