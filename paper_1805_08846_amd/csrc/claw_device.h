@@ -107,6 +107,26 @@ struct SweepArgs {
     R prm[4];           // plug-in solvers: the problem's parameters
 };
 
+// Row sweep geometry.  A wavefront covers 62 * cpl cells of a row (lanes 1..62;
+// lanes 0 and 63 only supply halos).  The cells left at the end of every row
+// (tail < 62 * cpl) are packed: one wavefront takes the tails of `rows` rows,
+// each in a sub-segment of `width` lanes (its useful lanes plus two halo lanes),
+// so short tails do not cost a whole wavefront per row.
+struct RowTail {
+    int width;
+    int rows;
+};
+__host__ __device__ inline RowTail row_tail(int nx, int cpl) {
+    const int seg = 62 * cpl;
+    const int tail = nx - (nx / seg) * seg;
+    RowTail t{64, 1};
+    if (tail > 0) {
+        t.width = (tail + cpl - 1) / cpl + 2;
+        t.rows = 64 / t.width;
+    }
+    return t;
+}
+
 // Rotation buffer i (0..2) chosen by selects rather than by indexing the
 // array: a dynamic index into a SweepArgs held in registers would force the
 // whole struct into private memory.

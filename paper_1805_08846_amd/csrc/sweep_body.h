@@ -165,22 +165,36 @@ __device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
 // ---------------------------------------------------------------------------
 // Row kernel: x sweep
 // ---------------------------------------------------------------------------
-// bx: segment of the row; by: group of four rows; lead: block (0, 0, 0).
+// bx: segment of the row (bx = nx / (62 CPL): the packed row tails, see
+// row_tail); by: group of four wavefronts; lead: block (0, 0, 0).
 template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK = LIM_RUNTIME>
 __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, bool lead) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
     typedef typename VecOf<R, CPL>::type V;
+    const int nx = a.nx;
+    // tail blocks: each wavefront takes the tails of S rows
+    const bool tail_blk = bx >= nx / (62 * CPL);
+    const RowTail tg = row_tail(nx, CPL);
+    const int width = tail_blk ? tg.width : 64;
+    const int S = tail_blk ? tg.rows : 1;
+    if (by * 4 * S >= a.nrows) return;  // a tail block past the last row (whole block)
     // The buffer of this trial is known before the previous trial is decided
     // unless that trial gets reverted: load from the predicted buffer first so
     // the decision's latency overlaps the loads, and reload on a mismatch.
     const int cur_guess = predicted_cur(a);
     const int lane = threadIdx.x & 63;
-    const int nx = a.nx;
-    const int row = by * 4 + (int)(threadIdx.x >> 6);
-    const bool active = row < a.nrows;
+    // sub-segment and lane within it: lane / width by a multiply (exact for
+    // lane < 64 and width <= 64)
+    const int sub = (int)(((unsigned)lane * (65536u / (unsigned)width + 1u)) >> 16);
+    const int l = lane - sub * width;
+    const int row = (by * 4 + (int)(threadIdx.x >> 6)) * S + sub;
+    const bool active = row < a.nrows && sub < S;
     const int x0 = bx * (62 * CPL);
-    const int xl = x0 - CPL + lane * CPL;
+    const int xl = x0 - CPL + l * CPL;
+    // lane roles: useful (updates its cells), right halo of its sub-segment
+    const bool useful = l >= 1 && l <= width - 2;
+    const bool rhalo = l == width - 1;
     const unsigned base = (unsigned)((active ? row : 0) * nx);
     const bool vec_ok = (nx % CPL) == 0 && (a.ncell % CPL) == 0;
     const bool interior = vec_ok && xl >= 0 && xl + CPL <= nx;
@@ -244,15 +258,15 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
 #pragma unroll
     for (int c = 1; c < CPL; ++c) solve_iface<R, SYS, 0>(cell[c - 1], cell[c], a, inv2Z, f[c]);
 
-    // largest speed over the interfaces j = x, 0 <= j <= nx, owned by lanes 1..62
-    // (and by lane 63 for j = nx when the row ends exactly at its first cell)
+    // largest speed over the interfaces j = x, 0 <= j <= nx, owned by the
+    // useful lanes 1..width-2 (and by the right halo lane for j = nx when the
+    // row ends exactly at its first cell)
     R sm = R(0);
     if (active) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int j = xl + c;
-            const bool own = (lane >= 1 && lane <= 62 && j >= 0 && j <= nx) ||
-                             (lane == 63 && c == 0 && j == nx);
+            const bool own = (useful && j >= 0 && j <= nx) || (rhalo && c == 0 && j == nx);
             if (own) sm = rmax(sm, iface_smax(f[c]));
         }
     }
@@ -276,7 +290,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
             if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nu, nrm, tng);
             else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nu, nrm, tng);
         }
-        if (active && lane >= 1 && lane <= 62) {
+        if (active && useful) {
             if (interior) {
 #pragma unroll
                 for (int e = 0; e < MEQN; ++e) {

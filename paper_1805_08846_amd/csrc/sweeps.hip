@@ -5,9 +5,14 @@
 
 namespace claw {
 
-// LIMK: limiter fixed at compile time (the MC kernels) or LIM_RUNTIME
+// LIMK: limiter fixed at compile time (the MC kernels) or LIM_RUNTIME.
+// FP32 row sweeps of the built-in systems are held to 80 VGPRs (6 wavefronts
+// per SIMD).
+template <typename R, int SYS>
+constexpr int row_waves_per_eu() { return sizeof(R) == 4 && !is_plugin(SYS) ? 6 : 1; }
 template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK>
-__global__ __launch_bounds__(256) void k_sweep_row(SweepArgs<R> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu<R, SYS>())))
+void k_sweep_row(SweepArgs<R> a) {
     const int by = (int)(blockIdx.y + blockIdx.z * gridDim.y);
     row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK>(a, (int)blockIdx.x, by,
                                               blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
