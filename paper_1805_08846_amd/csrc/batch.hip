@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void k_batch_row(BatchLaunch<R> L) {
     a.parity = L.parity;
     a.first = L.first;
     a.last = L.last;
-    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
+    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK, ROW_RPW_BATCH>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
 }
 
 template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS, int LIMK>

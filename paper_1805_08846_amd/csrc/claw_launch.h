@@ -7,6 +7,12 @@
 
 namespace claw {
 
+// Rows each row-sweep wavefront takes in turn: single grids, batched launches
+// (a batched workgroup first loads its table entry and its instance's
+// arguments, so it pays for more rows).
+constexpr int ROW_RPW_SINGLE = 1;
+constexpr int ROW_RPW_BATCH = 8;
+
 // One directional sweep (or, with speeds, its speed-only pass) of system sys
 // with meqn fields; a.dir selects the row (0) or column (1, 2) kernel.
 template <typename R>

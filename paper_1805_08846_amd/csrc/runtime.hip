@@ -858,11 +858,12 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule) {
     const int P = 62 * row_cpl(b->fp32);
     for (int i = 0; i < n; ++i) {
         const claw_desc& d = b->d[i];
-        const int segs = (int)((d.n[0] + P - 1) / P), groups = (int)((d.n[1] + 3) / 4);
+        const int rpw = ROW_RPW_BATCH;
+        const int segs = (int)((d.n[0] + P - 1) / P), groups = (int)((d.n[1] + 4 * rpw - 1) / (4 * rpw));
         const int nfull = (int)(d.n[0] / P), S = row_tail((int)d.n[0], row_cpl(b->fp32)).rows;
         for (int y = 0; y < groups; ++y)
             for (int x = 0; x < segs; ++x)
-                if (x < nfull || (int64_t)y * 4 * S < d.n[1]) rows[i].push_back({i, x, y, 0});
+                if (x < nfull || (int64_t)y * 4 * rpw * S < d.n[1]) rows[i].push_back({i, x, y, 0});
         const int sg = (int)(((d.n[0] + 63) / 64 + 3) / 4);
         const int c = chunk < d.n[1] ? chunk : (int)d.n[1];
         const int nch = (int)((d.n[1] + c - 1) / c);

@@ -166,19 +166,22 @@ __device__ __forceinline__ R ac_inv2Z(const SweepArgs<R>& a) {
 // Row kernel: x sweep
 // ---------------------------------------------------------------------------
 // bx: segment of the row (bx = nx / (62 CPL): the packed row tails, see
-// row_tail); by: group of four wavefronts; lead: block (0, 0, 0).
-template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK = LIM_RUNTIME>
+// row_tail); by: group of four wavefronts; lead: block (0, 0, 0).  Each
+// wavefront sweeps RPW rows (RPW * S with packed tails) one after the other,
+// so the work that opens a wavefront (argument loads, the step decision) is
+// paid once per RPW rows.
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK = LIM_RUNTIME, int RPW = 1>
 __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, bool lead) {
     using C = Cell<R, SYS>;
     using I = Iface<R, SYS>;
     typedef typename VecOf<R, CPL>::type V;
     const int nx = a.nx;
-    // tail blocks: each wavefront takes the tails of S rows
+    // tail blocks: each wavefront takes the tails of S rows at a time
     const bool tail_blk = bx >= nx / (62 * CPL);
     const RowTail tg = row_tail(nx, CPL);
     const int width = tail_blk ? tg.width : 64;
     const int S = tail_blk ? tg.rows : 1;
-    if (by * 4 * S >= a.nrows) return;  // a tail block past the last row (whole block)
+    if (by * 4 * RPW * S >= a.nrows) return;  // a block past the last row (whole block)
     // The buffer of this trial is known before the previous trial is decided
     // unless that trial gets reverted: load from the predicted buffer first so
     // the decision's latency overlaps the loads, and reload on a mismatch.
@@ -188,24 +191,24 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     // lane < 64 and width <= 64)
     const int sub = (int)(((unsigned)lane * (65536u / (unsigned)width + 1u)) >> 16);
     const int l = lane - sub * width;
-    const int row = (by * 4 + (int)(threadIdx.x >> 6)) * S + sub;
-    const bool active = row < a.nrows && sub < S;
+    // rows of this lane: row0 + i S, i < RPW
+    const int row0 = (by * 4 + (int)(threadIdx.x >> 6)) * RPW * S + sub;
     const int x0 = bx * (62 * CPL);
     const int xl = x0 - CPL + l * CPL;
     // lane roles: useful (updates its cells), right halo of its sub-segment
     const bool useful = l >= 1 && l <= width - 2;
     const bool rhalo = l == width - 1;
-    const unsigned base = (unsigned)((active ? row : 0) * nx);
     const bool vec_ok = (nx % CPL) == 0 && (a.ncell % CPL) == 0;
     const bool interior = vec_ok && xl >= 0 && xl + CPL <= nx;
     const R inv2Z = ac_inv2Z<R, SYS>(a);
     constexpr int nrm = 1, tng = 2;
     constexpr int NC = contrib_width<SYS>();
 
-    // load the lane's cells (ghost cells synthesised at the row ends)
+    // load the lane's cells of the row starting at base (ghost cells
+    // synthesised at the row ends)
     R q[CPL][MEQN];
     R zc[CPL][2];
-    auto load_cells = [&](const R* __restrict__ src) {
+    auto load_cells = [&](const R* __restrict__ src, unsigned base) {
         if (interior) {
 #pragma unroll
             for (int e = 0; e < MEQN; ++e) {
@@ -236,76 +239,86 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
             }
         }
     };
-    load_cells(pick_buf(a, (cur_guess + a.src_off) % 3));
+    auto base_of = [&](int row) { return (unsigned)((row < a.nrows ? row : 0) * nx); };
+    load_cells(pick_buf(a, (cur_guess + a.src_off) % 3), base_of(row0));
 
     const Trial<R> tr = open_trial(a, 0, lead);
     if (tr.done && !SPEEDS) return;
-    if (tr.cur != cur_guess) load_cells(pick_buf(a, (tr.cur + a.src_off) % 3));
+    const R* __restrict__ src = pick_buf(a, (tr.cur + a.src_off) % 3);
+    if (tr.cur != cur_guess) load_cells(src, base_of(row0));
     R* __restrict__ dst = pick_buf(a, (tr.cur + a.dst_off) % 3);
     const R nu = tr.nu;
 
     bool bad = false;
-    C cell[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.sqrt_grav, bad, cell[c]);
-    if (!active) bad = false;
-
-    // interfaces at the left face of each cell of this lane
-    C left;
-    cell_prev(cell[CPL - 1], left);
-    I f[CPL];
-    solve_iface<R, SYS, 0>(left, cell[0], a, inv2Z, f[0]);
-#pragma unroll
-    for (int c = 1; c < CPL; ++c) solve_iface<R, SYS, 0>(cell[c - 1], cell[c], a, inv2Z, f[c]);
-
-    // largest speed over the interfaces j = x, 0 <= j <= nx, owned by the
-    // useful lanes 1..width-2 (and by the right halo lane for j = nx when the
-    // row ends exactly at its first cell)
     R sm = R(0);
-    if (active) {
-#pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int j = xl + c;
-            const bool own = (useful && j >= 0 && j <= nx) || (rhalo && c == 0 && j == nx);
-            if (own) sm = rmax(sm, iface_smax(f[c]));
-        }
-    }
+    for (int i = 0; i < RPW; ++i) {
+        const int row = row0 + i * S;
+        const bool active = row < a.nrows && sub < S;
+        const unsigned base = base_of(row);
+        if (i > 0) load_cells(src, base);
 
-    if constexpr (!SPEEDS) {
-        I fprev, fnext;
-        iface_prev(f[CPL - 1], fprev);
-        iface_next(f[0], fnext);
-        Contrib<R, NC> k[CPL];
+        bool rbad = false;
+        C cell[CPL];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const I& km = c == 0 ? fprev : f[c - 1];
-            const I& kp = c == CPL - 1 ? fnext : f[c + 1];
-            limit_contrib(f[c], km, kp, nu, limiter_of<LIMK>(a), k[c]);
+        for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.sqrt_grav, rbad, cell[c]);
+        bad = bad || (active && rbad);
+
+        // interfaces at the left face of each cell of this lane
+        C left;
+        cell_prev(cell[CPL - 1], left);
+        I f[CPL];
+        solve_iface<R, SYS, 0>(left, cell[0], a, inv2Z, f[0]);
+#pragma unroll
+        for (int c = 1; c < CPL; ++c) solve_iface<R, SYS, 0>(cell[c - 1], cell[c], a, inv2Z, f[c]);
+
+        // largest speed over the interfaces j = x, 0 <= j <= nx, owned by the
+        // useful lanes 1..width-2 (and by the right halo lane for j = nx when
+        // the row ends exactly at its first cell)
+        if (active) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int j = xl + c;
+                const bool own = (useful && j >= 0 && j <= nx) || (rhalo && c == 0 && j == nx);
+                if (own) sm = rmax(sm, iface_smax(f[c]));
+            }
         }
-        R Lnext[NC];
+
+        if constexpr (!SPEEDS) {
+            I fprev, fnext;
+            iface_prev(f[CPL - 1], fprev);
+            iface_next(f[0], fnext);
+            Contrib<R, NC> k[CPL];
 #pragma unroll
-        for (int i = 0; i < NC; ++i) Lnext[i] = lane_next(k[0].L[i]);
+            for (int c = 0; c < CPL; ++c) {
+                const I& km = c == 0 ? fprev : f[c - 1];
+                const I& kp = c == CPL - 1 ? fnext : f[c + 1];
+                limit_contrib(f[c], km, kp, nu, limiter_of<LIMK>(a), k[c]);
+            }
+            R Lnext[NC];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nu, nrm, tng);
-            else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nu, nrm, tng);
-        }
-        if (active && useful) {
-            if (interior) {
+            for (int n = 0; n < NC; ++n) Lnext[n] = lane_next(k[0].L[n]);
 #pragma unroll
-                for (int e = 0; e < MEQN; ++e) {
-                    V v;
+            for (int c = 0; c < CPL; ++c) {
+                if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nu, nrm, tng);
+                else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nu, nrm, tng);
+            }
+            if (active && useful) {
+                if (interior) {
 #pragma unroll
-                    for (int c = 0; c < CPL; ++c) v[c] = q[c][e];
-                    *reinterpret_cast<V*>(dst + (size_t)e * a.ncell + base + (unsigned)xl) = v;
-                }
-            } else {
+                    for (int e = 0; e < MEQN; ++e) {
+                        V v;
 #pragma unroll
-                for (int c = 0; c < CPL; ++c) {
-                    if (xl + c < nx) {
+                        for (int c = 0; c < CPL; ++c) v[c] = q[c][e];
+                        *reinterpret_cast<V*>(dst + (size_t)e * a.ncell + base + (unsigned)xl) = v;
+                    }
+                } else {
 #pragma unroll
-                        for (int e = 0; e < MEQN; ++e)
-                            dst[(size_t)e * a.ncell + base + (unsigned)(xl + c)] = q[c][e];
+                    for (int c = 0; c < CPL; ++c) {
+                        if (xl + c < nx) {
+#pragma unroll
+                            for (int e = 0; e < MEQN; ++e)
+                                dst[(size_t)e * a.ncell + base + (unsigned)(xl + c)] = q[c][e];
+                        }
                     }
                 }
             }
