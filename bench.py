@@ -74,10 +74,10 @@ def load_traffic(path, kernel_class, source_hash):
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
-def cpu_baseline(prob, q0, steps):
+def cpu_baseline(prob, q0, steps, aux=None):
     import oracle
     t0 = time.perf_counter()
-    res = oracle.advance(prob, q0, None, steps)
+    res = oracle.advance(prob, q0, aux, steps)
     dt = time.perf_counter() - t0
     ncell = prob["n"][0] * prob["n"][1] * prob["n"][2]
     return {
@@ -86,7 +86,7 @@ def cpu_baseline(prob, q0, steps):
         "cores": oracle.num_threads(),
         "kind": "oracle",
         "sample": f"first {steps} adaptive steps ({steps + res['nreject']} trials) of the same "
-                  f"{prob['n'][0]}x{prob['n'][1]} workload, FP64 oracle, {dt:.2f} s",
+                  f"{'x'.join(str(v) for v in prob['n'][:prob['ndim']])} workload, FP64 oracle, {dt:.2f} s",
     }
 
 
@@ -277,6 +277,53 @@ def bench_plugin(args, torch, claw, inputs):
     return line
 
 
+def bench_ac3d(args, torch, claw, inputs):
+    """3D linear acoustics in a two-layer medium, 256^3 FP32 (per-cell rho, K):
+    throughput of the adaptive graph path and the slowest sweep against HBM."""
+    n = 256 if args.n == 2048 else args.n
+    steps = args.steps if args.steps_given else 200
+    warmup = args.warmup if args.warmup_given else 200
+    prob, q0, aux = inputs.acoustics3d_layers(n=n, dtype=args.dtype, nsteps=steps)
+    ncell = n ** 3
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
+    qa = torch.tensor(aux, dtype=tdt, device="cuda").contiguous()
+    solver = claw.Solver(prob, q, qa)
+    print(f"# acoustics3d_layers {n}^3 {args.dtype}: warmup {warmup}", file=sys.stderr, flush=True)
+    if warmup > 0:
+        solver.advance(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, nrej = solver.advance(steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms, cnt = solver.advance_timed(args.timed_steps)
+    solver.close()
+    names = ["x_sweep", "y_sweep", "z_sweep", "control"]
+    avg_us = {names[k]: (ms[k] / cnt[k] * 1e3 if cnt[k] else None) for k in range(4)}
+    dom = max(range(3), key=lambda k: ms[k] / cnt[k] if cnt[k] else 0.0)
+    real_bytes = 4 if args.dtype == "f32" else 8
+    alg_bytes = (2 * 4 + 2) * real_bytes * ncell  # p, u, v, w read and written, rho and K read
+    dom_s = ms[dom] / cnt[dom] * 1e-3
+    achieved = alg_bytes / dom_s / 1e9
+    line = {
+        "metric": "Gcell-updates/s + % HBM roofline", "value": ncell * steps / elapsed / 1e9,
+        "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": args.dtype,
+        "data": "synthetic (two-layer medium, Gaussian pulse at a seeded centre)",
+        "config": {"workload": "3D linear acoustics, two-layer medium (rho 1 / 4, K 1), extrapolation, "
+                               "MC, CFL 0.9", "grid": [n, n, n], "cells": ncell, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": names[dom],
+                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": dom_s * 1e6},
+        "kernel_avg_us": avg_us, "rejected_trials": nrej,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, q0, min(args.cpu_steps, 10), aux)
+    return line
+
+
 def bench_dpsp(args, torch, claw, inputs):
     """Double and single precision at 1024^2 (the radial dam break): the GPU
     path against the oracle on the host cores, each precision (the oracle's
@@ -327,7 +374,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
-    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp"])
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d"])
     ap.add_argument("--fused-step", action="store_true",
                     help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) instead of x and y sweeps")
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
@@ -356,6 +403,9 @@ def main():
         return
     if args.workload == "plugin":
         print(json.dumps(bench_plugin(args, torch, claw, inputs)), flush=True)
+        return
+    if args.workload == "ac3d":
+        print(json.dumps(bench_ac3d(args, torch, claw, inputs)), flush=True)
         return
     if args.workload == "dpsp":
         print(json.dumps(bench_dpsp(args, torch, claw, inputs)), flush=True)
