@@ -113,7 +113,9 @@ def bench_ensemble(args, torch, claw, inputs):
     b = claw.BatchSolver([p for p, _ in members], qs)
     tuned = b.tune(os.environ.get("CLAW_AUTOTUNE_CACHE"))
     print(f"# ensemble: {len(members)} instances, {cells} cells; tuned {tuned}", file=sys.stderr, flush=True)
-    b.advance(args.warmup if args.warmup_given else 50)
+    # one untimed step, as for the single-grid runs below: both time steps 2..steps+1
+    # (the autotuning above has warmed the GPU)
+    b.advance(args.warmup if args.warmup_given else 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, rej = b.advance(steps)
@@ -140,7 +142,7 @@ def bench_ensemble(args, torch, claw, inputs):
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": args.warmup if args.warmup_given else 50,
+        "warmup": args.warmup if args.warmup_given else 1,
         "ms_per_step": t_batch / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -215,6 +217,20 @@ def bench_learned(args, torch, claw, inputs):
     }
 
 
+def restart_after_warmup(torch, solver, q, warmup):
+    """Runs `warmup` untimed steps (clocks, caches, the captured step graph),
+    then puts the initial state back and restarts the clock at t = 0, so the
+    timed steps are the workload's first steps."""
+    if warmup <= 0:
+        torch.cuda.synchronize()
+        return
+    q_init = q.clone()
+    solver.advance(warmup)
+    q.copy_(q_init)
+    solver.set_control(0.0, 0.0)
+    torch.cuda.synchronize()
+
+
 def _timed_run(torch, claw, prob, q0, steps, warmup, timed_steps):
     """Throughput (Gcell-updates/s) of claw_advance on one grid and per-kernel
     average durations (us) from the event-timed path."""
@@ -222,9 +238,7 @@ def _timed_run(torch, claw, prob, q0, steps, warmup, timed_steps):
     tdt = torch.float32 if prob["dtype"] == "f32" else torch.float64
     q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
     solver = claw.Solver(prob, q, None)
-    if warmup > 0:
-        solver.advance(warmup)
-    torch.cuda.synchronize()
+    restart_after_warmup(torch, solver, q, warmup)
     t0 = time.perf_counter()
     _, nrej = solver.advance(steps)
     torch.cuda.synchronize()
@@ -290,9 +304,7 @@ def bench_ac3d(args, torch, claw, inputs):
     qa = torch.tensor(aux, dtype=tdt, device="cuda").contiguous()
     solver = claw.Solver(prob, q, qa)
     print(f"# acoustics3d_layers {n}^3 {args.dtype}: warmup {warmup}", file=sys.stderr, flush=True)
-    if warmup > 0:
-        solver.advance(warmup)
-    torch.cuda.synchronize()
+    restart_after_warmup(torch, solver, q, warmup)
     t0 = time.perf_counter()
     _, nrej = solver.advance(steps)
     torch.cuda.synchronize()
@@ -322,6 +334,43 @@ def bench_ac3d(args, torch, claw, inputs):
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, q0, min(args.cpu_steps, 10), aux)
     return line
+
+
+def bench_sizes(args, torch, claw, inputs):
+    """The radial dam break scaled from 256^2 to 16384^2 (FP32, plus FP64 at
+    4096^2): throughput and the slower sweep against HBM at each size, from the
+    MALL-resident sizes to the HBM-bound ones."""
+    steps = args.steps if args.steps_given else 200
+    rows = []
+    cases = [(n, "f32") for n in (256, 512, 1024, 2048, 4096, 8192, 16384)] + [(4096, "f64")]
+    for n, dt in cases:
+        prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=dt, nsteps=steps)
+        warm = max(200, min(3000, int(2e9 // (n * n))))
+        print(f"# sizes {n}^2 {dt}: warmup {warm}", file=sys.stderr, flush=True)
+        r = _timed_run(torch, claw, prob, q0, steps, warm, min(args.timed_steps, 20))
+        us = r["kernel_avg_us"]
+        dom = max(("x_sweep", "y_sweep"), key=lambda k: us[k])
+        alg = 2 * 3 * (4 if dt == "f32" else 8) * n * n
+        frac = alg / (us[dom] * 1e-6) / 1e9 / HBM_PEAK_GBPS
+        whole = r["value"] * 1e9 * 2 * alg / (n * n) / (HBM_PEAK_GBPS * 1e9)
+        rows.append({"n": n, "dtype": dt, "Gcell_per_s": r["value"], "x_us": us["x_sweep"],
+                     "y_us": us["y_sweep"], "sweep_frac_hbm": frac, "step_frac_hbm": whole})
+        del q0
+        torch.cuda.empty_cache()
+    big = [r for r in rows if r["n"] == 8192 and r["dtype"] == "f32"][0]
+    return {
+        "metric": "Gcell-updates/s + % HBM roofline (size sweep)", "value": big["Gcell_per_s"],
+        "unit": "Gcell-updates/s (8192^2 FP32)", "n_gpus": 1, "steps": steps, "warmup": None,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (and f64 at 4096^2)",
+        "data": "synthetic (seeded radial dam break + U(-1e-3,1e-3) noise on h)",
+        "config": {"workload": "2D shallow water radial dam break, walls, MC, CFL 0.9, sides 256..16384",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": big["sweep_frac_hbm"] * HBM_PEAK_GBPS,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": big["sweep_frac_hbm"],
+                     "traffic": None, "kernel": "slower sweep at 8192^2"},
+        "sizes": rows,
+    }
 
 
 def bench_dpsp(args, torch, claw, inputs):
@@ -374,7 +423,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
-    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d"])
+    ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d", "sizes"])
     ap.add_argument("--fused-step", action="store_true",
                     help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) instead of x and y sweeps")
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
@@ -404,6 +453,9 @@ def main():
     if args.workload == "plugin":
         print(json.dumps(bench_plugin(args, torch, claw, inputs)), flush=True)
         return
+    if args.workload == "sizes":
+        print(json.dumps(bench_sizes(args, torch, claw, inputs)), flush=True)
+        return
     if args.workload == "ac3d":
         print(json.dumps(bench_ac3d(args, torch, claw, inputs)), flush=True)
         return
@@ -419,11 +471,9 @@ def main():
     q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
     solver = claw.Solver(prob, q, None)
 
-    print(f"# workload sw_radial_dam {args.n}^2 {args.dtype}: warmup {args.warmup} steps",
-          file=sys.stderr, flush=True)
-    if args.warmup > 0:
-        solver.advance(args.warmup)
-    torch.cuda.synchronize()
+    print(f"# workload sw_radial_dam {args.n}^2 {args.dtype}: warmup {args.warmup} steps, then "
+          f"the timed steps from t = 0", file=sys.stderr, flush=True)
+    restart_after_warmup(torch, solver, q, args.warmup)
     t0 = time.perf_counter()
     _, nrej = solver.advance(args.steps)
     torch.cuda.synchronize()

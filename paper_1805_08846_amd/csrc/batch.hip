@@ -45,18 +45,12 @@ __global__ void k_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, doubl
             decide(c, q, fp32 != 0, N);
             c->st[q] = N;
             const int o = q ^ 1;
-            for (int d = 0; d < 4; ++d) {
-                c->smax32[o][d] = 0u;
-                c->smax64[o][d] = 0ull;
-            }
+            clear_speeds(c, o);
             c->nonphys[o] = 0;
             break;
         }
         case BOP_ZERO_SPEEDS:
-            for (int d = 0; d < 4; ++d) {
-                c->smax32[q][d] = 0u;
-                c->smax64[q][d] = 0ull;
-            }
+            clear_speeds(c, q);
             c->nonphys[q] = 0;
             break;
         case BOP_BEGIN_FIXED:  // trial step dt in mode `mode`

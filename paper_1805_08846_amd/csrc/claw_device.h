@@ -61,12 +61,23 @@ struct StepState {
     long long accepted, rejected, target, consecutive, trials;
 };
 
+// Per parity and direction the largest |s| is kept in SMAX_SLOTS slots on
+// separate 128-byte lines (a workgroup publishes into slot = its index mod
+// SMAX_SLOTS), so workgroups that publish rising maxima one after another do
+// not all serialise their atomics on one address; a decision takes the max
+// over the slots.
+constexpr int SMAX_SLOTS = 16;
+struct alignas(128) SmaxSlot {
+    unsigned long long v64;  // FP64 kernels: bits of max |s|
+    unsigned int v32;        // FP32 kernels: bits of max |s|
+    unsigned int pad[29];
+};
+
 // Device control block: step-control state that lives on the GPU so that a
 // captured graph can run many steps without the host.
 struct alignas(256) Ctrl {
     StepState st[2];
-    unsigned long long smax64[2][4];  // per parity and direction: max |s| (FP64 bits)
-    unsigned int smax32[2][4];        // the same for FP32 kernels
+    SmaxSlot smax[2][4][SMAX_SLOTS];  // per parity, direction and slot
     int32_t nonphys[2];               // per parity: a sweep met depth <= 0 or NaN
     int32_t ndim;
     int32_t pad;
@@ -679,15 +690,38 @@ __device__ __forceinline__ R wave_max(R v) {
 // patterns, so an unsigned atomic max is exact and order independent.  A
 // cached read first skips the atomic when a larger value is already known
 // (a stale read only costs an unneeded atomic).
-__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, float v) {
+__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, int slot, float v) {
     const unsigned bits = __float_as_uint(v);
-    unsigned* p = &c->smax32[par][dir];
+    unsigned* p = &c->smax[par][dir][slot].v32;
     if (bits > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, bits);
 }
-__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, double v) {
+__device__ __forceinline__ void publish_smax(Ctrl* c, int par, int dir, int slot, double v) {
     const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
-    unsigned long long* p = &c->smax64[par][dir];
+    unsigned long long* p = &c->smax[par][dir][slot].v64;
     if (bits > __atomic_load_n(p, __ATOMIC_RELAXED)) atomicMax(p, bits);
+}
+// slot of the calling workgroup
+__device__ __forceinline__ int smax_slot() {
+    return (int)((blockIdx.x + blockIdx.y + blockIdx.z) % SMAX_SLOTS);
+}
+// max |s| of parity q, direction d over the slots (bits of a non-negative value)
+__device__ __forceinline__ unsigned smax32_of(const Ctrl* c, int q, int d) {
+    unsigned m = 0u;
+    for (int k = 0; k < SMAX_SLOTS; ++k) m = c->smax[q][d][k].v32 > m ? c->smax[q][d][k].v32 : m;
+    return m;
+}
+__device__ __forceinline__ unsigned long long smax64_of(const Ctrl* c, int q, int d) {
+    unsigned long long m = 0ull;
+    for (int k = 0; k < SMAX_SLOTS; ++k) m = c->smax[q][d][k].v64 > m ? c->smax[q][d][k].v64 : m;
+    return m;
+}
+// zeroes the speed slots of parity q (one thread)
+__device__ __forceinline__ void clear_speeds(Ctrl* c, int q) {
+    for (int d = 0; d < 4; ++d)
+        for (int k = 0; k < SMAX_SLOTS; ++k) {
+            c->smax[q][d][k].v32 = 0u;
+            c->smax[q][d][k].v64 = 0ull;
+        }
 }
 
 template <typename R>
@@ -724,8 +758,8 @@ __device__ __forceinline__ void set_trial_dt(const Ctrl* c, StepState& s, double
 __device__ __forceinline__ double sigma_of(const Ctrl* c, int q, bool fp32) {
     double sigma = 0.0;
     for (int d = 0; d < c->ndim; ++d) {
-        const double sm = fp32 ? (double)__uint_as_float(c->smax32[q][d])
-                               : __longlong_as_double((long long)c->smax64[q][d]);
+        const double sm = fp32 ? (double)__uint_as_float(smax32_of(c, q, d))
+                               : __longlong_as_double((long long)smax64_of(c, q, d));
         const double v = sm * c->inv_dx[d];
         if (v > sigma) sigma = v;
     }
@@ -855,14 +889,11 @@ __device__ __forceinline__ void block_finish(const SweepArgs<R>& a, int dir, R v
             m = rmax(m, red[i]);
             b |= redbad[i];
         }
-        publish_smax(c, a.parity, dir, m);
+        publish_smax(c, a.parity, dir, smax_slot(), m);
         if (b) atomicOr(&c->nonphys[a.parity], 1);
         if (a.last && lead) {
             const int o = a.parity ^ 1;
-            for (int d = 0; d < 4; ++d) {
-                c->smax32[o][d] = 0u;
-                c->smax64[o][d] = 0ull;
-            }
+            clear_speeds(c, o);
             c->nonphys[o] = 0;
         }
     }

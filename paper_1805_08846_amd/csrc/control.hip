@@ -25,10 +25,7 @@ __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndi
         s.cur = s.done = s.err = s.last_accepted = s.pending = s.mode = s.pad = 0;
         s.result_off = result_off;
         s.accepted = s.rejected = s.target = s.consecutive = s.trials = 0;
-        for (int d = 0; d < 4; ++d) {
-            c->smax32[q][d] = 0u;
-            c->smax64[q][d] = 0ull;
-        }
+        clear_speeds(c, q);
         c->nonphys[q] = 0;
     }
     c->ndim = ndim;
@@ -51,10 +48,7 @@ __global__ void k_commit(Ctrl* c, int q, int fp32) {
     decide(c, q, fp32 != 0, N);
     c->st[q] = N;
     const int o = q ^ 1;
-    for (int d = 0; d < 4; ++d) {
-        c->smax32[o][d] = 0u;
-        c->smax64[o][d] = 0ull;
-    }
+    clear_speeds(c, o);
     c->nonphys[o] = 0;
 }
 
@@ -69,10 +63,7 @@ __global__ void k_begin(Ctrl* c, int q, double dt, int mode, int result_off) {
 }
 
 __global__ void k_zero_speeds(Ctrl* c, int q) {
-    for (int d = 0; d < 4; ++d) {
-        c->smax32[q][d] = 0u;
-        c->smax64[q][d] = 0ull;
-    }
+    clear_speeds(c, q);
     c->nonphys[q] = 0;
 }
 

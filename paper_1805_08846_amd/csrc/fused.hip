@@ -35,10 +35,7 @@ __global__ void k_open(Ctrl* c, int p, int fp32) {
     decide(c, p ^ 1, fp32 != 0, S);
     S.pending = S.done ? 0 : 1;
     c->st[p] = S;
-    for (int d = 0; d < 4; ++d) {
-        c->smax32[p][d] = 0u;
-        c->smax64[p][d] = 0ull;
-    }
+    clear_speeds(c, p);
     c->nonphys[p] = 0;
 }
 
@@ -64,8 +61,8 @@ __device__ __forceinline__ void block_finish2(const SweepArgs<R>& a, R vx, R vy,
             my = rmax(my, red[1][i]);
             b |= redbad[i];
         }
-        publish_smax(a.ctrl, a.parity, 0, mx);
-        publish_smax(a.ctrl, a.parity, 1, my);
+        publish_smax(a.ctrl, a.parity, 0, smax_slot(), mx);
+        publish_smax(a.ctrl, a.parity, 1, smax_slot(), my);
         if (b) atomicOr(&a.ctrl->nonphys[a.parity], 1);
     }
 }

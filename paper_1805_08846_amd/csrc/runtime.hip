@@ -325,14 +325,20 @@ claw_status speed_pass(claw_solver* h) {
     return CLAW_OK;
 }
 
+// max |s| of parity q and direction dir: the largest of the slots (the bit
+// patterns of non-negative values order like the values)
 double smax_value(const claw_solver* h, const Ctrl& c, int q, int dir) {
     if (h->fp32) {
+        unsigned m = 0u;
+        for (int k = 0; k < SMAX_SLOTS; ++k) m = c.smax[q][dir][k].v32 > m ? c.smax[q][dir][k].v32 : m;
         float f;
-        memcpy(&f, &c.smax32[q][dir], 4);
+        memcpy(&f, &m, 4);
         return f;
     }
+    unsigned long long m = 0ull;
+    for (int k = 0; k < SMAX_SLOTS; ++k) m = c.smax[q][dir][k].v64 > m ? c.smax[q][dir][k].v64 : m;
     double v;
-    memcpy(&v, &c.smax64[q][dir], 8);
+    memcpy(&v, &m, 8);
     return v;
 }
 
