@@ -35,10 +35,15 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
 def kernel_source_hash():
+    """Hash of the sweep kernels' sources with comments and blank lines removed
+    (a PMC summary stays valid across comment edits, not across code edits)."""
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h"):
-        with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h"):
+        with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

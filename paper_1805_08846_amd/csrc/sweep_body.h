@@ -14,7 +14,9 @@
 // the next lane's left-cell contribution) from the adjacent lanes with DPP
 // wave shifts, so each interface is solved once.  The first and last lane
 // of a wave only supply halo interfaces; neighbouring waves overlap by
-// 2 * CPL cells.  The four wavefronts of a workgroup take four rows.
+// 2 * CPL cells.  The cells left at the end of each row are packed several
+// rows to a wavefront (row_tail), and a wavefront may sweep several rows in
+// turn (RPW; the batched kernels use 8).
 //
 // Column kernel (y and z sweeps).  A wavefront owns 64 adjacent columns (one
 // per lane, coalesced rows) and marches along the sweep direction over a
