@@ -7,10 +7,12 @@
 
 namespace claw {
 
-// Rows each row-sweep wavefront takes in turn: single grids, batched launches
-// (a batched workgroup first loads its table entry and its instance's
-// arguments, so it pays for more rows).
-constexpr int ROW_RPW_SINGLE = 1;
+// Rows each row-sweep wavefront takes in turn: single grids (FP64 lanes hold
+// two cells, so a wavefront's fixed work is spread over two rows), batched
+// launches (a batched workgroup first loads its table entry and its
+// instance's arguments, so it pays for more rows).
+template <typename R>
+constexpr int row_rpw_single() { return sizeof(R) == 4 ? 1 : 2; }
 constexpr int ROW_RPW_BATCH = 8;
 
 // One directional sweep (or, with speeds, its speed-only pass) of system sys

@@ -14,7 +14,7 @@ template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(row_waves_per_eu<R, SYS>())))
 void k_sweep_row(SweepArgs<R> a) {
     const int by = (int)(blockIdx.y + blockIdx.z * gridDim.y);
-    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK, ROW_RPW_SINGLE>(a, (int)blockIdx.x, by,
+    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK, row_rpw_single<R>()>(a, (int)blockIdx.x, by,
                                               blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0);
 }
 
@@ -33,7 +33,7 @@ template <typename R, int SYS, int MEQN, bool SPEEDS, int LIMK>
 static hipError_t launch_row(const SweepArgs<R>& a, hipStream_t s) {
     constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
     const int segs = ceil_div(a.nx, 62 * CPL);
-    const int groups = ceil_div(a.nrows, 4 * ROW_RPW_SINGLE);
+    const int groups = ceil_div(a.nrows, 4 * row_rpw_single<R>());
     const int gy = groups < 32768 ? groups : 32768;
     const int gz = ceil_div(groups, gy);
     hipLaunchKernelGGL((k_sweep_row<R, SYS, MEQN, CPL, SPEEDS, LIMK>), dim3(segs, gy, gz), dim3(256), 0, s, a);
