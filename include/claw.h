@@ -149,7 +149,11 @@ claw_status claw_workspace_bytes(const claw_desc* d, size_t* bytes);
 /* Validates d and binds the caller's device buffers.  q, aux, workspace are
  * device pointers (aux NULL iff maux = 0); stream is a hipStream_t (NULL =
  * the null stream).  Enqueues the set-up kernels (derived coefficients,
- * control block) on the stream.  *out receives the handle. */
+ * control block) on the stream.  *out receives the handle.  The rows per
+ * column-sweep workgroup are chosen from the grid and the device's CU count;
+ * the environment variables CLAW_COL_WAVES (target wavefronts per column
+ * sweep) and CLAW_COL_CHUNK (rows per chunk) override that choice for tuning,
+ * read once per process; values <= 0 are ignored. */
 claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* workspace,
                         size_t workspace_bytes, void* stream, claw_solver** out);
 

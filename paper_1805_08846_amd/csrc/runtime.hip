@@ -148,10 +148,12 @@ int col_chunk(int64_t m, int64_t nx, int64_t nlines_o) {
     // redundant halo work) that still give every SIMD at most three
     // wavefronts, so no SIMD marches a fourth chunk (measured at 2048^2 FP32:
     // 22 rows, 3008 wavefronts on 1024 SIMDs; 24 rows 5 % slower, 20 rows
-    // 20 % slower); at least 16 rows
+    // 20 % slower); at least 16 rows.  Tuning overrides from the environment:
+    // CLAW_COL_WAVES (target wavefronts per column sweep) and CLAW_COL_CHUNK
+    // (rows per chunk, used as given up to m); values <= 0 are ignored.
     static const int64_t target_waves = [] {
         const char* e = getenv("CLAW_COL_WAVES");
-        if (e) return (int64_t)atoll(e);
+        if (e && atoll(e) > 0) return (int64_t)atoll(e);
         int dev = 0, cus = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
