@@ -57,6 +57,8 @@ claw_status validate(const claw_desc* d) {
     if (d->ndim != 2 && d->ndim != 3) return fail(CLAW_E_INVALID, "ndim must be 2 or 3 (got %d)", d->ndim);
     for (int k = 0; k < 3; ++k) {
         if (d->n[k] < 1) return fail(CLAW_E_INVALID, "n[%d] = %lld must be >= 1", k, (long long)d->n[k]);
+        if (d->n[k] >= ((int64_t)1 << 31))  // keeps the cell count below from overflowing
+            return fail(CLAW_E_UNSUPPORTED, "n[%d] = %lld is too large", k, (long long)d->n[k]);
         if (k < d->ndim && !(d->upper[k] > d->lower[k]))
             return fail(CLAW_E_INVALID, "upper[%d] must exceed lower[%d]", k, k);
         if (d->bc_lo[k] < 0 || d->bc_lo[k] > 2 || d->bc_hi[k] < 0 || d->bc_hi[k] > 2)

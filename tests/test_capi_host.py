@@ -106,6 +106,25 @@ def test_bad_grid_and_bc(claw):
     assert e.value.status == claw.CLAW_E_UNSUPPORTED
 
 
+def test_grid_size_limits(claw):
+    # extents whose product overflows 64 bits, and a grid just past the 32-bit
+    # element offsets, are refused on the host; one just inside is accepted
+    d = _sw_desc(claw)
+    d.n[0] = 1 << 40
+    d.n[1] = 1 << 40
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    d = _sw_desc(claw)
+    d.n[0] = 1 << 16
+    d.n[1] = (1 << 31) // (3 << 16) + 1
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    d.n[1] -= 1
+    assert claw.claw_workspace_bytes(d) >= 2 * 3 * 4 * d.n[0] * d.n[1]
+
+
 def _burgers_desc(claw, ndim=2):
     from paper_1805_08846_amd import inputs
     prob, _, _ = (inputs.burgers2d(n=32) if ndim == 2 else inputs.burgers3d(n=16))
