@@ -811,6 +811,9 @@ namespace {
 constexpr int kBatchChunkMin = 8;
 const int kTuneChunks[] = {16, 32, 64, 128};
 
+int inst_row_blocks(const claw_desc& d, bool fp32);
+int inst_col_blocks(const claw_desc& d, int chunk);
+
 claw_status batch_validate(const claw_desc* d, int32_t count) {
     if (!d || count < 1 || count > 65535) return fail(CLAW_E_INVALID, "need 1..65535 descriptors");
     for (int i = 0; i < count; ++i) {
@@ -821,6 +824,17 @@ claw_status batch_validate(const claw_desc* d, int32_t count) {
         if (d[i].dtype != d[0].dtype) return fail(CLAW_E_INVALID, "all instances need the same dtype");
         if (d[i].flags) return fail(CLAW_E_UNSUPPORTED, "batches run the default split step (instance %d)", i);
     }
+    // a batched sweep is one 1-D launch of 256-thread workgroups, and a
+    // dispatch counts its work-items in 32 bits: at most 2^24 - 1 workgroups
+    int64_t rows = 0, cols = 0;
+    for (int i = 0; i < count; ++i) {
+        rows += inst_row_blocks(d[i], d[0].dtype == CLAW_FP32);
+        cols += inst_col_blocks(d[i], kBatchChunkMin);
+    }
+    const int64_t max_blocks = ((int64_t)1 << 24) - 1;
+    if (rows > max_blocks || cols > max_blocks)
+        return fail(CLAW_E_UNSUPPORTED, "batch too large for one launch (%lld row blocks, %lld column blocks)",
+                    (long long)rows, (long long)cols);
     return CLAW_OK;
 }
 

@@ -125,6 +125,19 @@ def test_grid_size_limits(claw):
     assert claw.claw_workspace_bytes(d) >= 2 * 3 * 4 * d.n[0] * d.n[1]
 
 
+def test_batch_size_limits(claw):
+    # a batched sweep is one launch of at most 2^24 - 1 workgroups: 300 grids
+    # of 1 x 262140 cells need 300 x 65535 row workgroups and are refused;
+    # 200 of them fit
+    d = _sw_desc(claw)
+    d.n[0], d.n[1] = 1, 65535 * 4
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_batch_workspace_bytes([d] * 300)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    assert claw.claw_batch_workspace_bytes([d] * 200) >= 2 * 3 * 4 * 200 * d.n[1]
+    assert claw.claw_batch_workspace_bytes([_sw_desc(claw)] * 4) > 0
+
+
 def _burgers_desc(claw, ndim=2):
     from paper_1805_08846_amd import inputs
     prob, _, _ = (inputs.burgers2d(n=32) if ndim == 2 else inputs.burgers3d(n=16))
