@@ -1382,7 +1382,8 @@ LcWorkPlan lc_work_plan(const claw_lc_desc* d) {
 claw_status lc_validate(const claw_lc_desc* d) {
     if (!d) return fail(CLAW_E_INVALID, "learned-correction descriptor is NULL");
     if (d->nx < 2 || d->ny < 2) return fail(CLAW_E_INVALID, "grid must be at least 2 x 2");
-    if (3 * d->nx * d->ny >= ((int64_t)1 << 31) || d->nx + 1 >= ((int64_t)1 << 31) / 3)
+    if (d->nx >= ((int64_t)1 << 31) / 3 || d->ny >= ((int64_t)1 << 31) / 3 ||  // bounds the product below
+        3 * d->nx * d->ny >= ((int64_t)1 << 31) || d->nx + 1 >= ((int64_t)1 << 31) / 3)
         return fail(CLAW_E_UNSUPPORTED, "grid too large for 32-bit offsets");
     for (int c = 0; c < 3; ++c)
         if (!(d->sl[c] > 0 && d->sd1[c] > 0 && d->sd2[c] > 0 && d->sd3[c] > 0) || !isfinite(d->sl[c]) ||

@@ -217,6 +217,11 @@ def test_learned_sizes_and_validation(claw):
         with pytest.raises(claw.ClawError):
             claw.claw_lc_sizes(bad)
     bad = _lc_desc(claw)
+    bad.nx = bad.ny = 1 << 40  # the product overflows 64 bits
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_lc_sizes(bad)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    bad = _lc_desc(claw)
     bad.sd2[1] = 0.0
     with pytest.raises(claw.ClawError):
         claw.claw_lc_sizes(bad)
