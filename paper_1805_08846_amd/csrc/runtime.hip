@@ -1163,6 +1163,9 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
     int chunk = 0, schedule = 0;
     double best = 0;
     bool cached = cache_lookup(cache_path, key, &chunk, &schedule, &best);
+    // an entry that is no valid tile choice (an edited or damaged file) counts as a miss
+    if (cached && (chunk < kBatchChunkMin || chunk > 4096 || (schedule != 0 && schedule != 1) || !(best > 0)))
+        cached = false;
     if (!cached) {
         // time a few state-preserving trials (dt = 0, always accepted) per candidate
         claw_status st = batch_ctrl(b, BOP_COMMIT);

@@ -6,6 +6,8 @@ autotuner picks, and the small instances must match the CPU oracle.
 """
 import os
 
+import re
+
 import numpy as np
 import pytest
 
@@ -92,6 +94,14 @@ def test_autotuner_cache_roundtrip(claw, tmp_path):
     again = b.tune(cache)
     b.close()
     assert first == again and first["chunk"] in (16, 32, 64, 128)
+    # a damaged entry (chunk 0) is not used: the tuner times the candidates again
+    with open(cache, "w") as fh:
+        fh.write(re.sub(r'"chunk":\s*\d+', '"chunk": 0', text))
+    b = claw.BatchSolver([p for p, _ in members], qs)
+    retuned = b.tune(cache)
+    b.close()
+    assert retuned["chunk"] in (16, 32, 64, 128)
+    assert '"chunk": 0' not in open(cache).read()
 
 
 def test_batch_matches_oracle(claw):
