@@ -321,6 +321,11 @@ class BatchSolver:
         import torch
         self.probs = probs
         self.descs = [desc_from_problem(p) for p in probs]
+        if len(qs) != len(self.descs):
+            raise ValueError(f"{len(self.descs)} problems but {len(qs)} state tensors")
+        for i, (d, q) in enumerate(zip(self.descs, qs)):
+            _need(q, f"qs[{i}]", d.meqn * d.n[0] * d.n[1] * d.n[2],
+                  torch.float32 if d.dtype == CLAW_FP32 else torch.float64)
         self.qs = qs
         dev = qs[0].device
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
@@ -408,6 +413,18 @@ def claw_lc_advance(h, desc, params, nsteps, dt, tau, kappa, work):
                                 float(kappa), _ptr(work)), "claw_lc_advance")
 
 
+def _need(t, name, numel, dtype):
+    """Checks a device buffer before its pointer goes to the library: the C
+    calls take plain pointers, so a tensor of the wrong size or type would
+    become an out-of-bounds access on the GPU instead of an error here."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() != numel:
+        where = "device" if t.is_cuda else "host"
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor of {numel} elements "
+                         f"(got {tuple(t.shape)} {t.dtype} on the {where})")
+
+
 class LearnedCorrection:
     """Parameter block and workspace (torch device buffers) of the learned
     correction on an nx x ny grid; every method forwards to one C call."""
@@ -435,10 +452,23 @@ class LearnedCorrection:
     def theta(self):
         return self.params[:CLAW_LC_NPARAM].double().cpu().numpy()
 
+    def _cells(self, name, t):
+        import torch
+        _need(t, name, 3 * self.nx * self.ny, torch.float32)
+
+    def _faces(self, dF, dG):
+        import torch
+        _need(dF, "dF", 3 * self.ny * (self.nx + 1), torch.float32)
+        _need(dG, "dG", 3 * (self.ny + 1) * self.nx, torch.float32)
+
     def forward(self, q, dF, dG):
+        self._cells("q", q)
+        self._faces(dF, dG)
         claw_lc_forward(self.desc, self.params, q, dF, dG, self.stream.cuda_stream)
 
     def loss_grad(self, q, target, plain, nux, nuy, w):
+        for name, t in (("q", q), ("target", target), ("plain", plain)):
+            self._cells(name, t)
         claw_lc_loss_grad(self.desc, self.params, q, target, plain, nux, nuy, w, self.work, self.grad,
                           self.loss, self.stream.cuda_stream)
 
@@ -447,6 +477,14 @@ class LearnedCorrection:
         claw_lc_adam(self.params, self.grad, self.step_count, lr, beta1, beta2, eps, self.stream.cuda_stream)
 
     def apply(self, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x=None, keep_y=None):
+        import torch
+        for name, t in (("qn", qn), ("plain", plain), ("out", out)):
+            self._cells(name, t)
+        self._faces(dF, dG)
+        if keep_x is not None:
+            _need(keep_x, "keep_x", self.ny * (self.nx + 1), torch.uint8)
+        if keep_y is not None:
+            _need(keep_y, "keep_y", (self.ny + 1) * self.nx, torch.uint8)
         claw_lc_apply(self.desc, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x, keep_y, self.work,
                       self.stream.cuda_stream)
 
@@ -529,6 +567,12 @@ class Solver:
             raise ValueError(f"q must be a contiguous {want} device tensor")
         if aux is not None and (aux.dtype != want or not aux.is_contiguous()):
             raise ValueError(f"aux must be a contiguous {want} device tensor")
+        ncell = self.desc.n[0] * self.desc.n[1] * self.desc.n[2]
+        _need(q, "q", self.desc.meqn * ncell, want)
+        if self.desc.maux > 0:
+            _need(aux, "aux", self.desc.maux * ncell, want)
+        elif aux is not None:
+            raise ValueError("aux given for a problem without aux fields")
         self.q = q
         self.aux = aux
         self.stream = stream if stream is not None else torch.cuda.current_stream(q.device)
