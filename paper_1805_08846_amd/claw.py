@@ -404,6 +404,9 @@ def claw_lc_apply(desc, qn, plain, dF, dG, nux, nuy, tau, kappa, out, keep_x, ke
 
 
 def claw_lc_coarsen(nx, ny, fine, coarse, stream_handle):
+    import torch
+    _need(fine, "fine", 3 * (2 * int(ny)) * (2 * int(nx)), torch.float32)
+    _need(coarse, "coarse", 3 * int(ny) * int(nx), torch.float32)
     _check(_lib.claw_lc_coarsen(int(nx), int(ny), _ptr(fine), _ptr(coarse), ctypes.c_void_p(stream_handle)),
            "claw_lc_coarsen")
 

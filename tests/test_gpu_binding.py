@@ -61,5 +61,7 @@ def test_learned_checks_buffers(claw):
     with pytest.raises(ValueError, match="keep_y must be"):
         lc.apply(q, q, dF, dG, 0.1, 0.1, 0.3, 10.0, out, None,
                  torch.zeros((ny, nx), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError, match="fine must be"):
+        claw.claw_lc_coarsen(nx, ny, q, out, lc.stream.cuda_stream)
     lc.forward(q, dF, dG)  # the right buffers run
     torch.cuda.synchronize()
