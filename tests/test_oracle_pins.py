@@ -205,6 +205,36 @@ def test_single_sweep_matches_characteristic_closed_form(limiter, direction):
     assert np.array_equal(out[tng], q[tng])
 
 
+@pytest.mark.parametrize("limiter", ["mc", "superbee", "vanleer"])
+@pytest.mark.parametrize("direction", [0, 1, 2])
+def test_3d_single_sweep_matches_characteristic_closed_form(limiter, direction):
+    # 3D acoustics (p, u, v, w) on a periodic 24 x 20 x 16 box: every
+    # direction's sweep, with its own dx, equals the scalar step per
+    # characteristic along that axis, and leaves the two transverse velocities
+    # untouched
+    rho, K = 1.0, 4.0
+    Z, c = 2.0, 2.0
+    n = (24, 20, 16)
+    prob = inputs._base(3, n, (0, 0, 0), (1, 1, 1), "acoustics", 4, "periodic", rho=rho, bulk=K,
+                        limiter=limiter)
+    rng = np.random.default_rng(33)
+    q = rng.uniform(-1, 1, (4, n[2], n[1], n[0]))
+    dt = 0.6 / (c * n[direction])  # nu = 0.6 along the sweep direction
+    out, smax = oracle.sweep(prob, q, None, direction, dt)
+    assert smax == c
+    normal = 1 + direction
+    axis = -1 - direction  # arrays are (nz, ny, nx)
+    w1, w2 = _characteristics(q, Z, normal)
+    e1 = np.moveaxis(_scalar_hr_step(np.moveaxis(w1, axis, -1), 0.6, False, limiter), -1, axis)
+    e2 = np.moveaxis(_scalar_hr_step(np.moveaxis(w2, axis, -1), 0.6, True, limiter), -1, axis)
+    o1, o2 = _characteristics(out, Z, normal)
+    assert np.max(np.abs(o1 - e1)) < 1e-14
+    assert np.max(np.abs(o2 - e2)) < 1e-14
+    for f in range(1, 4):
+        if f != normal:
+            assert np.array_equal(out[f], q[f])
+
+
 @pytest.mark.parametrize("limiter", ["mc", "none"])
 @pytest.mark.parametrize("direction", [0, 1])
 def test_courant_one_exact_shift(limiter, direction):
