@@ -8,6 +8,7 @@ for the built-in systems: FP64 1e-12 and FP32 1e-5 relative L-infinity per
 field against the FP64 oracle; single sweeps 1e-13 / 2e-6.
 """
 import math
+import zlib
 
 import numpy as np
 import pytest
@@ -67,7 +68,7 @@ SIZES = [(3, 3), (1, 9), (9, 1), (127, 129), (300, 70), (70, 300), (251, 5)]
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("direction", [0, 1])
 def test_burgers_single_sweep_random_states(claw, n, dtype, direction):
-    rng = np.random.default_rng(hash((n, dtype, direction, "burgers")) % 2 ** 32)
+    rng = np.random.default_rng(zlib.crc32(repr((n, dtype, direction, "burgers")).encode()))
     bcs = ["extrap", "wall", "periodic"]
     prob = _burgers(n, dtype)
     prob["bc_lo"] = tuple(rng.choice(bcs) for _ in range(3))
@@ -88,7 +89,7 @@ def test_burgers_single_sweep_random_states(claw, n, dtype, direction):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("direction", [0, 1])
 def test_generic_shallow_water_single_sweep_random_states(claw, n, dtype, direction):
-    rng = np.random.default_rng(hash((n, dtype, direction, "swg")) % 2 ** 32)
+    rng = np.random.default_rng(zlib.crc32(repr((n, dtype, direction, "swg")).encode()))
     bcs = ["extrap", "wall", "periodic"]
     prob = inputs._base(2, n, (0, 0), (1.0, 1.5), "shallow_water", 3, "extrap", dtype=dtype,
                         grav=1.3, solver="generic")
