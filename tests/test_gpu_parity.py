@@ -308,6 +308,26 @@ def test_graph_path_equals_eager_path_bitwise(claw):
     assert np.array_equal(_host(q1), _host(q2))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_graph_replays_with_eager_work_between(claw, dtype):
+    # several advance calls, each replaying captured graphs, with unrelated
+    # eager GPU work, a speed pass and synchronisations between them; every
+    # call's result equals the eager path's bitwise
+    prob, q0, _ = inputs.sw_radial_dam(n=200, dtype=dtype, seed=14)
+    s1, q1 = _solver(claw, prob, q0)
+    s2, q2 = _solver(claw, prob, q0)
+    for k in range(3):
+        s1.advance(40)
+        s2.advance_timed(40)
+        assert np.array_equal(_host(q1), _host(q2)), k
+        junk = torch.randn(1 << 20, device="cuda")
+        float((junk * junk).sum())
+        assert s1.cfl() == s2.cfl()
+        torch.cuda.synchronize()
+    s1.close()
+    s2.close()
+
+
 def test_run_to_run_determinism(claw):
     prob, q0, _ = inputs.sw_radial_dam(n=333, dtype="f32", seed=12)
     outs = []
