@@ -79,6 +79,32 @@ def test_tiles_and_schedules_do_not_change_results(claw):
             assert np.array_equal(a, b), tiles
 
 
+def test_batch_graph_replays_with_eager_work_between(claw):
+    # three advance calls of the batch (captured graphs replayed) with
+    # unrelated eager GPU work and synchronisations between them; after each
+    # call every instance equals its single grid advanced eagerly, bitwise
+    members = inputs.sw_ensemble(sides=[37, 64, 129], seed=9, dtype="f32", nsteps=120)
+    qs = _tensors(members, "f32")
+    b = claw.BatchSolver([p for p, _ in members], qs)
+    singles = []
+    for prob, q0 in members:
+        q = torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous()
+        singles.append((claw.Solver(prob, q), q))
+    for k in range(3):
+        b.advance(40)
+        for s, _ in singles:
+            s.advance_timed(40)
+        torch.cuda.synchronize()
+        for i, (_, q) in enumerate(singles):
+            assert torch.equal(qs[i], q), (k, i)
+        junk = torch.randn(1 << 20, device="cuda")
+        float((junk * junk).sum())
+        torch.cuda.synchronize()
+    b.close()
+    for s, _ in singles:
+        s.close()
+
+
 def test_autotuner_cache_roundtrip(claw, tmp_path):
     members = inputs.sw_ensemble(sides=SIDES, seed=5, dtype="f32", nsteps=30)
     base, _, _ = _batch(claw, members, "f32", 30)
