@@ -185,6 +185,35 @@ def test_coarsen_matches_oracle(claw):
     assert np.abs(coarse.double().cpu().numpy() - ref).max() <= 2e-7 * np.abs(ref).max()
 
 
+def test_learned_advance_replays_with_eager_work_between(claw):
+    # three calls of 20 steps (a captured graph of 16 replayed each call) with
+    # unrelated eager GPU work between them; after every call the state equals
+    # the composition of the separate entry points, bitwise
+    n, dt = 48, 0.4 / 48
+    prob, q0, _ = inputs.sw_hump(n=n, seed=4, dtype="f32", nsteps=60)
+    th = inputs.lc_init_params(seed=4, out_gain=1.0)
+    lc = claw.LearnedCorrection(n, n, inputs.lc_norm(s_out=(2e-3, 2e-3, 2e-3)), th)
+    tau, kappa = 0.5, 5.0
+    qa, qb = _dev(q0), _dev(q0)
+    sa, sb = claw.Solver(prob, qa), claw.Solver(prob, qb)
+    dF = torch.empty((3, n, n + 1), device="cuda")
+    dG = torch.empty((3, n + 1, n), device="cuda")
+    for k in range(3):
+        lc.advance(sa, 20, dt, tau, kappa)
+        for _ in range(20):
+            qn = qb.clone()
+            sb.advance_fixed([dt])
+            lc.forward(qn, dF, dG)
+            lc.apply(qn, qb, dF, dG, dt * n, dt * n, tau, kappa, qb)
+        torch.cuda.synchronize()
+        assert torch.equal(qa, qb), k
+        junk = torch.randn(1 << 20, device="cuda")
+        float((junk * junk).sum())
+        torch.cuda.synchronize()
+    sa.close()
+    sb.close()
+
+
 @pytest.mark.parametrize("steps", [6, 40])  # 40: two captured graphs of 16 and 8 eager steps
 def test_learned_advance_equals_composition_and_conserves(claw, steps):
     n, dt = 64, 0.4 / 64
