@@ -322,9 +322,9 @@ __device__ __forceinline__ void roe_c(float x, float& c, float& i2c) {
 // Roe solver with arithmetic-mean depth and sqrt(h)-weighted velocities plus
 // the Harten-Hyman entropy fix on the 1- and 3-waves.  The transonic test of
 // the fix, lambda_r = m/h - sqrt(g h) > 0 in the middle state, is taken as
-// m > 0 and m^2 > g h^3 so that the division and square root are only paid in
-// the (rare) transonic case; the split it selects is continuous across the
-// test's boundary.
+// h > 0, m > 0 and m^2 > g h^3 so that the division and square root are only
+// paid in the (rare) transonic case; the split it selects is continuous
+// across the test's boundary.  A middle state of depth <= 0 takes no fix.
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, SYS_SW>& r,
                                         R, R, R, R g, int efix, Iface<R, SYS_SW>& o) {
@@ -348,14 +348,14 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, 
         R lam_l = l.u - l.c;
         R hm = l.h + a1;
         R mm = l.mn + a1 * s1;
-        if (lam_l < R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
+        if (lam_l < R(0) && hm > R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
             R lam_r = fdiv(mm, hm) - fsqrt(g * hm);
             if (lam_r > R(0)) am1 = fdiv(lam_l * (lam_r - s1), lam_r - lam_l);
         }
         R lam_r3 = r.u + r.c;
         R hm3 = r.h - a3;
         R mm3 = r.mn - a3 * s3;
-        if (lam_r3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
+        if (lam_r3 > R(0) && hm3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
             R lam_l3 = fdiv(mm3, hm3) + fsqrt(g * hm3);
             if (lam_l3 < R(0)) am3 = fdiv(lam_l3 * (lam_r3 - s3), lam_r3 - lam_l3);
         }

@@ -94,16 +94,19 @@ def acoustics2d_pulse(n=128, dtype="f64", nsteps=100):
     return prob, round_to(q, dtype), None
 
 
-def sw_radial_dam(n=2048, dtype="f32", nsteps=1000, noise=True, seed=0):
+def sw_radial_dam(n=2048, dtype="f32", nsteps=1000, noise=True, seed=0, h_in=2.0, h_out=1.0):
     """2D shallow water, n x n on [-2.5, 2.5]^2, g = 1; radial dam break
-    h = 2 for r < 0.5 else 1, plus seeded U(-1e-3, 1e-3) per cell on h
-    (drawn in memory order, y-major); hu = hv = 0; reflecting walls, CFL 0.9."""
+    h = h_in (2) for r < 0.5 else h_out (1), plus seeded U(-1e-3, 1e-3) per
+    cell on h (drawn in memory order, y-major); hu = hv = 0; reflecting walls,
+    CFL 0.9.  With h_in = 1, h_out = 0.1 the outflow is supercritical and the
+    rarefactions are transonic in both directions (1-waves on the far side of
+    the centre, 3-waves on the near side)."""
     prob = _base(2, (n, n), (-2.5, -2.5), (2.5, 2.5), "shallow_water", 3, "wall", grav=1.0,
                  nsteps=nsteps, dtype=dtype, name="sw_radial_dam", seed=seed, noise=noise)
     x, y, _ = cell_centers(prob)
     r = np.sqrt(x * x + y * y)
     q = np.zeros((3,) + x.shape)
-    q[0] = np.where(r < 0.5, 2.0, 1.0)
+    q[0] = np.where(r < 0.5, float(h_in), float(h_out))
     if noise:
         rng = np.random.default_rng(seed)
         q[0] += rng.uniform(-1e-3, 1e-3, size=x.shape)
@@ -254,7 +257,8 @@ CONFIGS = {
 
 def random_states(system, count, seed, meqn=3, depth=(0.5, 2.0), vel=0.5):
     """Seeded random valid cell states (count, meqn) for interface-level tests:
-    shallow water depths in the given range and velocities up to vel; acoustics
+    shallow water depths in the given range and velocities up to vel (with
+    depth (0.1, 2) and vel 2 many neighbouring pairs are transonic); acoustics
     pressures and velocities in [-1, 1]."""
     rng = np.random.default_rng(seed)
     if system == "shallow_water":

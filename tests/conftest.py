@@ -10,4 +10,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
-    config.addinivalue_line("markers", "slow: long CPU-only checks (oracle floors, golden files)")
+    config.addinivalue_line("markers", "slow: long CPU-only checks (the FP32 rounding floor of the oracle)")

@@ -79,6 +79,92 @@ def test_sw_entropy_fix_harten_hyman_value():
     assert np.allclose(am, expect, rtol=1e-14, atol=1e-15)
 
 
+def test_sw_entropy_fix_three_wave_exact_rational():
+    # Worked example of the Harten-Hyman fix on the 3-wave, every quantity a
+    # rational number (g = 1, h_l = 1, h_r = 49, so sqrt(h) = 1, 7 and
+    # c^ = sqrt(g (1 + 49) / 2) = 5), derived by hand:
+    #   u_l = u_r = -6, v_l = 2, v_r = 1:  u^ = -6, v^ = (2 + 7) / 8 = 9/8
+    #   speeds s = (-11, -6, -1)
+    #   strengths a1 = ((u^ + c^) dh - dm_n) / (2 c^) = (-48 + 288) / 10 = 24,
+    #             a2 = dm_t - v^ dh = 47 - 54 = -7,
+    #             a3 = (dm_n - (u^ - c^) dh) / (2 c^) = (-288 + 528) / 10 = 24
+    #   3-wave middle state q_r - W3 = (25, -270, 22): lambda_l = -270/25 + 5
+    #   = -29/5 < 0 < lambda_r = -6 + 7 = 1, transonic; the fix gives
+    #   a_3 = lambda_l (lambda_r - s3) / (lambda_r - lambda_l) = -29/17
+    #   (plain Roe: min(s3, 0) = -1).  1-wave middle state q_l + W1 = (25,
+    #   -270, 29): lambda_r = -270/25 - 5 < 0, not transonic, a_1 = -11.
+    #   A-dQ = -11 W1 - 6 W2 - 29/17 W3 with W1 = (24, -264, 27),
+    #   W2 = (0, 0, -7), W3 = (24, -24, 27):  (-5184, 50064, -5118) / 17.
+    expect_am = np.array([-5184.0, 50064.0, -5118.0]) / 17.0
+    expect_total = -11 * np.array([24.0, -264, 27]) - 6 * np.array([0.0, 0, -7]) \
+        - 1 * np.array([24.0, -24, 27])
+    for normal in (1, 2):
+        tng = 3 - normal
+        ql = np.zeros(3)
+        qr = np.zeros(3)
+        ql[0], ql[normal], ql[tng] = 1.0, -6.0, 2.0
+        qr[0], qr[normal], qr[tng] = 49.0, -294.0, 49.0
+        W, s, am, ap = oracle.riemann_sw(ql, qr, 1.0, normal, efix=True)
+        assert np.allclose(s, [-11.0, -6.0, -1.0], rtol=0, atol=1e-14)
+        got = np.array([am[0], am[normal], am[tng]])
+        assert np.allclose(got, expect_am, rtol=1e-14, atol=0), got * 17
+        # without the fix the 3-wave sends min(s3, 0) W3 = -W3 left
+        W0, s0, am0, ap0 = oracle.riemann_sw(ql, qr, 1.0, normal, efix=False)
+        got0 = np.array([am0[0], am0[normal], am0[tng]])
+        assert np.allclose(got0, expect_total, rtol=1e-14, atol=0)
+        # the right-going fluctuation completes the flux difference
+        df = sw_flux(qr, 1.0, normal) - sw_flux(ql, 1.0, normal)
+        assert np.allclose(am + ap, df, rtol=1e-14, atol=1e-12)
+
+
+def _mirror(q, normal):
+    r = np.array(q, dtype=np.float64).copy()
+    r[normal] = -r[normal]
+    return r
+
+
+@pytest.mark.parametrize("normal", [1, 2])
+def test_sw_riemann_mirror_symmetry_with_transonic_states(normal):
+    # Reflecting x -> -x swaps the two cells and negates the normal momentum;
+    # the flux obeys f(Rq) = -R f(q), so the mirrored problem (R q_r, R q_l)
+    # sends left exactly what the original sends right: A-dQ' = R A+dQ and
+    # A+dQ' = R A-dQ.  The Harten-Hyman fix of the 1-wave of one problem is the
+    # fix of the 3-wave of the other, so this pins the 3-wave branch against
+    # the 1-wave branch (whose value is pinned above), on states where each
+    # branch engages.
+    rng = np.random.default_rng(21 + normal)
+    g = 1.0
+    n1 = n3 = 0
+    for _ in range(4000):
+        hl, hr = rng.uniform(0.1, 2.0, 2)
+        ul, ur = rng.uniform(-2.5, 2.5, 2)
+        vl, vr = rng.uniform(-1.0, 1.0, 2)
+        tng = 3 - normal
+        ql = np.zeros(3)
+        qr = np.zeros(3)
+        ql[0], ql[normal], ql[tng] = hl, hl * ul, hl * vl
+        qr[0], qr[normal], qr[tng] = hr, hr * ur, hr * vr
+        W, s, am, ap = oracle.riemann_sw(ql, qr, g, normal, efix=True)
+        Wm, sm, amm, apm = oracle.riemann_sw(_mirror(qr, normal), _mirror(ql, normal), g, normal,
+                                             efix=True)
+        scale = max(1.0, np.abs(am).max(), np.abs(ap).max())
+        assert np.max(np.abs(amm - _mirror(ap, normal))) <= 1e-13 * scale
+        assert np.max(np.abs(apm - _mirror(am, normal))) <= 1e-13 * scale
+        assert np.allclose(sm, -s[::-1], rtol=0, atol=1e-14 * max(1.0, np.abs(s).max()))
+        # count the samples where the fix changes A-dQ against plain Roe, by
+        # the wave whose middle state is transonic
+        plain = (np.minimum(s, 0)[:, None] * W).sum(axis=0)
+        if np.max(np.abs(am - plain)) > 1e-12:
+            h1 = hl + W[0, 0]
+            h3 = hr - W[2, 0]
+            t1 = h1 > 0 and ul - math.sqrt(g * hl) < 0 < (ql[normal] + W[0, normal]) / h1 - math.sqrt(g * h1)
+            t3 = h3 > 0 and (qr[normal] - W[2, normal]) / h3 + math.sqrt(g * h3) < 0 < ur + math.sqrt(g * hr)
+            assert t1 or t3
+            n1 += int(t1)
+            n3 += int(t3)
+    assert n1 > 20 and n3 > 20, (n1, n3)
+
+
 def test_acoustics_waves_and_constant_coefficient_fluctuations():
     rng = np.random.default_rng(3)
     for meqn, normals in ((3, (1, 2)), (4, (1, 2, 3))):
@@ -360,18 +446,20 @@ def test_exact_dam_break_reference_values():
     assert ref2["head"] < 0 < ref2["tail"]
 
 
-def _dam_break_l1_fast(hl, hr, nx, efix=True, t_end=0.4, limiter="mc"):
+def _dam_break_l1_fast(hl, hr, nx, efix=True, t_end=0.4, limiter="mc", mirrored=False):
+    # mirrored: the deep water on the right (h = hr for x < 0, hl for x > 0),
+    # whose exact solution is the original one reflected, h(x) = h_orig(-x)
     prob = _prob2d((nx, 1), (-1, 0), (1, 1), "shallow_water", "extrap", grav=1.0, efix=efix,
                    limiter=limiter)
     x, _, _ = inputs.cell_centers(prob)
     q = np.zeros((3,) + x.shape)
-    q[0] = np.where(x < 0, hl, hr)
+    q[0] = np.where(x < 0, hr, hl) if mirrored else np.where(x < 0, hl, hr)
     smax = 1.0 + math.sqrt(hl)
     nsteps = int(math.ceil(t_end * smax / (0.9 * 2.0 / nx)))
     out, cfl = oracle.advance_fixed(prob, q, None, [t_end / nsteps] * nsteps)
     assert cfl.max() < 1.0
     _, sample = sw_dam_break_exact(hl, hr)
-    h_ex, _ = sample(x[0, 0] / t_end)
+    h_ex, _ = sample((-x[0, 0] if mirrored else x[0, 0]) / t_end)
     dx = 2.0 / nx
     return dx * np.abs(out[0, 0, 0] - h_ex).sum(), out[0, 0, 0], x[0, 0]
 
@@ -404,6 +492,31 @@ def test_transonic_dam_break_entropy_fix():
     assert all(a < b for a, b in zip(l1_fix, l1_nofix))
     assert jumps_nofix[-1] > 0.03                  # glitch persists without the fix
     assert jumps_fix[-1] < 0.6 * jumps_fix[0] / 2  # shrinks at least like dx with it
+    assert jumps_fix[-1] < 0.2 * jumps_nofix[-1]
+
+
+def test_mirrored_transonic_dam_break_entropy_fix():
+    # deep water on the right (h = 0.1 | 1): the transonic rarefaction is now a
+    # 3-wave, so this runs the 3-wave branch of the fix end to end
+    ns = [400, 800, 1600]
+    errs = [_dam_break_l1_fast(1.0, 0.1, n, efix=True, mirrored=True)[0] for n in ns]
+    assert errs[0] > errs[1] > errs[2]
+    assert observed_order(errs, ns) >= 0.7
+    jumps_fix, jumps_nofix, l1_fix, l1_nofix = [], [], [], []
+    for n in (200, 400, 800):
+        e1, h1, x = _dam_break_l1_fast(1.0, 0.1, n, efix=True, limiter="first_order", mirrored=True)
+        e0, h0, _ = _dam_break_l1_fast(1.0, 0.1, n, efix=False, limiter="first_order", mirrored=True)
+        near = np.abs(x[:-1]) < 0.05
+        jumps_fix.append(np.max(np.abs(np.diff(h1))[near]))
+        jumps_nofix.append(np.max(np.abs(np.diff(h0))[near]))
+        l1_fix.append(e1)
+        l1_nofix.append(e0)
+        # the scheme is mirror symmetric: the reflected original run, per cell
+        e_orig, h_orig, _ = _dam_break_l1_fast(1.0, 0.1, n, efix=True, limiter="first_order")
+        assert np.max(np.abs(h1 - h_orig[::-1])) <= 1e-13
+    assert all(a < b for a, b in zip(l1_fix, l1_nofix))
+    assert jumps_nofix[-1] > 0.03
+    assert jumps_fix[-1] < 0.6 * jumps_fix[0] / 2
     assert jumps_fix[-1] < 0.2 * jumps_nofix[-1]
 
 
