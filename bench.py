@@ -1,8 +1,11 @@
 """Throughput benchmark of the split wave-propagation step on one MI355X.
 
 Workload (default): 2D shallow water, Roe solver with entropy fix, MC limiter,
-2048 x 2048 cells on [-2.5, 2.5]^2, radial dam break with seeded +-1e-3 noise
-on h, reflecting walls, CFL 0.9, FP32.  A step is one adaptive time step of
+8192 x 8192 cells on [-2.5, 2.5]^2 (768 MiB per state, beyond the 256 MB
+MALL, so the bandwidth figure is an HBM figure), radial dam break with seeded
++-1e-3 noise on h, reflecting walls, CFL 0.9, FP32.  The 2048 x 2048
+configuration (whose working set stays in the MALL) runs next and is reported
+under "mall_resident_2048".  A step is one adaptive time step of
 the whole path: x sweep, y sweep (Riemann solve, limiter, correction flux,
 update, fused speed maximum) and the device CFL control.  The timed region is
 K steps run from captured HIP graphs (claw_advance) with the state resident
@@ -79,13 +82,35 @@ def load_traffic(path, kernel_class, source_hash):
 VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
+def host_cpu():
+    """Model name and clock of the host CPU (from /proc/cpuinfo and sysfs)."""
+    model, mhz = None, []
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name") and model is None:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("cpu MHz"):
+                    mhz.append(float(line.split(":", 1)[1]))
+    except OSError:
+        pass
+    max_mhz = None
+    try:
+        with open("/sys/devices/system/cpu/cpu0/cpufreq/cpuinfo_max_freq") as fh:
+            max_mhz = int(fh.read().strip()) / 1000.0
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model, "cpu_mhz_now_mean": (sum(mhz) / len(mhz)) if mhz else None,
+            "cpu_mhz_max": max_mhz, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(prob, q0, steps, aux=None):
     import oracle
     t0 = time.perf_counter()
     res = oracle.advance(prob, q0, aux, steps)
     dt = time.perf_counter() - t0
     ncell = prob["n"][0] * prob["n"][1] * prob["n"][2]
-    return {
+    out = {
         "value": ncell * steps / dt / 1e9,
         "unit": "Gcell-updates/s",
         "cores": oracle.num_threads(),
@@ -93,6 +118,8 @@ def cpu_baseline(prob, q0, steps, aux=None):
         "sample": f"first {steps} adaptive steps ({steps + res['nreject']} trials) of the same "
                   f"{'x'.join(str(v) for v in prob['n'][:prob['ndim']])} workload, FP64 oracle, {dt:.2f} s",
     }
+    out.update(host_cpu())
+    return out
 
 
 def achievable_bandwidth(torch, claw, nbytes=1 << 30, reps=10):
@@ -261,8 +288,9 @@ def bench_plugin(args, torch, claw, inputs):
     """Point-wise solver plug-ins at 2048^2 FP32: the scalar Burgers-type law
     (one field, one wave), and shallow water through the plug-in path next to
     the specialised shallow-water sweep on the same dam break."""
-    n = args.n
-    steps, warmup = args.steps, args.warmup
+    n = args.n if args.n_given else 2048
+    steps = args.steps if args.steps_given else 1000
+    warmup = args.warmup if args.warmup_given else 3000
     prob, q0, _ = inputs.burgers2d(n=n, seed=0, dtype=args.dtype, nsteps=steps)
     print(f"# burgers {n}^2 {args.dtype}", file=sys.stderr, flush=True)
     bur = _timed_run(torch, claw, prob, q0, steps, warmup, args.timed_steps)
@@ -292,14 +320,14 @@ def bench_plugin(args, torch, claw, inputs):
         "plugin_over_specialised": gen["value"] / spec["value"],
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps or max(2, int(round(1e9 / ncell))))
     return line
 
 
 def bench_ac3d(args, torch, claw, inputs):
     """3D linear acoustics in a two-layer medium, 256^3 FP32 (per-cell rho, K):
     throughput of the adaptive graph path and the slowest sweep against HBM."""
-    n = 256 if args.n == 2048 else args.n
+    n = args.n if args.n_given else 256
     steps = args.steps if args.steps_given else 200
     warmup = args.warmup if args.warmup_given else 200
     prob, q0, aux = inputs.acoustics3d_layers(n=n, dtype=args.dtype, nsteps=steps)
@@ -337,7 +365,7 @@ def bench_ac3d(args, torch, claw, inputs):
         "kernel_avg_us": avg_us, "rejected_trials": nrej,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, q0, min(args.cpu_steps, 10), aux)
+        line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps or 10, aux)
     return line
 
 
@@ -386,16 +414,17 @@ def bench_dpsp(args, torch, claw, inputs):
     n = 1024
     steps = args.steps if args.steps_given else 500
     warmup = args.warmup if args.warmup_given else 1500
+    cpu_steps = args.cpu_steps or 150
     out = {}
     for dt in ("f64", "f32"):
         prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=dt, nsteps=steps)
         print(f"# dpsp {n}^2 {dt}: gpu", file=sys.stderr, flush=True)
         g = _timed_run(torch, claw, prob, q0, steps, warmup, args.timed_steps)
-        print(f"# dpsp {n}^2 {dt}: oracle {args.cpu_steps} steps", file=sys.stderr, flush=True)
+        print(f"# dpsp {n}^2 {dt}: oracle {cpu_steps} steps", file=sys.stderr, flush=True)
         t0 = time.perf_counter()
-        oracle.advance(prob, q0, None, args.cpu_steps, precision=dt)
+        oracle.advance(prob, q0, None, cpu_steps, precision=dt)
         el = time.perf_counter() - t0
-        cpu = n * n * args.cpu_steps / el / 1e9
+        cpu = n * n * cpu_steps / el / 1e9
         out[dt] = {"gpu_Gcell_per_s": g["value"], "gpu_kernel_avg_us": g["kernel_avg_us"],
                    "oracle_Gcell_per_s": cpu, "oracle_seconds": el, "gpu_over_oracle": g["value"] / cpu}
     return {
@@ -409,24 +438,27 @@ def bench_dpsp(args, torch, claw, inputs):
         "results": out,
         "fp32_over_fp64_gpu": out["f32"]["gpu_Gcell_per_s"] / out["f64"]["gpu_Gcell_per_s"],
         "cpu_cores": oracle.num_threads(),
-        "cpu_sample": f"first {args.cpu_steps} adaptive steps of each precision",
+        "cpu_sample": f"first {cpu_steps} adaptive steps of each precision",
     }
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=3000,
-                    help="untimed steps first (also lets the GPU clocks ramp up)")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 100 at 8192^2, the 2048^2 configuration's 1000)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (also lets the GPU clocks ramp up); default 300 / 3000")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--n", type=int, default=8192,
+                    help="grid side of the headline run (8192: beyond the MALL; 2048 also runs, as extra keys)")
     ap.add_argument("--timed-steps", type=int, default=200,
                     help="steps of the per-kernel event timing run")
     ap.add_argument("--reps", type=int, default=5,
                     help="timed repetitions of the steps from the initial state (median reported)")
-    ap.add_argument("--cpu-steps", type=int, default=150,
-                    help="oracle steps of the CPU baseline sample (about 10 s on 16 threads)")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="oracle steps of the CPU baseline sample (default: about 1e9 cell-updates, "
+                         "10-20 s on 16 threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
     ap.add_argument("--traffic-file", default=None)
@@ -437,8 +469,9 @@ def main():
     ap.add_argument("--train-runs", type=int, default=200, help="learned: training runs")
     ap.add_argument("--eval-seeds", type=int, default=5, help="learned: held-out evaluation seeds")
     args = ap.parse_args()
-    args.steps_given = "--steps" in sys.argv
-    args.warmup_given = "--warmup" in sys.argv
+    args.steps_given = args.steps is not None
+    args.warmup_given = args.warmup is not None
+    args.n_given = "--n" in sys.argv
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the "
@@ -470,7 +503,42 @@ def main():
         print(json.dumps(bench_dpsp(args, torch, claw, inputs)), flush=True)
         return
 
-    prob, q0, _ = inputs.sw_radial_dam(n=args.n, dtype=args.dtype, nsteps=args.steps)
+    n = args.n
+    steps = args.steps if args.steps_given else (100 if n >= 4096 else 1000)
+    warmup = args.warmup if args.warmup_given else (300 if n >= 4096 else 3000)
+    line = bench_grid(args, torch, claw, inputs, n, steps, warmup, headline=True)
+    if n != 2048:
+        # the 2048^2 configuration itself (its 3 x 48 MiB working set stays in
+        # the 256 MB MALL, so its bandwidth figure is not an HBM figure)
+        st2 = args.steps if args.steps_given else 1000
+        wu2 = args.warmup if args.warmup_given else 3000
+        line["mall_resident_2048"] = bench_grid(args, torch, claw, inputs, 2048, st2, wu2, headline=False)
+    if not args.no_copy_bw:
+        bw = achievable_bandwidth(torch, claw)
+        line["achievable_GBps"] = bw
+        best_rw = max(bw["copy"], bw["copy_nt"])
+        line["roofline"]["frac_of_achievable_copy"] = line["roofline"]["achieved"] / best_rw
+        # the same copy kernels at one sweep's size (one state read, one written),
+        # back to back like the sweeps: launch gaps and ramp included
+        alg_bytes = line["roofline"]["alg_bytes_per_launch"]
+        bw_s = achievable_bandwidth(torch, claw, nbytes=alg_bytes // 2, reps=50 if n >= 4096 else 200)
+        line["achievable_GBps_sweep_size"] = bw_s
+        line["roofline"]["frac_of_copy_at_sweep_size"] = line["roofline"]["achieved"] / max(
+            bw_s["copy"], bw_s["copy_nt"])
+    if not args.no_cpu_baseline:
+        prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=args.dtype, nsteps=steps)
+        csteps = args.cpu_steps if args.cpu_steps else max(2, int(round(1e9 / (n * n))))
+        print(f"# cpu baseline: oracle on {csteps} steps of {n}^2", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(prob, q0, csteps)
+    print(json.dumps(line), flush=True)
+
+
+def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):
+    """The radial dam break at n^2: `steps` adaptive steps from t = 0 timed
+    (median of the repetitions), per-kernel event times over a second run,
+    the dominant sweep against HBM.  headline: the full bench line, else the
+    figures only."""
+    prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=args.dtype, nsteps=steps)
     prob["fused_step"] = args.fused_step
     ncell = prob["n"][0] * prob["n"][1]
     real_bytes = 4 if args.dtype == "f32" else 8
@@ -478,12 +546,12 @@ def main():
     q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
     solver = claw.Solver(prob, q, None)
 
-    print(f"# workload sw_radial_dam {args.n}^2 {args.dtype}: warmup {args.warmup} steps, then "
-          f"the timed steps from t = 0", file=sys.stderr, flush=True)
+    print(f"# workload sw_radial_dam {n}^2 {args.dtype}: warmup {warmup} steps, then "
+          f"{steps} timed steps from t = 0", file=sys.stderr, flush=True)
     # each repetition times the configuration's steps from the initial state;
     # the reported time is the median repetition
     q_init = q.clone()
-    restart_after_warmup(torch, solver, q, args.warmup)
+    restart_after_warmup(torch, solver, q, warmup)
     times = []
     for rep in range(args.reps):
         if rep > 0:
@@ -491,17 +559,18 @@ def main():
             solver.set_control(0.0, 0.0)
             torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, nrej = solver.advance(args.steps)
+        _, nrej = solver.advance(steps)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     elapsed = sorted(times)[len(times) // 2]
-    value = ncell * args.steps / elapsed / 1e9
-    print(f"# timed {args.steps} steps from t = 0, {args.reps} repetitions: median {elapsed:.4f} s, "
+    value = ncell * steps / elapsed / 1e9
+    print(f"# timed {steps} steps from t = 0, {args.reps} repetitions: median {elapsed:.4f} s, "
           f"min {min(times):.4f} s, max {max(times):.4f} s ({nrej} rejected trials)",
           file=sys.stderr, flush=True)
 
     # per-kernel durations with HIP events on the solver's stream
-    ms, cnt = solver.advance_timed(args.timed_steps)
+    timed = args.timed_steps if n < 4096 else min(args.timed_steps, 100)
+    ms, cnt = solver.advance_timed(timed)
     names = ["x_sweep", "y_sweep", "z_sweep", "control"]
     if args.fused_step:
         names[0] = "step2d"  # one fused kernel per step: same algorithmic bytes per launch
@@ -511,31 +580,24 @@ def main():
     alg_bytes = 2 * 3 * real_bytes * ncell
     dom_s = ms[dom] / cnt[dom] * 1e-3
     achieved = alg_bytes / dom_s / 1e9
-    pmc_file = args.traffic_file or os.path.join(ROOT, "profiles", f"pmc_sweeps_sw{args.n}_{args.dtype}.txt")
+    pmc_file = args.traffic_file or os.path.join(ROOT, "profiles", f"pmc_sweeps_sw{n}_{args.dtype}.txt")
     traffic = load_traffic(pmc_file, names[dom], kernel_source_hash())
     valu = load_pmc(pmc_file, names[dom], "valu_insts", kernel_source_hash())
     print(f"# kernel averages (us): {avg_us}", file=sys.stderr, flush=True)
+    solver.close()
+    del q, q_init
+    torch.cuda.empty_cache()
 
-    line = {
-        "metric": "Gcell-updates/s + % HBM roofline",
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                "kernel": names[dom], "alg_bytes_per_launch": alg_bytes,
+                "avg_launch_us": dom_s * 1e6}
+    figures = {
         "value": value,
-        "unit": "Gcell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic (seeded radial dam break + U(-1e-3,1e-3) noise on h)",
-        "config": {"workload": "2D shallow water Roe+entropy fix, MC limiter, radial dam break, "
-                               "reflecting walls, CFL 0.9",
-                   "grid": [args.n, args.n], "cells": ncell, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": names[dom], "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": dom_s * 1e6},
+        "ms_per_step": elapsed / steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "roofline": roofline,
         "kernel_avg_us": avg_us,
         # the same kernel against the VALU issue rate: SQ_INSTS_VALU (wave
         # instructions per launch, committed PMC summary) x 64 lanes over the
@@ -548,22 +610,29 @@ def main():
         "rejected_trials": nrej,
         "repetitions": {"count": args.reps, "seconds": times},
     }
-    solver.close()
-    del q
-    if not args.no_copy_bw:
-        bw = achievable_bandwidth(torch, claw)
-        line["achievable_GBps"] = bw
-        best_rw = max(bw["copy"], bw["copy_nt"])
-        line["roofline"]["frac_of_achievable_copy"] = achieved / best_rw
-        # the same copy kernels at one sweep's size (one state read, one written),
-        # back to back like the sweeps: launch gaps and ramp included
-        bw_s = achievable_bandwidth(torch, claw, nbytes=alg_bytes // 2, reps=200)
-        line["achievable_GBps_sweep_size"] = bw_s
-        line["roofline"]["frac_of_copy_at_sweep_size"] = achieved / max(bw_s["copy"], bw_s["copy_nt"])
-    if not args.no_cpu_baseline:
-        print(f"# cpu baseline: oracle on {args.cpu_steps} steps", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps)
-    print(json.dumps(line), flush=True)
+    if not headline:
+        figures["grid"] = [n, n]
+        return figures
+    line = {
+        "metric": "Gcell-updates/s + % HBM roofline",
+        "value": value,
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded radial dam break + U(-1e-3,1e-3) noise on h)",
+        "config": {"workload": f"2D shallow water Roe+entropy fix, MC limiter, radial dam break, "
+                               f"reflecting walls, CFL 0.9, {n}x{n}"
+                               + (" (working set beyond the 256 MB MALL)" if n >= 4096 else ""),
+                   "grid": [n, n], "cells": ncell, "parallelism": "single GPU"},
+    }
+    line.update({k: v for k, v in figures.items() if k not in ("value", "ms_per_step", "steps", "warmup")})
+    return line
 
 
 if __name__ == "__main__":

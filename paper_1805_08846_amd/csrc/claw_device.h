@@ -59,6 +59,7 @@ struct StepState {
     int32_t result_off;  // buffer offset of the trial's result
     int32_t pad;
     long long accepted, rejected, target, consecutive, trials;
+    long long base_accepted, base_rejected;  // counts when the current target was set
 };
 
 // Per parity and direction the largest |s| is kept in SMAX_SLOTS slots on
@@ -111,7 +112,8 @@ struct SweepArgs {
     int32_t parity;     // trial parity: step-state copy and speed slots in use
     int32_t first;      // this sweep opens a trial (decides the previous one)
     int32_t last;       // this sweep closes a trial (clears the other parity's slots)
-    int32_t pad;
+    int32_t auto_dt;    // speed pass of an adaptive start: skipped when the step
+                        // state already holds a next step (dt_next > 0)
     R grav;
     R sqrt_grav;
     R Z0, c0;           // constant-coefficient acoustics

@@ -40,7 +40,7 @@ hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desi
 hipError_t launch_commit(Ctrl* c, int q, bool fp32, hipStream_t s);
 hipError_t launch_begin(Ctrl* c, int q, double dt, int mode, int result_off, hipStream_t s);
 hipError_t launch_zero_speeds(Ctrl* c, int q, hipStream_t s);
-hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, hipStream_t s);
+hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, bool use_next, hipStream_t s);
 hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s);
 hipError_t launch_set_control(Ctrl* c, int q, double t, double dt_next, hipStream_t s);
 

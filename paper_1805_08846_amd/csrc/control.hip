@@ -25,6 +25,7 @@ __global__ void k_ctrl_init(Ctrl* c, double dx0, double dx1, double dx2, int ndi
         s.cur = s.done = s.err = s.last_accepted = s.pending = s.mode = s.pad = 0;
         s.result_off = result_off;
         s.accepted = s.rejected = s.target = s.consecutive = s.trials = 0;
+        s.base_accepted = s.base_rejected = 0;
         clear_speeds(c, q);
         c->nonphys[q] = 0;
     }
@@ -67,14 +68,20 @@ __global__ void k_zero_speeds(Ctrl* c, int q) {
     c->nonphys[q] = 0;
 }
 
-// First trial step from the speed-only pass that filled slot q.
-__global__ void k_init_dt(Ctrl* c, int q, int fp32, int mode, int result_off) {
+// First trial step from the speed-only pass that filled slot q; with
+// use_next, the next step a previous run left (dt_next > 0) if there is one
+// (the speed pass then skipped its work).
+__global__ void k_init_dt(Ctrl* c, int q, int fp32, int mode, int result_off, int use_next) {
     StepState& s = c->st[q];
     s.mode = mode;
     s.result_off = result_off;
     s.pending = 0;
     s.done = 0;
     s.err = 0;
+    if (use_next && s.dt_next > 0.0) {
+        set_trial_dt(c, s, s.dt_next);
+        return;
+    }
     if (c->nonphys[q]) {
         s.err = 5;
         s.done = 1;
@@ -92,6 +99,8 @@ __global__ void k_init_dt(Ctrl* c, int q, int fp32, int mode, int result_off) {
 __global__ void k_set_target(Ctrl* c, int q, long long nsteps) {
     StepState& s = c->st[q];
     s.target = s.accepted + nsteps;
+    s.base_accepted = s.accepted;
+    s.base_rejected = s.rejected;
     s.done = nsteps <= 0 ? 1 : 0;
     s.consecutive = 0;
 }
@@ -143,8 +152,9 @@ hipError_t launch_zero_speeds(Ctrl* c, int q, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_speeds, dim3(1), dim3(1), 0, s, c, q);
     return hipGetLastError();
 }
-hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, s, c, q, fp32 ? 1 : 0, mode, result_off);
+hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, bool use_next, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_dt, dim3(1), dim3(1), 0, s, c, q, fp32 ? 1 : 0, mode, result_off,
+                       use_next ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s) {

@@ -41,7 +41,11 @@ claw_status fail(claw_status s, const char* fmt, ...) {
     } while (0)
 
 constexpr size_t kAlign = 4096;
-constexpr int kGraphSteps = 32;  // trial steps per captured graph
+constexpr int kGraphSteps = 32;  // trial steps per captured graph (batched ensembles)
+// Trial counts of the captured single-grid graphs: a call replays a
+// decomposition of the trials it needs (greedy, largest first), so a short
+// advance dispatches no trial beyond its step count.
+constexpr int kLadder[4] = {32, 8, 2, 1};
 
 size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -132,9 +136,9 @@ struct claw_solver {
     void* zc;
     Ctrl* ctrl;
     double dx[3];
-    int parity;               // parity of the next trial; copy parity ^ 1 is the committed state
-    hipGraphExec_t gexec[2];  // captured trial sequences, by starting parity
-    hipGraph_t graph[2];
+    int parity;                  // parity of the next trial; copy parity ^ 1 is the committed state
+    hipGraphExec_t gexec[4][2];  // captured trial sequences, by ladder rung and starting parity
+    hipGraph_t graph[4][2];
     std::vector<hipEvent_t> events;
     hipGraphExec_t lc_exec;  // captured learned steps and the arguments they were captured with
     hipGraph_t lc_graph;
@@ -316,6 +320,14 @@ claw_status read_ctrl(claw_solver* h, Ctrl* out) {
     return CLAW_OK;
 }
 
+// The committed step state only (one small copy and one stream synchronisation).
+claw_status read_state(claw_solver* h, StepState* out) {
+    HIP_TRY(hipMemcpyAsync(out, &h->ctrl->st[committed(h)], sizeof(StepState), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return CLAW_OK;
+}
+
 claw_status sync_state(claw_solver* h) {
     if (h->fp32)
         HIP_TRY(launch_sync_state<float>(h->ctrl, committed(h), (float*)h->buf[0], (float*)h->buf[1],
@@ -327,12 +339,24 @@ claw_status sync_state(claw_solver* h) {
 }
 
 // Speed-only pass on the committed state into the committed copy's slots
-// (call after commit()).
-claw_status speed_pass(claw_solver* h) {
+// (call after commit()).  auto_dt: the pass skips its work when the committed
+// copy already holds a next step (dt_next > 0).
+claw_status speed_pass(claw_solver* h, bool auto_dt = false) {
     const int q = committed(h);
     HIP_TRY(launch_zero_speeds(h->ctrl, q, h->stream));
-    for (int dir = 0; dir < h->d.ndim; ++dir)
-        HIP_TRY(enqueue_sweep(h, dir, 0, 0, true, q, false, false, h->stream));
+    for (int dir = 0; dir < h->d.ndim; ++dir) {
+        if (h->fp32) {
+            SweepArgs<float> a = sweep_args<float>(h, dir, 0, 0);
+            a.parity = q;
+            a.auto_dt = auto_dt ? 1 : 0;
+            HIP_TRY(launch_sweep<float>(a, h->sys, h->d.meqn, true, h->stream));
+        } else {
+            SweepArgs<double> a = sweep_args<double>(h, dir, 0, 0);
+            a.parity = q;
+            a.auto_dt = auto_dt ? 1 : 0;
+            HIP_TRY(launch_sweep<double>(a, h->sys, h->d.meqn, true, h->stream));
+        }
+    }
     return CLAW_OK;
 }
 
@@ -354,7 +378,8 @@ double smax_value(const claw_solver* h, const Ctrl& c, int q, int dir) {
 }
 
 // First trial step of an adaptive run (call after commit()): dt0, else the
-// dt_next of a previous run, else cfl_desired / sigma of a speed pass.
+// dt_next of a previous run, else cfl_desired / sigma of a speed pass.  The
+// choice between the last two is made on the device (no host round trip).
 claw_status begin_adaptive(claw_solver* h, double dt0) {
     const int q = committed(h);
     const int roff = result_offset_of(h);
@@ -362,16 +387,9 @@ claw_status begin_adaptive(claw_solver* h, double dt0) {
         HIP_TRY(launch_begin(h->ctrl, q, dt0, MODE_ADAPT, roff, h->stream));
         return CLAW_OK;
     }
-    Ctrl c;
-    claw_status st = read_ctrl(h, &c);
+    claw_status st = speed_pass(h, true);
     if (st) return st;
-    if (c.st[q].dt_next > 0) {
-        HIP_TRY(launch_begin(h->ctrl, q, c.st[q].dt_next, MODE_ADAPT, roff, h->stream));
-        return CLAW_OK;
-    }
-    st = speed_pass(h);
-    if (st) return st;
-    HIP_TRY(launch_init_dt(h->ctrl, q, h->fp32, MODE_ADAPT, roff, h->stream));
+    HIP_TRY(launch_init_dt(h->ctrl, q, h->fp32, MODE_ADAPT, roff, true, h->stream));
     return CLAW_OK;
 }
 
@@ -382,14 +400,14 @@ claw_status ctrl_status(const StepState& c) {
     return CLAW_OK;
 }
 
-// Graph of kGraphSteps trials starting at the current parity (an even count,
-// so the parity after a replay is the parity before it).
-claw_status ensure_graph(claw_solver* h) {
+// Graph of kLadder[r] trials starting at the current parity (captured once
+// per rung and starting parity).
+claw_status ensure_graph(claw_solver* h, int r) {
     const int p = h->parity;
-    if (h->gexec[p]) return CLAW_OK;
+    if (h->gexec[r][p]) return CLAW_OK;
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     claw_status st = CLAW_OK;
-    for (int k = 0; k < kGraphSteps && st == CLAW_OK; ++k) st = enqueue_trial(h, h->cap_stream, nullptr);
+    for (int k = 0; k < kLadder[r] && st == CLAW_OK; ++k) st = enqueue_trial(h, h->cap_stream, nullptr);
     h->parity = p;
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
@@ -398,13 +416,27 @@ claw_status ensure_graph(claw_solver* h) {
         return st;
     }
     if (e != hipSuccess) return fail(CLAW_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec[p], g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&h->gexec[r][p], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(g);
-        h->gexec[p] = nullptr;
+        h->gexec[r][p] = nullptr;
         return fail(CLAW_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    h->graph[p] = g;
+    h->graph[r][p] = g;
+    return CLAW_OK;
+}
+
+// Enqueues exactly `trials` trial steps as replays of the captured graphs.
+claw_status replay_trials(claw_solver* h, int64_t trials) {
+    for (int r = 0; r < 4; ++r) {
+        while (trials >= kLadder[r]) {
+            claw_status st = ensure_graph(h, r);
+            if (st) return st;
+            HIP_TRY(hipGraphLaunch(h->gexec[r][h->parity], h->stream));
+            h->parity ^= kLadder[r] & 1;
+            trials -= kLadder[r];
+        }
+    }
     return CLAW_OK;
 }
 
@@ -537,10 +569,9 @@ claw_status claw_step(claw_solver* h, double dt, double* cfl) {
     st = enqueue_trial(h, h->stream, nullptr);
     if (!st) st = commit(h);
     if (st || !cfl) return st;
-    Ctrl c;
-    st = read_ctrl(h, &c);
+    StepState S;
+    st = read_state(h, &S);
     if (st) return st;
-    const StepState& S = c.st[committed(h)];
     *cfl = S.cfl;
     st = ctrl_status(S);
     if (st) return st;
@@ -568,46 +599,36 @@ claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax) {
     return CLAW_OK;
 }
 
+// The adaptive loop: one speed pass (skipped when a previous run left the
+// next step), then as many trials as steps are asked for, replayed from the
+// graph ladder; the state is copied back into q and the committed step state
+// read once.  A rejected trial leaves one step to do, so the loop repeats with
+// that many trials (each repetition costs one more read).
 claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t, int64_t* nreject) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
     claw_status st = commit(h);
     if (st) return st;
-    Ctrl c0;
-    st = read_ctrl(h, &c0);
-    if (st) return st;
-    const long long rej0 = c0.st[committed(h)].rejected, acc0 = c0.st[committed(h)].accepted;
     if (nsteps > 0) {
         st = begin_adaptive(h, dt0);
         if (st) return st;
-        HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
-        st = ensure_graph(h);
-        if (st) return st;
-        int64_t remaining = nsteps;
-        for (int round = 0; round < 1000; ++round) {
-            const int64_t reps = (remaining + kGraphSteps - 1) / kGraphSteps;
-            for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec[h->parity], h->stream));
-            st = commit(h);
-            if (st) return st;
-            Ctrl c;
-            st = read_ctrl(h, &c);
-            if (st) return st;
-            const StepState& S = c.st[committed(h)];
-            if (S.err) return ctrl_status(S);
-            if (S.done) break;
-            remaining = S.target - S.accepted;
-            if (remaining <= 0) break;
-        }
     }
-    st = sync_state(h);
-    if (st) return st;
-    Ctrl c;
-    st = read_ctrl(h, &c);
-    if (st) return st;
-    const StepState& S = c.st[committed(h)];
+    HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
+    int64_t remaining = nsteps;
+    StepState S;
+    for (int round = 0; round < 1000; ++round) {
+        st = replay_trials(h, remaining);
+        if (!st) st = commit(h);
+        if (!st) st = sync_state(h);
+        if (!st) st = read_state(h, &S);
+        if (st) return st;
+        if (S.err) return ctrl_status(S);
+        remaining = S.target - S.accepted;
+        if (S.done || remaining <= 0) break;
+    }
     if (t) *t = S.t;
-    if (nreject) *nreject = S.rejected - rej0;
-    if (S.accepted - acc0 != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
+    if (nreject) *nreject = S.rejected - S.base_rejected;
+    if (S.accepted - S.base_accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
     return CLAW_OK;
 }
 
@@ -625,18 +646,14 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
         st = commit(h);
         if (st) return st;
         HIP_TRY(launch_begin(h->ctrl, committed(h), dts[0], MODE_FIXED, result_offset_of(h), h->stream));
-        st = ensure_graph(h);
-        if (st) return st;
-        const int64_t reps = nsteps / kGraphSteps;
-        for (int64_t r = 0; r < reps; ++r) HIP_TRY(hipGraphLaunch(h->gexec[h->parity], h->stream));
-        for (int64_t k = reps * kGraphSteps; k < nsteps && st == CLAW_OK; ++k) st = enqueue_trial(h, h->stream, nullptr);
+        st = replay_trials(h, nsteps);
         if (!st) st = commit(h);
         if (!st) st = sync_state(h);
         if (st) return st;
-        Ctrl c;
-        st = read_ctrl(h, &c);
+        StepState S;
+        st = read_state(h, &S);
         if (st) return st;
-        return ctrl_status(c.st[committed(h)]);
+        return ctrl_status(S);
     }
     for (int64_t k = 0; k < nsteps; ++k) {
         st = commit(h);
@@ -651,10 +668,10 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
     }
     st = sync_state(h);
     if (st) return st;
-    Ctrl c;
-    st = read_ctrl(h, &c);
+    StepState S;
+    st = read_state(h, &S);
     if (st) return st;
-    return ctrl_status(c.st[committed(h)]);
+    return ctrl_status(S);
 }
 
 claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms, int64_t* launches) {
@@ -727,10 +744,9 @@ claw_status claw_get_control(claw_solver* h, double* t, double* dt_next, int64_t
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     claw_status st = commit(h);
     if (st) return st;
-    Ctrl c;
-    st = read_ctrl(h, &c);
+    StepState S;
+    st = read_state(h, &S);
     if (st) return st;
-    const StepState& S = c.st[committed(h)];
     if (t) *t = S.t;
     if (dt_next) *dt_next = S.dt_next;
     if (accepted) *accepted = S.accepted;
@@ -750,10 +766,11 @@ claw_status claw_set_control(claw_solver* h, double t, double dt_next) {
 claw_status claw_destroy(claw_solver* h) {
     if (!h) return CLAW_OK;
     hipError_t e = hipStreamSynchronize(h->stream);
-    for (int p = 0; p < 2; ++p) {
-        if (h->gexec[p]) (void)hipGraphExecDestroy(h->gexec[p]);
-        if (h->graph[p]) (void)hipGraphDestroy(h->graph[p]);
-    }
+    for (int r = 0; r < 4; ++r)
+        for (int p = 0; p < 2; ++p) {
+            if (h->gexec[r][p]) (void)hipGraphExecDestroy(h->gexec[r][p]);
+            if (h->graph[r][p]) (void)hipGraphDestroy(h->graph[r][p]);
+        }
     if (h->lc_exec) (void)hipGraphExecDestroy(h->lc_exec);
     if (h->lc_graph) (void)hipGraphDestroy(h->lc_graph);
     for (hipEvent_t ev : h->events) (void)hipEventDestroy(ev);

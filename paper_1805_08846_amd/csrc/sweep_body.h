@@ -184,6 +184,9 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     const int width = tail_blk ? tg.width : 64;
     const int S = tail_blk ? tg.rows : 1;
     if (by * 4 * RPW * S >= a.nrows) return;  // a block past the last row (whole block)
+    if constexpr (SPEEDS) {
+        if (a.auto_dt && a.ctrl->st[a.parity].dt_next > 0.0) return;  // next step already known
+    }
     // The buffer of this trial is known before the previous trial is decided
     // unless that trial gets reverted: load from the predicted buffer first so
     // the decision's latency overlaps the loads, and reload on a mismatch.
@@ -363,6 +366,9 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     constexpr int TNG = SYS == SYS_SW ? 3 - NRM : 0;
     constexpr int dir = NRM - 1;  // the normal component of direction d is q[d + 1]
     constexpr int NC = contrib_width<SYS>();
+    if constexpr (SPEEDS) {
+        if (a.auto_dt && a.ctrl->st[a.parity].dt_next > 0.0) return;  // next step already known
+    }
     const Trial<R> tr = open_trial(a, dir, lead);
     if (tr.done && !SPEEDS) return;
     const R* __restrict__ src = pick_buf(a, (tr.cur + a.src_off) % 3);

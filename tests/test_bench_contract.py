@@ -36,8 +36,12 @@ def test_headline_line():
     r = d["roofline"]
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
     assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12 and 0 < r["frac"] < 1
+    assert d["config"]["grid"] == [8192, 8192]
+    m = d["mall_resident_2048"]
+    assert m["grid"] == [2048, 2048] and m["value"] > 0 and 0 < m["roofline"]["frac"] < 1
     c = d["cpu_baseline"]
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["value"] > 0 and c["sample"]
+    assert "cpu_model" in c and "cpu_mhz_max" in c
 
 
 def test_more_than_one_gpu_is_refused():

@@ -300,6 +300,30 @@ def test_resume_equals_single_run_bitwise(claw):
     assert c1["t"] == c2["t"] and c1["dt_next"] == c2["dt_next"]
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_advance_in_odd_pieces_equals_one_call_bitwise(claw, dtype):
+    # calls of 1, 2, 3, 5, 8, 13 and 41 steps replay every rung of the graph
+    # ladder (32, 8, 2, 1 trials) from both trial parities; together they equal
+    # one call of the same 73 steps, and a call of 0 steps changes nothing
+    prob, q0, _ = inputs.sw_radial_dam(n=144, dtype=dtype, seed=16)
+    s1, q1 = _solver(claw, prob, q0)
+    t_sum = 0.0
+    for k in (1, 2, 3, 5, 8, 13, 41):
+        t_sum, _ = s1.advance(k)
+    t0, r0 = s1.advance(0)
+    assert t0 == t_sum and r0 == 0
+    s2, q2 = _solver(claw, prob, q0)
+    t_one, _ = s2.advance(73)
+    assert np.array_equal(_host(q1), _host(q2))
+    c1, c2 = s1.control(), s2.control()
+    assert c1["t"] == c2["t"] == t_one and c1["dt_next"] == c2["dt_next"]
+    assert c1["accepted"] == c2["accepted"] == 73
+    ref = oracle.advance(prob, q0, None, 73)
+    assert rel_linf(_host(q1), ref["q"])[0] <= TOL[dtype]
+    s1.close()
+    s2.close()
+
+
 def test_graph_path_equals_eager_path_bitwise(claw):
     prob, q0, _ = inputs.sw_radial_dam(n=150, dtype="f64", seed=10)
     s1, q1 = _solver(claw, prob, q0)
