@@ -426,6 +426,39 @@ claw_status ensure_graph(claw_solver* h, int r) {
     return CLAW_OK;
 }
 
+// Fills the handle for a validated descriptor d over the state q and a
+// workspace laid out by plan p at ws; no device work.
+void bind_solver(claw_solver* h, const claw_desc* d, const Plan& p, void* q, char* ws, hipStream_t stream) {
+    h->d = *d;
+    h->plan = p;
+    h->fp32 = d->dtype == CLAW_FP32;
+    h->sys = d->riemann >= CLAW_RP_PLUGIN_BASE ? d->riemann
+             : (d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC));
+    h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
+    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && !h->strang && h->sys == SYS_SW && d->ndim == 2 &&
+               d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;
+    h->stream = stream;
+    h->ctrl = (Ctrl*)(ws + p.off_ctrl);
+    h->buf[0] = q;
+    h->buf[1] = ws + p.off_b1;
+    h->buf[2] = ws + p.off_b2;
+    h->zc = d->maux ? (void*)(ws + p.off_zc) : nullptr;
+    for (int k = 0; k < 3; ++k) h->dx[k] = k < d->ndim ? (d->upper[k] - d->lower[k]) / (double)d->n[k] : 1.0;
+    h->parity = 0;
+}
+
+// Set-up kernels on the handle's stream: control block, derived acoustic
+// coefficients.
+hipError_t setup_kernels(claw_solver* h, const void* aux) {
+    hipError_t e = launch_ctrl_init(h->ctrl, h->dx, h->d.ndim, h->d.cfl_desired, h->d.cfl_max, h->d.dt_max,
+                                    h->strang, result_offset_of(h), h->stream);
+    if (e == hipSuccess && h->d.maux) {
+        if (h->fp32) e = launch_derive_zc<float>((const float*)aux, (float*)h->zc, h->plan.ncell, h->stream);
+        else e = launch_derive_zc<double>((const double*)aux, (double*)h->zc, h->plan.ncell, h->stream);
+    }
+    return e;
+}
+
 // Enqueues exactly `trials` trial steps as replays of the captured graphs.
 claw_status replay_trials(claw_solver* h, int64_t trials) {
     for (int r = 0; r < 4; ++r) {
@@ -437,6 +470,39 @@ claw_status replay_trials(claw_solver* h, int64_t trials) {
             trials -= kLadder[r];
         }
     }
+    return CLAW_OK;
+}
+
+// The adaptive loop of claw_advance: trials from the graph ladder (graphs)
+// or enqueued one by one (no graph objects, nothing allocated).
+claw_status run_adaptive(claw_solver* h, int64_t nsteps, double dt0, bool graphs, double* t,
+                         int64_t* nreject) {
+    claw_status st = commit(h);
+    if (st) return st;
+    if (nsteps > 0) {
+        st = begin_adaptive(h, dt0);
+        if (st) return st;
+    }
+    HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
+    int64_t remaining = nsteps;
+    StepState S;
+    for (int round = 0; round < 1000; ++round) {
+        if (graphs) {
+            st = replay_trials(h, remaining);
+        } else {
+            for (int64_t k = 0; k < remaining && st == CLAW_OK; ++k) st = enqueue_trial(h, h->stream, nullptr);
+        }
+        if (!st) st = commit(h);
+        if (!st) st = sync_state(h);
+        if (!st) st = read_state(h, &S);
+        if (st) return st;
+        if (S.err) return ctrl_status(S);
+        remaining = S.target - S.accepted;
+        if (S.done || remaining <= 0) break;
+    }
+    if (t) *t = S.t;
+    if (nreject) *nreject = S.rejected - S.base_rejected;
+    if (S.accepted - S.base_accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
     return CLAW_OK;
 }
 
@@ -500,34 +566,13 @@ claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* work
         return fail(CLAW_E_INVALID, "q and workspace must be 256-byte aligned");
     claw_solver* h = new (std::nothrow) claw_solver();
     if (!h) return fail(CLAW_E_HIP, "out of host memory");
-    h->d = *d;
-    h->plan = p;
-    h->fp32 = d->dtype == CLAW_FP32;
-    h->sys = d->riemann >= CLAW_RP_PLUGIN_BASE ? d->riemann
-             : (d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC));
-    h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
-    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && !h->strang && h->sys == SYS_SW && d->ndim == 2 &&
-               d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;
-    h->stream = (hipStream_t)stream;
-    char* ws = (char*)workspace;
-    h->ctrl = (Ctrl*)(ws + p.off_ctrl);
-    h->buf[0] = q;
-    h->buf[1] = ws + p.off_b1;
-    h->buf[2] = ws + p.off_b2;
-    h->zc = d->maux ? (void*)(ws + p.off_zc) : nullptr;
-    for (int k = 0; k < 3; ++k) h->dx[k] = k < d->ndim ? (d->upper[k] - d->lower[k]) / (double)d->n[k] : 1.0;
-    h->parity = 0;
+    bind_solver(h, d, p, q, (char*)workspace, (hipStream_t)stream);
     hipError_t e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         delete h;
         return fail(CLAW_E_HIP, "stream create failed: %s", hipGetErrorString(e));
     }
-    e = launch_ctrl_init(h->ctrl, h->dx, d->ndim, d->cfl_desired, d->cfl_max, d->dt_max, h->strang,
-                         result_offset_of(h), h->stream);
-    if (e == hipSuccess && d->maux) {
-        if (h->fp32) e = launch_derive_zc<float>((const float*)aux, (float*)h->zc, p.ncell, h->stream);
-        else e = launch_derive_zc<double>((const double*)aux, (double*)h->zc, p.ncell, h->stream);
-    }
+    e = setup_kernels(h, aux);
     if (e != hipSuccess) {
         (void)hipStreamDestroy(h->cap_stream);
         delete h;
@@ -607,29 +652,7 @@ claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax) {
 claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t, int64_t* nreject) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");
     if (nsteps < 0) return fail(CLAW_E_INVALID, "nsteps must be >= 0");
-    claw_status st = commit(h);
-    if (st) return st;
-    if (nsteps > 0) {
-        st = begin_adaptive(h, dt0);
-        if (st) return st;
-    }
-    HIP_TRY(launch_set_target(h->ctrl, committed(h), nsteps, h->stream));
-    int64_t remaining = nsteps;
-    StepState S;
-    for (int round = 0; round < 1000; ++round) {
-        st = replay_trials(h, remaining);
-        if (!st) st = commit(h);
-        if (!st) st = sync_state(h);
-        if (!st) st = read_state(h, &S);
-        if (st) return st;
-        if (S.err) return ctrl_status(S);
-        remaining = S.target - S.accepted;
-        if (S.done || remaining <= 0) break;
-    }
-    if (t) *t = S.t;
-    if (nreject) *nreject = S.rejected - S.base_rejected;
-    if (S.accepted - S.base_accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");
-    return CLAW_OK;
+    return run_adaptive(h, nsteps, dt0, true, t, nreject);
 }
 
 claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts, double* cfl_log) {
