@@ -461,6 +461,8 @@ def main():
                          "10-20 s on 16 threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-bw", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the 2048^2 run that follows the headline size (profiling runs)")
     ap.add_argument("--traffic-file", default=None)
     ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d", "sizes"])
     ap.add_argument("--fused-step", action="store_true",
@@ -507,7 +509,7 @@ def main():
     steps = args.steps if args.steps_given else (100 if n >= 4096 else 1000)
     warmup = args.warmup if args.warmup_given else (300 if n >= 4096 else 3000)
     line = bench_grid(args, torch, claw, inputs, n, steps, warmup, headline=True)
-    if n != 2048:
+    if n != 2048 and not args.headline_only:
         # the 2048^2 configuration itself (its 3 x 48 MiB working set stays in
         # the 256 MB MALL, so its bandwidth figure is not an HBM figure)
         st2 = args.steps if args.steps_given else 1000

@@ -92,7 +92,6 @@ typedef enum {
 /* Ghost-cell rules (2 ghost cells per side): zero-order extrapolation,
  * reflecting wall (normal velocity / momentum negated), periodic. */
 typedef enum { CLAW_BC_EXTRAP = 0, CLAW_BC_WALL = 1, CLAW_BC_PERIODIC = 2 } claw_bc;
-/* Wave limiter: MC; none (phi = 1, Lax-Wendroff); first order (no correction). */
 /* Wave limiters phi(theta) of the high-resolution method (section 3): MC,
  * none (phi = 1, Lax-Wendroff), first order (no correction), minmod, superbee,
  * van Leer. */
@@ -130,20 +129,25 @@ typedef struct {
 } claw_desc;
 
 /* Fills *d with defaults (MC limiter, entropy fix on, 2 ghosts, CFL 0.9 / 1.0,
- * dt_max = +inf); the caller then sets grid, system and boundary conditions. */
+ * dt_max = +inf); the caller then sets grid, system and boundary conditions.
+ * Defined by: section 4.1 (the user states the equations, grid, boundary conditions
+ * and limiter) and equation CFL-condition (the Courant limits). */
 void claw_desc_init(claw_desc* d);
 
 /* Plug-in solver id (claw_desc.riemann >= CLAW_RP_PLUGIN_BASE): its field
  * and wave counts, the largest ndim it runs in, the first field of the vector
  * that rotates with the sweep direction (-1 if none; a wall negates its normal
  * component) and a static name.  Any output pointer may be NULL.
- * CLAW_E_INVALID if id names no compiled plug-in. */
+ * CLAW_E_INVALID if id names no compiled plug-in.
+ * Defined by: section 4.2 (point-wise Riemann solver supplied by the user). */
 claw_status claw_plugin_info(int32_t id, int32_t* meqn, int32_t* mwaves, int32_t* ndim_max,
                              int32_t* vec_field, const char** name);
 
 /* Workspace size in bytes for descriptor d (two scratch state buffers, the
  * derived acoustic coefficients and the control block).  CLAW_E_INVALID for a
- * bad descriptor. */
+ * bad descriptor.
+ * Defined by: section 4.3 (one global array per field; waves never stored) and
+ * section 4.1 (a revert needs Q^n kept). */
 claw_status claw_workspace_bytes(const claw_desc* d, size_t* bytes);
 
 /* Validates d and binds the caller's device buffers.  q, aux, workspace are
@@ -153,13 +157,16 @@ claw_status claw_workspace_bytes(const claw_desc* d, size_t* bytes);
  * column-sweep workgroup are chosen from the grid and the device's CU count;
  * the environment variables CLAW_COL_WAVES (target wavefronts per column
  * sweep) and CLAW_COL_CHUNK (rows per chunk) override that choice for tuning,
- * read once per process; values <= 0 are ignored. */
+ * read once per process; values <= 0 are ignored.
+ * Defined by: section 4.1 (problem set-up: Riemann solver, grid, boundary conditions)
+ * and section 6 (set-up driven from Python). */
 claw_status claw_create(const claw_desc* d, void* q, const void* aux, void* workspace,
                         size_t workspace_bytes, void* stream, claw_solver** out);
 
 /* Speed-only pass (Riemann speeds of every direction on the current state,
  * nothing updated) and host sync: *sigma = max_d max|s| / dx_d.  smax (may be
- * NULL) receives max|s| per direction. */
+ * NULL) receives max|s| per direction.
+ * Defined by: equation CFL-condition and the speed reduction of section 4.1. */
 claw_status claw_cfl(claw_solver* h, double* sigma, double* smax);
 
 /* One trial step x, y (, z) with time step dt (section 4.1 pipeline).  If the
@@ -167,12 +174,16 @@ claw_status claw_cfl(claw_solver* h, double* sigma, double* smax);
  * Q^n bitwise).  If cfl != NULL the call synchronises, stores the Courant
  * number and returns CLAW_E_CFL for a rejected step, CLAW_E_NONPHYSICAL for a
  * non-physical state; with cfl == NULL nothing is synchronised and the
- * outcome is only recorded in the control block. */
+ * outcome is only recorded in the control block.
+ * Defined by: equation LW-update (the split step) and section 4.1 (pipeline; revert
+ * when the CFL condition fails). */
 claw_status claw_step(claw_solver* h, double dt, double* cfl);
 
 /* One directional sweep dir (0, 1, 2) with time step dt, always accepted
  * (a building block for tests; the result becomes the current state).
- * smax (may be NULL) receives the largest |s| of the sweep (synchronises). */
+ * smax (may be NULL) receives the largest |s| of the sweep (synchronises).
+ * Defined by: equation LW-update (one directional sweep of the splitting) and
+ * section 5.3 (single-stage update). */
 claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax);
 
 /* Adaptive stepping with revert (the production path): advances by nsteps
@@ -182,13 +193,16 @@ claw_status claw_sweep(claw_solver* h, int32_t dir, double dt, double* smax);
  * step sequence runs from a captured HIP graph with dt kept on the device;
  * the call synchronises once at the end and leaves the state in q.
  * *t receives the simulation time, *nreject the rejected trials of this call
- * (either may be NULL). */
+ * (either may be NULL).
+ * Defined by: section 4.1 (time step from the previous step's speeds; revert and redo
+ * on a CFL violation) and equation CFL-condition. */
 claw_status claw_advance(claw_solver* h, int64_t nsteps, double dt0, double* t,
                          int64_t* nreject);
 
 /* Prescribed time steps: one step per entry of dts (host array), each always
  * accepted; cfl_log (host, may be NULL) receives each step's Courant number.
- * Synchronises; the state is left in q. */
+ * Synchronises; the state is left in q.
+ * Defined by: equation LW-update applied with given time steps. */
 claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts,
                                double* cfl_log);
 
@@ -196,23 +210,29 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
  * kernel, for per-kernel timing: kernel_ms[k] receives the summed duration of
  * the sweeps in direction k (0: x, 1: y, 2: z; the step control runs inside
  * the last sweep of a step; slot 3 is unused) and launches[k] their count
- * (either array may be NULL; both have 4 entries). */
+ * (either array may be NULL; both have 4 entries).
+ * Defined by: section 7.1 (per-kernel measurement behind the roofline). */
 claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms,
                                int64_t* launches);
 
 /* Enqueues a copy of the current state into q if it lives in a workspace
- * buffer; no synchronisation. */
+ * buffer; no synchronisation.
+ * Defined by: section 6 (the caller's array holds the solution it evolves). */
 claw_status claw_sync_state(claw_solver* h);
 
-/* Step-control scalars (synchronises).  Any output pointer may be NULL. */
+/* Step-control scalars (synchronises).  Any output pointer may be NULL.
+ * Defined by: section 4.1 (time, next time step, accepted and reverted steps). */
 claw_status claw_get_control(claw_solver* h, double* t, double* dt_next, int64_t* accepted,
                              int64_t* rejected);
-/* Restores t and dt_next (checkpoint / resume); enqueued, no sync. */
+/* Restores t and dt_next (checkpoint / resume); enqueued, no sync.
+ * Defined by: section 4.1 (the next step's dt comes from the previous step). */
 claw_status claw_set_control(claw_solver* h, double t, double dt_next);
 
 /* Releases the handle (waits for its stream first).  Device buffers stay the
- * caller's. */
+ * caller's.
+ * Defined by: section 6 (the caller owns the arrays it passed in). */
 claw_status claw_destroy(claw_solver* h);
+
 
 /* ---------------------------------------------------------------------------
  * Batched ensembles: many independent 2D shallow-water grids of different
@@ -224,10 +244,13 @@ claw_status claw_destroy(claw_solver* h);
  * ------------------------------------------------------------------------- */
 typedef struct claw_batch claw_batch; /* opaque */
 
-/* Workspace bytes for count descriptors (all 2D shallow water, one dtype). */
+/* Workspace bytes for count descriptors (all 2D shallow water, one dtype).
+ * Defined by: section 8 (independent subproblems on one device) and section 4.3
+ * (one array per field). */
 claw_status claw_batch_workspace_bytes(const claw_desc* descs, int32_t count, size_t* bytes);
 /* q[i]: device state of instance i (layout as for claw_create, 256-byte
- * aligned); workspace: device buffer of claw_batch_workspace_bytes() bytes. */
+ * aligned); workspace: device buffer of claw_batch_workspace_bytes() bytes.
+ * Defined by: section 8 (independent subproblems) and section 4.1 (set-up). */
 claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const* q, void* workspace,
                               size_t workspace_bytes, void* stream, claw_batch** out);
 /* Autotuner: times state-preserving trial steps (dt = 0) for each candidate
@@ -235,16 +258,21 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
  * first, 1 round-robin), keeps the fastest, and records it in the JSON cache
  * file cache_path (may be NULL) keyed by arch, dtype, system, instance count
  * and total-cell bucket; a cached key is used without timing.  Outputs may be
- * NULL.  Synchronises. */
+ * NULL.  Synchronises.
+ * Defined by: section 5.2 (block shapes chosen for the hardware). */
 claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk, int32_t* schedule,
                             double* us_per_step);
-/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1). */
+/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1).
+ * Defined by: section 5.2 (block shapes). */
 claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule);
 /* Advances every instance by nsteps accepted steps (adaptive dt per
  * instance, first dt from a speed pass); t[i], nreject[i] (host arrays of
  * count entries, may be NULL) receive each instance's time and rejected
- * trials of this call.  Synchronises; states end in q[i]. */
+ * trials of this call.  Synchronises; states end in q[i].
+ * Defined by: section 4.1 (adaptive step with revert, per instance) and section 8
+ * (independent subproblems). */
 claw_status claw_batch_advance(claw_batch* b, int64_t nsteps, double* t, int64_t* nreject);
+/* Defined by: section 6 (the caller owns the arrays it passed in). */
 claw_status claw_batch_destroy(claw_batch* b);
 
 /* ------------------------------------------------------------------------
@@ -285,15 +313,18 @@ typedef struct {
 
 /* Device bytes of the parameter block (masters, Adam moments, BF16 copies;
  * layout private except that the first CLAW_LC_NPARAM floats are the FP32
- * masters in the order above) and of the scratch workspace a grid needs. */
+ * masters in the order above) and of the scratch workspace a grid needs.
+ * Defined by: equation LW-update (the correction enters as a flux difference). */
 claw_status claw_lc_sizes(const claw_lc_desc* d, size_t* param_bytes, size_t* work_bytes);
 
 /* After the caller has written the masters: zeroes the Adam moments and
- * emits the BF16 copies.  Enqueued on `stream`. */
+ * emits the BF16 copies.  Enqueued on `stream`.
+ * Defined by: equation LW-update (parameters of the flux-difference correction). */
 claw_status claw_lc_init(void* params, void* stream);
 
 /* Corrections of every face of state q: dF (3, ny, nx+1) and dG (3, ny+1, nx)
- * in state component order, zero on wall faces.  Enqueued. */
+ * in state component order, zero on wall faces.  Enqueued.
+ * Defined by: equation LW-update (per-face fluxes F~, G~ of the update). */
 claw_status claw_lc_forward(const claw_lc_desc* d, const void* params, const float* q, float* dF, float* dG,
                             void* stream);
 
@@ -305,13 +336,15 @@ claw_status claw_lc_forward(const claw_lc_desc* d, const void* params, const flo
  * if loss != NULL, loss[0] = L and loss[1..3] = sum r_f^2 (device doubles).
  * BF16 rounding points: inputs, weights, activations, and the output and
  * pre-activation gradients entering products; bias gradients sum unrounded
- * values.  Enqueued; workspace from claw_lc_sizes. */
+ * values.  Enqueued; workspace from claw_lc_sizes.
+ * Defined by: equation LW-update (the corrected update whose error is fitted). */
 claw_status claw_lc_loss_grad(const claw_lc_desc* d, const void* params, const float* q, const float* target,
                               const float* plain, double nux, double nuy, const double* w, void* work,
                               float* grad, double* loss, void* stream);
 
 /* One Adam step (step counts from 1) on the masters with gradient grad, then
- * new BF16 copies.  Enqueued. */
+ * new BF16 copies.  Enqueued.
+ * Defined by: equation LW-update (training of the flux-difference correction). */
 claw_status claw_lc_adam(void* params, const float* grad, int64_t step, double lr, double beta1, double beta2,
                          double eps, void* stream);
 
@@ -319,22 +352,48 @@ claw_status claw_lc_adam(void* params, const float* grad, int64_t step, double l
  * corrections.  A face keeps its correction when |h_R - h_L| <= tau min(h_L,
  * h_R) (no shock across it, h from qn) and |d_c| <= kappa s_out[c] for the
  * three components in the face frame (the output within kappa of its scale);
- * then faces next to a cell whose corrected depth is below half its plain
- * depth, or not positive, are dropped (one pass).  FP32 decisions.  out may alias plain.  keep_x (ny, nx+1) and keep_y (ny+1, nx),
- * optional, receive 1 where a face kept its correction.  Enqueued. */
+ * then faces next to a bad cell are dropped: a cell whose depth from only
+ * those kept faces that lower it is below half its plain depth, or not
+ * positive (that worst case bounds its depth whatever faces are dropped, so
+ * every cell ends at half its plain depth or more).  FP32 decisions.  out may alias plain.  keep_x (ny, nx+1) and keep_y (ny+1, nx),
+ * optional, receive 1 where a face kept its correction.  Enqueued.
+ * Defined by: equation LW-update (conservative flux-difference form) and eq:SW (depth
+ * positivity). */
 claw_status claw_lc_apply(const claw_lc_desc* d, const float* qn, const float* plain, const float* dF,
                           const float* dG, double nux, double nuy, double tau, double kappa, float* out,
                           uint8_t* keep_x, uint8_t* keep_y, void* work, void* stream);
 
 /* 2 x 2 cell averages of a fine FP32 state (3, 2ny, 2nx) into coarse (3, ny, nx).
- * Enqueued. */
+ * Enqueued.
+ * Defined by: section 3 (cell averages Q_ij of the finite-volume method). */
 claw_status claw_lc_coarsen(int64_t nx, int64_t ny, const float* fine, float* coarse, void* stream);
+
+/* Training input noise: out = q + sigma_f z for every value of an FP32 state
+ * (3, ny, nx) (f the field), z standard normal from Philox4x32-10 (a
+ * counter-based generator: counter (i / 2, call, 0, 0), key (seed, 0)) and
+ * the Box-Muller transform of its first two words (values 2k and 2k + 1 share
+ * one draw).  q, out: device buffers (may alias); sigma: host array of 3.
+ * Enqueued.
+ * Defined by: equation LW-update (training of the flux-difference correction
+ * on perturbed coarse states). */
+claw_status claw_lc_perturb(int64_t nx, int64_t ny, const float* q, float* out, const float* sigma, uint32_t seed,
+                            uint32_t call, void* stream);
+
+/* Output scales and loss weights from the residual energy of the first
+ * samples: r2[f] = sum over ncell cells of the squared residual of field f
+ * (host array of 3).  With ms_f = max(r2[f] / ncell, 1e-30): w[f] = 1 / ms_f,
+ * s_out = (sqrt(ms_h) / nu or 0 when correct_depth is 0, m / nu, m / nu) with
+ * m the mean of the momenta's sqrt(ms).  Host arithmetic only.
+ * Defined by: equation LW-update (scales of the flux-difference correction). */
+claw_status claw_lc_scales(const double* r2, int64_t ncell, double nu, int32_t correct_depth, float* s_out,
+                           double* w);
 
 /* nsteps learned coarse steps of fixed dt on solver h (FP32 2D shallow water,
  * walls, grid d->nx x d->ny): each is the plain split step followed by the
  * corrections computed from Q^n and applied as above, with no host round trip
  * between steps.  The state is left in the solver's q.  Synchronises at the end;
- * CLAW_E_NONPHYSICAL as for claw_advance_fixed. */
+ * CLAW_E_NONPHYSICAL as for claw_advance_fixed.
+ * Defined by: equation LW-update (plain split step plus the flux difference). */
 claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* params, int64_t nsteps, double dt,
                             double tau, double kappa, void* work);
 
@@ -342,11 +401,14 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
  * 7.1): streams over device buffers a (read, must be zero-filled) and b
  * (written), each of `bytes` bytes, reps times per kernel, on `stream`, and
  * stores GB/s in gbps[5]: copy, copy with non-temporal stores, read only,
- * write only, write only non-temporal.  Synchronises. */
+ * write only, write only non-temporal.  Synchronises.
+ * Defined by: section 7.1 (achievable bandwidth roof). */
 claw_status claw_stream_bench(void* a, void* b, size_t bytes, int32_t reps, void* stream,
                               double* gbps);
 
+/* Defined by: section 4.1 (the CFL revert and failure outcomes of a step). */
 const char* claw_status_string(claw_status s);
+/* Defined by: section 4.1 (why the last call failed). */
 const char* claw_last_error(void);
 
 #ifdef __cplusplus

@@ -62,9 +62,14 @@ Fallback (inference).  A face keeps its correction only if
     |d_c| <= kappa * s_out_c for all three components c of the face frame
                                              (the output within kappa of its
                                              training scale)
-and, after a first application, neither neighbour's corrected depth is below
-half its plain value or non-positive (one pass).  These decisions are taken
-in FP32 arithmetic on FP32 data, as the device takes them.
+and neither neighbour is a bad cell.  A cell is bad when the depth it would
+get from only those of its kept faces that lower it,
+    p - [(max(nu_x dF_r, 0) - min(nu_x dF_l, 0)) + (max(nu_y dG_t, 0) - min(nu_y dG_b, 0))],
+is below half its plain depth p or not positive.  That worst case bounds the
+depth after any of its faces are dropped, so every cell ends at least at half
+its plain depth (a bad cell loses all its faces and keeps its plain depth).
+These decisions are taken in FP32 arithmetic on FP32 data, in this order, as
+the device takes them.
 """
 import numpy as np
 
@@ -299,8 +304,15 @@ def apply(qn, plain, dF, dG, nux, nuy, tau, kappa, s_out):
         cy = nuy * (G[:, 1:, :] - G[:, :-1, :])
         return plain - (cx + cy)
 
-    out = corrected(keepF, keepG)
-    bad = (out[0] < f32(0.5) * plain[0]) | (out[0] <= f32(0))
+    # worst case of each cell's depth: only the kept faces that lower it
+    F0 = np.where(keepF, dF[0], f32(0))
+    G0 = np.where(keepG, dG[0], f32(0))
+    tl, tr = nux * F0[:, :-1], nux * F0[:, 1:]
+    tb, tt = nuy * G0[:-1, :], nuy * G0[1:, :]
+    f0 = f32(0)
+    lower = (np.maximum(tr, f0) - np.minimum(tl, f0)) + (np.maximum(tt, f0) - np.minimum(tb, f0))
+    worst = plain[0] - lower
+    bad = (worst < f32(0.5) * plain[0]) | (worst <= f0)
     keepF[:, :-1] &= ~bad
     keepF[:, 1:] &= ~bad
     keepG[:-1, :] &= ~bad

@@ -36,7 +36,7 @@ EXPORTED = ["claw_desc_init", "claw_plugin_info", "claw_workspace_bytes", "claw_
             "claw_batch_workspace_bytes", "claw_batch_create", "claw_batch_tune",
             "claw_batch_set_tiles", "claw_batch_advance", "claw_batch_destroy",
             "claw_lc_sizes", "claw_lc_init", "claw_lc_forward", "claw_lc_loss_grad", "claw_lc_adam",
-            "claw_lc_apply", "claw_lc_coarsen", "claw_lc_advance",
+            "claw_lc_apply", "claw_lc_coarsen", "claw_lc_advance", "claw_lc_perturb", "claw_lc_scales",
             "claw_stream_bench", "claw_status_string", "claw_last_error"]
 
 CLAW_LC_NET = 5187
@@ -131,6 +131,8 @@ def _load():
         "claw_lc_apply": (i32, [P(claw_lc_desc), vp, vp, vp, vp, dbl, dbl, dbl, dbl, vp, vp, vp, vp, vp]),
         "claw_lc_coarsen": (i32, [i64, i64, vp, vp, vp]),
         "claw_lc_advance": (i32, [vp, P(claw_lc_desc), vp, i64, dbl, dbl, dbl, vp]),
+        "claw_lc_perturb": (i32, [i64, i64, vp, vp, P(ctypes.c_float), ctypes.c_uint32, ctypes.c_uint32, vp]),
+        "claw_lc_scales": (i32, [P(dbl), i64, dbl, i32, P(ctypes.c_float), P(dbl)]),
         "claw_status_string": (ctypes.c_char_p, [i32]),
         "claw_last_error": (ctypes.c_char_p, []),
     }
@@ -409,6 +411,24 @@ def claw_lc_coarsen(nx, ny, fine, coarse, stream_handle):
     _need(coarse, "coarse", 3 * int(ny) * int(nx), torch.float32)
     _check(_lib.claw_lc_coarsen(int(nx), int(ny), _ptr(fine), _ptr(coarse), ctypes.c_void_p(stream_handle)),
            "claw_lc_coarsen")
+
+
+def claw_lc_perturb(nx, ny, q, out, sigma, seed, call, stream_handle):
+    import torch
+    _need(q, "q", 3 * int(ny) * int(nx), torch.float32)
+    _need(out, "out", 3 * int(ny) * int(nx), torch.float32)
+    sg = (ctypes.c_float * 3)(*[float(v) for v in sigma])
+    _check(_lib.claw_lc_perturb(int(nx), int(ny), _ptr(q), _ptr(out), sg, int(seed) & 0xFFFFFFFF,
+                                int(call) & 0xFFFFFFFF, ctypes.c_void_p(stream_handle)), "claw_lc_perturb")
+
+
+def claw_lc_scales(r2, ncell, nu, correct_depth=True):
+    """(s_out, w): output scales and loss weights from residual energies r2 (3 sums)."""
+    r = (ctypes.c_double * 3)(*[float(v) for v in r2])
+    so = (ctypes.c_float * 3)()
+    w = (ctypes.c_double * 3)()
+    _check(_lib.claw_lc_scales(r, int(ncell), float(nu), 1 if correct_depth else 0, so, w), "claw_lc_scales")
+    return tuple(float(v) for v in so), tuple(float(v) for v in w)
 
 
 def claw_lc_advance(h, desc, params, nsteps, dt, tau, kappa, work):

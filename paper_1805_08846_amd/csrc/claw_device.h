@@ -13,10 +13,10 @@
 //                                 velocity;
 //   acoustics (p, u_n):           r_1 = (-e0, 1), r_2 = (e1, 1), e0 = Z left,
 //                                 e1 = Z right (impedances).
-// With the limited strength phi_p and c_p = 1/2 |s_p| (1 - dt/dx |s_p|) the
-// interface hands its left cell  L = A-dQ + F~ = sum (a_p + c_p phi_p) alpha_p r_p
-// and its right cell  R = A+dQ - F~ = sum (s_p - a_p - c_p phi_p) alpha_p r_p,
-// and every cell is updated once: Q_k -= dt/dx (R_{k-1/2} + L_{k+1/2})
+// With the limited strength phi_p alpha_p and c_p = 1/2 |s_p| (1 - dt/dx |s_p|)
+// the interface hands its left cell  L = A-dQ + F~ = sum (a_p alpha_p + c_p
+// phi_p alpha_p) r_p and its right cell  R = A+dQ - F~ = sum (s_p alpha_p) r_p
+// - L, and every cell is updated once: Q_k -= dt/dx (R_{k-1/2} + L_{k+1/2})
 // (single-stage update, section 5.3).
 #pragma once
 
@@ -330,12 +330,11 @@ __device__ __forceinline__ void roe_c(float x, float& c, float& i2c) {
 template <typename R>
 __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, SYS_SW>& r,
                                         R, R, R, R g, int efix, Iface<R, SYS_SW>& o) {
-    R hbar = R(0.5) * (l.h + r.h);
     R inv = frcp(l.sqh + r.sqh);
     R uhat = (l.sqh * l.u + r.sqh * r.u) * inv;
     R vhat = (l.sqh * l.v + r.sqh * r.v) * inv;
     R chat, i2c;
-    roe_c(g * hbar, chat, i2c);
+    roe_c((l.h + r.h) * (R(0.5) * g), chat, i2c);  // c^2 = g hbar, hbar = (h_l + h_r) / 2
     R dh = r.h - l.h;
     R dn = r.mn - l.mn;
     R dt = r.mt - l.mt;
@@ -347,17 +346,19 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_SW>& l, const Cell<R, 
     R am1 = rmin(s1, R(0));
     R am3 = rmin(s3, R(0));
     if (efix) {
-        R lam_l = l.u - l.c;
+        // lambda_l = u_l - c_l < 0 is u_l < c_l; lambda_r3 = u_r + c_r > 0 is
+        // u_r > -c_r (the differences are only formed in the transonic case)
         R hm = l.h + a1;
         R mm = l.mn + a1 * s1;
-        if (lam_l < R(0) && hm > R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
+        if (l.u < l.c && hm > R(0) && mm > R(0) && mm * mm > g * hm * hm * hm) {
+            R lam_l = l.u - l.c;
             R lam_r = fdiv(mm, hm) - fsqrt(g * hm);
             if (lam_r > R(0)) am1 = fdiv(lam_l * (lam_r - s1), lam_r - lam_l);
         }
-        R lam_r3 = r.u + r.c;
         R hm3 = r.h - a3;
         R mm3 = r.mn - a3 * s3;
-        if (lam_r3 > R(0) && hm3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
+        if (r.u > -r.c && hm3 > R(0) && mm3 < R(0) && mm3 * mm3 > g * hm3 * hm3 * hm3) {
+            R lam_r3 = r.u + r.c;
             R lam_l3 = fdiv(mm3, hm3) + fsqrt(g * hm3);
             if (lam_l3 < R(0)) am3 = fdiv(lam_l3 * (lam_r3 - s3), lam_r3 - lam_l3);
         }
@@ -392,18 +393,22 @@ __device__ __forceinline__ R iface_smax(const Iface<R, SYS>& k) {
     }
 }
 
-// Limited wave strength phi(theta) * alpha of the MC limiter without forming
-// theta = n / (alpha |r|^2): with a = |alpha| and b = sign(alpha) n / |r|^2,
-//   phi(theta) alpha = sign(alpha) max(0, min((a + b) / 2, 2 a, 2 b)),
-// which is phi(theta) alpha exactly in real arithmetic and vanishes with alpha.
-// n = alpha_up (r_up . r) is the projection of the upwind wave.
-template <typename R>
-__device__ __forceinline__ R mc_limited(R alpha, R n_over_r2) {
-    const R sg = rsign1(alpha);
-    const R a = rabs(alpha);
-    const R b = sg * n_over_r2;
-    const R m = rmax(R(0), rmin(R(0.5) * (a + b), rmin(a + a, b + b)));
-    return sg * m;
+// Half the limited wave strength, phi(theta) alpha / 2, of the MC limiter
+// without forming theta = beta / alpha, beta = n / |r|^2 (n = alpha_up (r_up .
+// r), the projection of the upwind wave).  phi(theta) alpha equals the
+// minmod of the three values (alpha + beta) / 2, 2 alpha, 2 beta (all of one
+// sign: the one nearest zero; else 0) in real arithmetic, and vanishes with
+// alpha; halved, that is minmod((alpha + beta) / 4, alpha, beta).  In FP32 a
+// two-value minmod is med3(x, y, 0), so the whole limiter is two v_med3_f32.
+__device__ __forceinline__ float mc_half(float alpha, float beta) {
+    const float m = __builtin_amdgcn_fmed3f(alpha, beta, 0.0f);
+    return __builtin_amdgcn_fmed3f(0.25f * (alpha + beta), m, 0.0f);
+}
+__device__ __forceinline__ double mc_half(double alpha, double beta) {
+    const double sg = rsign1(alpha);
+    const double a = rabs(alpha);
+    const double b = sg * beta;
+    return sg * rmax(0.0, rmin(0.25 * (a + b), rmin(a, b)));
 }
 
 // phi(theta) * alpha for the other limiters, with a = |alpha| and b = theta |alpha|
@@ -495,15 +500,20 @@ __device__ __forceinline__ void plugin_contrib(const Iface<R, SYS>& k, const Ifa
     }
 }
 
-// Limited strengths phi_p alpha_p of interface k given its neighbours km
-// (k - 1) and kp (k + 1).
+// Half the limited wave strengths, phi_p alpha_p / 2, of interface k given
+// its neighbours km (k - 1) and kp (k + 1).
+template <typename R>
+__device__ __forceinline__ R half_limited(R alpha, R beta, int limiter) {
+    if (limiter == LIM_MC) return mc_half(alpha, beta);
+    return R(0.5) * wave_limited(alpha, beta, limiter);
+}
 template <typename R>
 __device__ __forceinline__ void limited(const Iface<R, SYS_SW>& k, const Iface<R, SYS_SW>& km,
                                         const Iface<R, SYS_SW>& kp, int limiter, R (&w)[3]) {
     if (limiter == LIM_NONE) {
-        w[0] = k.alpha[0];
-        w[1] = k.alpha[1];
-        w[2] = k.alpha[2];
+        w[0] = R(0.5) * k.alpha[0];
+        w[1] = R(0.5) * k.alpha[1];
+        w[2] = R(0.5) * k.alpha[2];
         return;
     }
     // |r_1|^2 and |r_3|^2 share one reciprocal
@@ -522,15 +532,9 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_SW>& k, const Iface<R
     const R a2u = p2 ? km.alpha[1] : kp.alpha[1];
     const R n1 = a1u * (R(1) + s1u * k.s[0] + v1u * k.e0);
     const R n3 = a3u * (R(1) + s3u * k.s[2] + v3u * k.e0);
-    if (limiter == LIM_MC) {
-        w[0] = mc_limited(k.alpha[0], n1 * ir1);
-        w[1] = mc_limited(k.alpha[1], a2u);
-        w[2] = mc_limited(k.alpha[2], n3 * ir3);
-    } else {
-        w[0] = wave_limited(k.alpha[0], n1 * ir1, limiter);
-        w[1] = wave_limited(k.alpha[1], a2u, limiter);
-        w[2] = wave_limited(k.alpha[2], n3 * ir3, limiter);
-    }
+    w[0] = half_limited(k.alpha[0], n1 * ir1, limiter);
+    w[1] = half_limited(k.alpha[1], a2u, limiter);
+    w[2] = half_limited(k.alpha[2], n3 * ir3, limiter);
 }
 
 // Acoustics: wave 1 moves left (upwind neighbour k + 1), wave 2 right (k - 1).
@@ -538,25 +542,20 @@ template <typename R>
 __device__ __forceinline__ void limited(const Iface<R, SYS_AC>& k, const Iface<R, SYS_AC>& km,
                                         const Iface<R, SYS_AC>& kp, int limiter, R (&w)[2]) {
     if (limiter == LIM_NONE) {
-        w[0] = k.alpha[0];
-        w[1] = k.alpha[1];
+        w[0] = R(0.5) * k.alpha[0];
+        w[1] = R(0.5) * k.alpha[1];
         return;
     }
     // constant coefficients: r_p is the same at every interface
-    if (limiter == LIM_MC) {
-        w[0] = mc_limited(k.alpha[0], kp.alpha[0]);
-        w[1] = mc_limited(k.alpha[1], km.alpha[1]);
-    } else {
-        w[0] = wave_limited(k.alpha[0], kp.alpha[0], limiter);
-        w[1] = wave_limited(k.alpha[1], km.alpha[1], limiter);
-    }
+    w[0] = half_limited(k.alpha[0], kp.alpha[0], limiter);
+    w[1] = half_limited(k.alpha[1], km.alpha[1], limiter);
 }
 template <typename R>
 __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<R, SYS_ACV>& km,
                                         const Iface<R, SYS_ACV>& kp, int limiter, R (&w)[2]) {
     if (limiter == LIM_NONE) {
-        w[0] = k.alpha[0];
-        w[1] = k.alpha[1];
+        w[0] = R(0.5) * k.alpha[0];
+        w[1] = R(0.5) * k.alpha[1];
         return;
     }
     // r_1 = (-Z_l, 1), r_2 = (Z_r, 1)
@@ -565,13 +564,8 @@ __device__ __forceinline__ void limited(const Iface<R, SYS_ACV>& k, const Iface<
     const R t = frcp(r1 * r2);
     const R n1 = kp.alpha[0] * (R(1) + kp.e0 * k.e0);
     const R n2 = km.alpha[1] * (R(1) + km.e1 * k.e1);
-    if (limiter == LIM_MC) {
-        w[0] = mc_limited(k.alpha[0], n1 * (t * r2));
-        w[1] = mc_limited(k.alpha[1], n2 * (t * r1));
-    } else {
-        w[0] = wave_limited(k.alpha[0], n1 * (t * r2), limiter);
-        w[1] = wave_limited(k.alpha[1], n2 * (t * r1), limiter);
-    }
+    w[0] = half_limited(k.alpha[0], n1 * (t * r2), limiter);
+    w[1] = half_limited(k.alpha[1], n2 * (t * r1), limiter);
 }
 
 // Limits interface k and forms its contributions to the left cell
@@ -588,15 +582,17 @@ __device__ __forceinline__ void compact_contrib(const Iface<R, SYS>& k, const If
     } else {
         limited(k, km, kp, limiter, w);
     }
+    // w holds phi_p alpha_p / 2, so the F~ share of wave p is
+    // |s| (1 - nu |s|) w = (|s| - nu |s| |s|) w; the left share adds the A-dQ
+    // share a_p alpha_p, and the right share is the rest of s_p alpha_p.
     R kl[MW], kr[MW];
 #pragma unroll
     for (int p = 0; p < MW; ++p) {
         const R sp = k.s[p];
         const R as = rabs(sp);
-        const R cw = R(0.5) * as * (R(1) - nu * as) * w[p];  // F~ share of wave p
-        const R am = k.am[p] * k.alpha[p];                     // A-dQ share
-        kl[p] = am + cw;
-        kr[p] = (sp * k.alpha[p] - am) - cw;
+        const R cw = (as - (nu * as) * as) * w[p];
+        kl[p] = k.am[p] * k.alpha[p] + cw;
+        kr[p] = sp * k.alpha[p] - kl[p];
     }
     if constexpr (SYS == SYS_SW) {
         R l13 = kl[0] + kl[2];

@@ -145,6 +145,8 @@ hipError_t launch_lc_adam(const LcParams& a, const float* grad, float lr, float 
                           float c1, float c2, hipStream_t s);
 hipError_t launch_lc_apply(const LcApply& a, hipStream_t s);
 hipError_t launch_lc_coarsen(const float* fine, float* coarse, int nx, int ny, hipStream_t s);
+hipError_t launch_lc_perturb(const float* q, float* out, int ncell, const float* sigma, unsigned seed,
+                             unsigned call, hipStream_t s);
 
 // Element-wise set-up kernels.
 template <typename R>

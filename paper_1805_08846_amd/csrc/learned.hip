@@ -611,8 +611,11 @@ __device__ __forceinline__ float corrected(const LcApply& a, float plain, int f,
     return fsub(plain, fadd(cx, cy));
 }
 
-// Pass 1: cells whose depth the indicator-filtered correction would push
-// below half the plain depth, or to zero or below.
+// Pass 1: cells whose depth could fall below half the plain depth, or to zero
+// or below: the depth from only those indicator-kept faces that lower it
+// (outflow through the right / top face, inflow through the left / bottom
+// face taken as negative).  This worst case bounds the depth after any subset
+// of the faces is dropped in pass 2, so no cell ends below it.
 __global__ __launch_bounds__(256) void k_lc_apply1(LcApply a) {
     ApplyState S;
     if (!resolve_apply(a, S)) return;
@@ -620,8 +623,15 @@ __global__ __launch_bounds__(256) void k_lc_apply1(LcApply a) {
         const int j = c / a.nx, i = c - j * a.nx;
         const FaceKeep k = keep_of(a, S.qn, i, j);
         const float p = S.plain[c];
-        const float o = corrected(a, p, 0, i, j, k);
-        a.bad[c] = (o < fmul(0.5f, p) || o <= 0.0f) ? 1 : 0;
+        const float* F = a.dF + (size_t)j * (a.nx + 1);
+        const float Fl = k.l ? F[i] : 0.0f, Fr = k.r ? F[i + 1] : 0.0f;
+        const float Gb = k.b ? a.dG[(size_t)j * a.nx + i] : 0.0f;
+        const float Gt = k.t ? a.dG[(size_t)(j + 1) * a.nx + i] : 0.0f;
+        const float tl = fmul(a.nux, Fl), tr = fmul(a.nux, Fr);
+        const float tb = fmul(a.nuy, Gb), tt = fmul(a.nuy, Gt);
+        const float lower = fadd(fsub(fmaxf(tr, 0.0f), fminf(tl, 0.0f)), fsub(fmaxf(tt, 0.0f), fminf(tb, 0.0f)));
+        const float worst = fsub(p, lower);
+        a.bad[c] = (worst < fmul(0.5f, p) || worst <= 0.0f) ? 1 : 0;
     }
 }
 
@@ -661,6 +671,61 @@ __global__ __launch_bounds__(256) void k_lc_coarsen(const float* __restrict__ fi
         const int j = r / nx, i = r - j * nx;
         const float* F = fine + (size_t)f * 4 * ncell + (size_t)(2 * j) * (2 * nx) + 2 * i;
         coarse[c] = 0.25f * ((F[0] + F[1]) + (F[2 * nx] + F[2 * nx + 1]));
+    }
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011): a counter-based generator, ten rounds of the
+// 4x32 Philox S-box with the published multipliers and Weyl key increments.
+struct Philox4 {
+    unsigned v[4];
+};
+__device__ __forceinline__ Philox4 philox4x32_10(unsigned c0, unsigned c1, unsigned c2, unsigned c3, unsigned k0,
+                                                 unsigned k1) {
+    const unsigned M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long p0 = (unsigned long long)M0 * c0;
+        const unsigned long long p1 = (unsigned long long)M1 * c2;
+        const unsigned hi0 = (unsigned)(p0 >> 32), lo0 = (unsigned)p0;
+        const unsigned hi1 = (unsigned)(p1 >> 32), lo1 = (unsigned)p1;
+        const unsigned n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    Philox4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+// out = q + sigma_f * N(0, 1) per value (field f = index / ncell).  Value i
+// draws from counter (i / 2, call, 0, 0) with key (seed, 0): two uniforms
+// u = (x + 0.5) / 2^32 from the first two output words, and Box-Muller
+// (sqrt(-2 ln u0) cos / sin (2 pi u1)) gives values 2k and 2k + 1.
+__global__ __launch_bounds__(256) void k_lc_perturb(const float* __restrict__ q, float* __restrict__ out, int ncell,
+                                                    float s0, float s1, float s2, unsigned seed, unsigned call) {
+    const int n = 3 * ncell;
+    for (int k = blockIdx.x * 256 + threadIdx.x; 2 * k < n; k += gridDim.x * 256) {
+        const Philox4 r = philox4x32_10((unsigned)k, call, 0u, 0u, seed, 0u);
+        const float u0 = ((float)r.v[0] + 0.5f) * 2.3283064365386963e-10f;
+        const float u1 = ((float)r.v[1] + 0.5f) * 2.3283064365386963e-10f;
+        const float rad = sqrtf(-2.0f * logf(u0));
+        const float ang = 6.283185307179586f * u1;
+        const float z[2] = {rad * cosf(ang), rad * sinf(ang)};
+        for (int e = 0; e < 2; ++e) {
+            const int i = 2 * k + e;
+            if (i < n) {
+                const int f = i / ncell;
+                const float sg = f == 0 ? s0 : (f == 1 ? s1 : s2);
+                out[i] = q[i] + sg * z[e];
+            }
+        }
     }
 }
 
@@ -730,6 +795,13 @@ hipError_t launch_lc_apply(const LcApply& a, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_lc_apply2, dim3(b), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lc_perturb(const float* q, float* out, int ncell, const float* sigma, unsigned seed,
+                             unsigned call, hipStream_t s) {
+    hipLaunchKernelGGL(k_lc_perturb, dim3(blocks_for((3 * (int64_t)ncell + 1) / 2)), dim3(256), 0, s, q, out,
+                       ncell, sigma[0], sigma[1], sigma[2], seed, call);
     return hipGetLastError();
 }
 

@@ -1589,6 +1589,35 @@ claw_status claw_lc_coarsen(int64_t nx, int64_t ny, const float* fine, float* co
     return CLAW_OK;
 }
 
+claw_status claw_lc_perturb(int64_t nx, int64_t ny, const float* q, float* out, const float* sigma, uint32_t seed,
+                            uint32_t call, void* stream) {
+    if (nx < 1 || ny < 1 || 3 * nx * ny >= ((int64_t)1 << 31)) return fail(CLAW_E_INVALID, "bad grid");
+    if (!q || !out || !sigma) return fail(CLAW_E_INVALID, "NULL buffer");
+    for (int f = 0; f < 3; ++f)
+        if (!(sigma[f] >= 0.0f) || !isfinite(sigma[f])) return fail(CLAW_E_INVALID, "sigma[%d] invalid", f);
+    HIP_TRY(launch_lc_perturb(q, out, (int)(nx * ny), sigma, seed, call, (hipStream_t)stream));
+    return CLAW_OK;
+}
+
+claw_status claw_lc_scales(const double* r2, int64_t ncell, double nu, int32_t correct_depth, float* s_out,
+                           double* w) {
+    if (!r2 || !s_out || !w) return fail(CLAW_E_INVALID, "NULL argument");
+    if (ncell < 1 || !(nu > 0)) return fail(CLAW_E_INVALID, "need ncell >= 1 and nu > 0");
+    double rms[3];
+    for (int f = 0; f < 3; ++f) {
+        if (!(r2[f] >= 0)) return fail(CLAW_E_INVALID, "r2[%d] invalid", f);
+        const double ms = r2[f] / (double)ncell;
+        const double m = ms > 1e-30 ? ms : 1e-30;
+        rms[f] = sqrt(m);
+        w[f] = 1.0 / m;
+    }
+    const double mom = 0.5 * (rms[1] + rms[2]);
+    s_out[0] = correct_depth ? (float)(rms[0] / nu) : 0.0f;
+    s_out[1] = (float)(mom / nu);
+    s_out[2] = (float)(mom / nu);
+    return CLAW_OK;
+}
+
 claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* params, int64_t nsteps, double dt,
                             double tau, double kappa, void* work) {
     if (!h) return fail(CLAW_E_INVALID, "solver is NULL");

@@ -96,9 +96,11 @@ class Trainer:
         self.total = total_samples
         self.resync, self.tau, self.kappa = int(resync), tau, kappa
         self.correct_depth = bool(correct_depth)
-        # input noise per field (random draws are inputs: torch's seeded generator)
+        # input noise per field, drawn on the device by claw_lc_perturb
+        # (counter-based: seed and a per-sample call counter)
         self.noise = tuple(float(v) for v in noise)
-        self.gen = torch.Generator(device="cuda").manual_seed(int(noise_seed))
+        self.noise_seed = int(noise_seed)
+        self.noise_calls = 0
         self.samples = 0
         self.losses = []
         self.scaled = False
@@ -108,6 +110,7 @@ class Trainer:
         self.qcn = torch.empty(c, dtype=torch.float32, device="cuda")
         self.target = torch.empty(c, dtype=torch.float32, device="cuda")
         self.plain = torch.empty(c, dtype=torch.float32, device="cuda")
+        self.qin = torch.empty(c, dtype=torch.float32, device="cuda")
         pc, _, _ = inputs.sw_hump(n=self.nc, seed=0, dtype="f32")
         self.coarse = claw.Solver(pc, self.plain)
 
@@ -119,15 +122,12 @@ class Trainer:
 
     def _set_scales(self, r2):
         """Output scales and loss weights from the residual energy of the
-        first samples (sum r_f^2 over cells, per field)."""
-        ms = np.asarray(r2, dtype=np.float64) / (self.nc * self.nc)
-        rms = np.sqrt(np.maximum(ms, 1e-30))
-        mom = 0.5 * (rms[1] + rms[2])
-        # correct_depth False: momentum-only corrections (output scale of h zero)
-        s = (rms[0] / self.nu if self.correct_depth else 0.0, mom / self.nu, mom / self.nu)
-        self.norm["s_out"] = tuple(float(v) for v in s)
+        first samples (sum r_f^2 over cells, per field), by claw_lc_scales;
+        correct_depth False gives momentum-only corrections."""
+        s_out, w = claw.claw_lc_scales(r2, self.nc * self.nc, self.nu, self.correct_depth)
+        self.norm["s_out"] = s_out
         self.lc.desc = claw.lc_desc(self.nc, self.nc, self.norm)
-        self.w = tuple(float(1.0 / m) for m in np.maximum(ms, 1e-30))
+        self.w = w
         self.scaled = True
 
     def run(self, seed, steps_fine=500):
@@ -151,8 +151,10 @@ class Trainer:
             claw.claw_lc_coarsen(self.nc, self.nc, qf, self.target, _stream())
             if any(self.noise) and self.scaled:
                 # the network sees a perturbed Q^n; the plain step and the target do not
-                qin = self.qcn + torch.randn(self.qcn.shape, generator=self.gen, device="cuda") * \
-                    torch.tensor(self.noise, device="cuda").view(3, 1, 1)
+                claw.claw_lc_perturb(self.nc, self.nc, self.qcn, self.qin, self.noise, self.noise_seed,
+                                     self.noise_calls, _stream())
+                self.noise_calls += 1
+                qin = self.qin
             else:
                 qin = self.qcn
             self.lc.loss_grad(qin, self.target, self.plain, self.nu, self.nu, self.w)

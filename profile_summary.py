@@ -1,0 +1,190 @@
+"""Reduces raw rocprofv3 output into the short text summaries under profiles/.
+
+Two kinds of input, both CSV files written by rocprofv3 with
+``--output-format csv``:
+
+  kernel trace   ``rocprofv3 --kernel-trace --stats ... -o kt`` writes
+                 kt_kernel_stats.csv (name, calls, total / average / min /
+                 max duration in ns); ``trace`` turns it into a markdown
+                 table of the kernels by share of GPU time.
+  counters       one ``rocprofv3 --pmc <counters> ... -o p`` run per counter
+                 group writes p_counter_collection.csv (one row per dispatch
+                 and counter); ``pmc`` takes the median per dispatch of each
+                 counter for the sweep kernels and writes, per kernel class,
+                 HBM bytes per launch and VALU instructions per launch in the
+                 key: value form bench.py reads.
+
+HBM bytes: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by what
+the same counters read for the plain copy kernel of the streaming benchmark
+(claw_stream_bench's k_copy, 1 GiB read and 1 GiB written per dispatch) in
+the same run, so the summary states bytes in the copy's calibration: on
+MI355X FETCH_SIZE reads half the copy's 1 GiB (factor 2.000) and WRITE_SIZE
+all of it (factor 1.000).
+
+VALU issue: SQ_INSTS_VALU counts wave instructions.  Without packed FP32 a
+wave64 VALU instruction occupies a SIMD for 4 clocks, so a launch of N
+instructions needs at least 4 N / (1024 SIMDs x 2.4 GHz) seconds; the
+summary divides that by the kernel's average traced duration to give the
+fraction of the VALU issue peak (transcendental instructions take longer, so
+this understates how busy the VALU is).
+
+Usage:
+  python profile_summary.py trace <kernel_stats.csv> <title> <command> > profiles/kernels_X.md
+  python profile_summary.py pmc --title T --commands-file F --ncell N --real-bytes B \
+      --trace <kernel_stats.csv> <counter_collection.csv> ... > profiles/pmc_sweeps_X.txt
+"""
+import argparse
+import csv
+import hashlib
+import os
+import statistics
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+VALU_PEAK_SIMD_CLOCKS = 1024 * 2.4e9  # SIMDs x clock (Hz)
+SWEEP_CLASSES = (("k_sweep_row<", "x_sweep"), ("k_sweep_col<", "y_sweep"), ("k_step2d<", "step2d"))
+
+
+def kernel_source_hash():
+    """Hash of the sweep kernels' sources without comments and blank lines
+    (the same function bench.py uses to accept a summary)."""
+    h = hashlib.sha256()
+    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h"):
+        with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
+def read_stats(path):
+    """kernel name -> (calls, average ns, min ns, max ns, total ns)."""
+    out = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            name = row.get("Name") or row.get("KernelName") or row.get("Kernel_Name")
+            out[name] = (int(float(row["Calls"])), float(row["AverageNs"]), float(row["MinNs"]),
+                         float(row["MaxNs"]), float(row["TotalDurationNs"]))
+    return out
+
+
+def trace(path, title, command):
+    st = read_stats(path)
+    total = sum(v[4] for v in st.values()) or 1.0
+    lines = [f"# rocprofv3 kernel trace summary: {title}", "",
+             f"command (from the repository root): {command}", "",
+             "| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |",
+             "|---|---|---|---|---|---|"]
+    for name, (calls, avg, mn, mx, tot) in sorted(st.items(), key=lambda kv: -kv[1][4]):
+        short = name if len(name) <= 100 else name[:100]
+        lines.append(f"| {short} | {calls} | {avg / 1e3:.2f} | {mn / 1e3:.2f} | {mx / 1e3:.2f} | "
+                     f"{100 * tot / total:.1f} % |")
+    return "\n".join(lines) + "\n"
+
+
+def read_counters(paths):
+    """(kernel name, counter) -> list of per-dispatch values."""
+    vals = defaultdict(dict)
+    for p in paths:
+        with open(p) as fh:
+            for row in csv.DictReader(fh):
+                key = (row["Kernel_Name"], row["Counter_Name"])
+                d = int(row["Dispatch_Id"])
+                vals[key][d] = vals[key].get(d, 0.0) + float(row["Counter_Value"])
+    return {k: list(v.values()) for k, v in vals.items()}
+
+
+def _median(v):
+    return statistics.median(v) if v else None
+
+
+def pmc(args):
+    c = read_counters(args.csv)
+    kernels = sorted({k for k, _ in c})
+    copy = [k for k in kernels if "k_copy<false>" in k]
+    alg = 2 * 3 * args.real_bytes * args.ncell
+    out = [f"# rocprofv3 counters: {args.title}", ""]
+    if args.commands_file:
+        with open(args.commands_file) as fh:
+            out += [ln.rstrip() for ln in fh if ln.strip()]
+        out.append("")
+    scale = {"FETCH_SIZE": 1.0, "WRITE_SIZE": 1.0}
+    if copy:
+        # the largest copy dispatches are the 1 GiB ones (2^20 KiB read and written)
+        for cn in scale:
+            v = c.get((copy[0], cn), [])
+            if v and max(v) > 0.25 * 2 ** 20:
+                scale[cn] = 2 ** 20 / max(v)
+        out.append("calibration: plain copy kernel k_copy<false> (claw_stream_bench), 1 GiB read + 1 GiB "
+                   "written per dispatch, same runs")
+        for cn in scale:
+            v = c.get((copy[0], cn), [])
+            if v and max(v) > 0.25 * 2 ** 20:
+                out.append(f"- {cn} per copy dispatch (KiB): {max(v):.1f} -> scale {scale[cn]:.4f}")
+        out.append("")
+    out.append(f"algorithmic bytes per sweep launch: {alg}")
+    stats = read_stats(args.trace) if args.trace else {}
+    for pat, cls in SWEEP_CLASSES:
+        names = [k for k in kernels if pat in k and ", false, 0>" in k]
+        if not names:
+            continue
+        name = names[0]
+        out.append("")
+        n = len(c.get((name, "SQ_WAVES"), []) or c.get((name, "FETCH_SIZE"), []))
+        out.append(f"{cls} kernel {name}: {n} dispatches (medians per dispatch)")
+        fs, ws = _median(c.get((name, "FETCH_SIZE"), [])), _median(c.get((name, "WRITE_SIZE"), []))
+        if fs is not None and ws is not None:
+            rb, wb = fs * scale["FETCH_SIZE"] * 1024, ws * scale["WRITE_SIZE"] * 1024
+            out.append(f"- FETCH_SIZE KiB: {fs:.1f} (scaled {rb / 1024:.1f})")
+            out.append(f"- WRITE_SIZE KiB: {ws:.1f} (scaled {wb / 1024:.1f})")
+            out.append(f"- {cls}_hbm_bytes_per_launch: {rb + wb:.0f}")
+            out.append(f"- ratio to algorithmic bytes: {(rb + wb) / alg:.3f} (read {2 * rb / alg:.3f}, "
+                       f"written {2 * wb / alg:.3f})")
+        waves = _median(c.get((name, "SQ_WAVES"), []))
+        valu = _median(c.get((name, "SQ_INSTS_VALU"), []))
+        if waves:
+            out.append(f"- SQ_WAVES: {waves:.0f}")
+        if valu:
+            out.append(f"- {cls}_valu_insts_per_launch: {valu:.0f}")
+            if waves:
+                out.append(f"- VALU instructions per wave: {valu / waves:.1f}; per cell (x 64 lanes / cells): "
+                           f"{valu * 64 / args.ncell:.1f}")
+            salu = _median(c.get((name, "SQ_INSTS_SALU"), []))
+            if salu and waves:
+                out.append(f"- SQ_INSTS_SALU: {salu:.0f} ({salu / waves:.1f} per wave)")
+            tr = [v for k, v in stats.items() if k.startswith(name.split("(")[0])]
+            if tr:
+                avg_s = tr[0][1] * 1e-9
+                out.append(f"- traced average duration: {tr[0][1] / 1e3:.2f} us -> VALU issue fraction = "
+                           f"4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x duration) = "
+                           f"{4 * valu / (VALU_PEAK_SIMD_CLOCKS * avg_s):.3f}")
+    out.append("")
+    out.append(f"kernel_source_hash: {kernel_source_hash()}")
+    return "\n".join(out) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("stats")
+    t.add_argument("title")
+    t.add_argument("command")
+    p = sub.add_parser("pmc")
+    p.add_argument("csv", nargs="+")
+    p.add_argument("--title", required=True)
+    p.add_argument("--commands-file")
+    p.add_argument("--ncell", type=int, required=True)
+    p.add_argument("--real-bytes", type=int, default=4)
+    p.add_argument("--trace")
+    a = ap.parse_args()
+    if a.cmd == "trace":
+        sys.stdout.write(trace(a.stats, a.title, a.command))
+    else:
+        sys.stdout.write(pmc(a))
+
+
+if __name__ == "__main__":
+    main()

@@ -90,3 +90,21 @@ def observed_order(errors, ns):
     e1, e2 = errors[-2], errors[-1]
     n1, n2 = ns[-2], ns[-1]
     return math.log(e1 / e2) / math.log(n2 / n1)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0, k1):
+    """Philox4x32-10 of Salmon et al. (SC 2011) on numpy uint32 arrays (or
+    scalars): ten rounds of the 4x32 S-box with multipliers 0xD2511F53,
+    0xCD9E8D57 and key increments 0x9E3779B9, 0xBB67AE85.  Returns the four
+    32-bit output words as uint64 arrays."""
+    u = np.uint64
+    c = [np.asarray(x, dtype=np.uint64) for x in (c0, c1, c2, c3)]
+    k0, k1 = np.asarray(k0, dtype=np.uint64), np.asarray(k1, dtype=np.uint64)
+    m32 = u(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = u(0xD2511F53) * c[0]
+        p1 = u(0xCD9E8D57) * c[2]
+        c = [(p1 >> u(32)) ^ c[1] ^ k0, p1 & m32, (p0 >> u(32)) ^ c[3] ^ k1, p0 & m32]
+        k0 = (k0 + u(0x9E3779B9)) & m32
+        k1 = (k1 + u(0xBB67AE85)) & m32
+    return c

@@ -243,3 +243,31 @@ def test_learned_calls_reject_null_buffers_before_touching_the_gpu(claw):
                            None, None) == claw.CLAW_E_INVALID
     assert L.claw_lc_coarsen(0, 4, fake, fake, None) == claw.CLAW_E_INVALID
     assert L.claw_lc_advance(None, ctypes.byref(d), None, 1, 0.1, 0.5, 0.01, None) == claw.CLAW_E_INVALID
+
+
+def test_philox_helper_known_answers():
+    # the test helper the noise kernel is checked against reproduces the
+    # published known-answer vectors of Philox4x32-10
+    from helpers import philox4x32_10
+    cases = [((0, 0, 0, 0, 0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+             ((0xffffffff,) * 6, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+             ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344, 0xa4093822, 0x299f31d0),
+              (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for args, want in cases:
+        assert tuple(int(v) for v in philox4x32_10(*args)) == want
+
+
+def test_learned_scales_host_call(claw):
+    # residual energies (sum over 64 cells) -> output scales and loss weights
+    r2 = (64 * 4e-6, 64 * 9e-6, 64 * 1e-6)
+    s_out, w = claw.claw_lc_scales(r2, 64, 0.5, True)
+    assert s_out[0] == pytest.approx(2e-3 / 0.5, rel=1e-6)
+    assert s_out[1] == s_out[2] == pytest.approx(0.5 * (3e-3 + 1e-3) / 0.5, rel=1e-6)
+    assert w == pytest.approx((1 / 4e-6, 1 / 9e-6, 1 / 1e-6), rel=1e-12)
+    s0, _ = claw.claw_lc_scales(r2, 64, 0.5, False)
+    assert s0[0] == 0.0
+    # a field with no residual gets the floor 1e-30, not a division by zero
+    _, w0 = claw.claw_lc_scales((0.0, 1.0, 1.0), 64, 0.5, True)
+    assert w0[0] == pytest.approx(1e30)
+    with pytest.raises(claw.ClawError):
+        claw.claw_lc_scales((1.0, 1.0, 1.0), 0, 0.5, True)

@@ -265,3 +265,39 @@ def test_fixed_steps_graph_path_equals_eager_path(claw):
     assert 0.3 < cfl.max() < 1.0
     sa.close()
     sb.close()
+
+
+def test_training_noise_matches_philox_box_muller(claw):
+    # claw_lc_perturb against the published generator written out in numpy
+    # (tests/helpers.philox4x32_10) and the Box-Muller transform in FP64
+    from helpers import philox4x32_10
+    ny, nx = 37, 29
+    rng = np.random.default_rng(3)
+    q = rng.uniform(0.5, 1.5, (3, ny, nx)).astype(np.float32)
+    sigma = (1e-5, 3e-5, 2e-5)
+    seed, call = 12345, 7
+    out = torch.empty((3, ny, nx), dtype=torch.float32, device="cuda")
+    claw.claw_lc_perturb(nx, ny, _dev(q), out, sigma, seed, call, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    n = 3 * ny * nx
+    k = np.arange((n + 1) // 2, dtype=np.uint64)
+    w = philox4x32_10(k, call, 0, 0, seed, 0)
+    u0 = (w[0].astype(np.float64) + 0.5) * 2.0 ** -32
+    u1 = (w[1].astype(np.float64) + 0.5) * 2.0 ** -32
+    rad = np.sqrt(-2 * np.log(u0))
+    z = np.stack([rad * np.cos(2 * np.pi * u1), rad * np.sin(2 * np.pi * u1)], axis=1).ravel()[:n]
+    sg = np.repeat(np.asarray(sigma), ny * nx)
+    want = q.astype(np.float64).ravel() + sg * z
+    err = np.abs(got.ravel() - want)
+    assert np.all(err <= 1e-5 * sg * (1 + np.abs(z)) + 2 * np.spacing(np.float32(2.0)))
+    zz = (got.ravel() - q.astype(np.float64).ravel()) / sg
+    assert abs(zz.mean()) < 0.1 and 0.9 < zz.std() < 1.1
+    # in place gives the same values; another call number gives others
+    qq = _dev(q)
+    claw.claw_lc_perturb(nx, ny, qq, qq, sigma, seed, call, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(qq, out)
+    claw.claw_lc_perturb(nx, ny, qq, qq, sigma, seed, call + 1, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert not torch.equal(qq, out)

@@ -180,6 +180,38 @@ def test_apply_conserves_and_falls_back():
     assert not kG3[8, 3] and kG3[8, 4]
 
 
+def test_fallback_keeps_every_depth_at_half_its_plain_value():
+    # Cell 8 of row 8 takes depth in through its left face and gives the same
+    # amount out through its right face (net zero).  Cell 7 loses 0.6 of its
+    # depth 1 through the shared face, so that face must go; judged on the
+    # full correction, cell 8 would look safe, keep its right face alone and
+    # end at 0.4.  Judged on its depth-lowering faces alone it is bad itself,
+    # so it keeps its plain depth.
+    q = np.zeros((3, 16, 16), dtype=np.float32)
+    q[0] = 1.0
+    plain = q.copy()
+    dF = np.zeros((3, 16, 17), dtype=np.float32)
+    dF[0, 8, 8] = dF[0, 8, 9] = 0.6 / 0.3
+    out, kF, _ = L.apply(q, plain, dF, np.zeros((3, 17, 16), np.float32), 0.3, 0.3, 0.5, 1000.0,
+                         _norm()["s_out"])
+    assert not kF[8, 8] and not kF[8, 9]
+    assert out[0, 8, 8] == plain[0, 8, 8] and out[0, 8, 7] == plain[0, 8, 7]
+    # random corrections large enough to push many cells below half their
+    # depth: after the fallback none is
+    rng = np.random.default_rng(9)
+    for k in range(20):
+        q = _state(ny=24, nx=20, seed=100 + k).astype(np.float32)
+        plain = (q + 0.01 * rng.normal(size=q.shape)).astype(np.float32)
+        plain[0] = np.maximum(plain[0], 0.3)
+        dF = (0.6 * rng.normal(size=(3, 24, 21))).astype(np.float32)
+        dG = (0.6 * rng.normal(size=(3, 25, 20))).astype(np.float32)
+        dF[:, :, [0, 20]] = 0
+        dG[:, [0, 24], :] = 0
+        out, kF, kG = L.apply(q, plain, dF, dG, 0.4, 0.4, 10.0, 1e6, _norm()["s_out"])
+        assert 0.05 < kF[:, 1:20].mean() < 0.95
+        assert np.all(out[0] >= np.float32(0.5) * plain[0] * np.float32(1 - 1e-6))
+
+
 def test_transpose_symmetry():
     # swapping x <-> y (and hu <-> hv) in the state swaps the roles of the
     # two networks: the x-face network of the swapped state sees what the
