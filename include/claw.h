@@ -254,17 +254,19 @@ claw_status claw_batch_workspace_bytes(const claw_desc* descs, int32_t count, si
 claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const* q, void* workspace,
                               size_t workspace_bytes, void* stream, claw_batch** out);
 /* Autotuner: times state-preserving trial steps (dt = 0) for each candidate
- * column chunk {16, 32, 64, 128} and block schedule (0 largest instances
- * first, 1 round-robin), keeps the fastest, and records it in the JSON cache
- * file cache_path (may be NULL) keyed by arch, dtype, system, instance count
- * and total-cell bucket; a cached key is used without timing.  Outputs may be
+ * column chunk {16, 32, 64, 128} x block schedule (0 largest instances
+ * first, 1 round-robin) x rows each row-sweep wavefront takes in turn
+ * {2, 4, 8}, keeps the fastest, and records it in the JSON cache file
+ * cache_path (may be NULL) keyed by arch, dtype, system, instance count and
+ * total-cell bucket; a cached key is used without timing.  Outputs may be
  * NULL.  Synchronises.
  * Defined by: section 5.2 (block shapes chosen for the hardware). */
 claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk, int32_t* schedule,
-                            double* us_per_step);
-/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1).
+                            int32_t* rows_per_wave, double* us_per_step);
+/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1; rows_per_wave
+ * 2, 4 or 8; the default after claw_batch_create is 32, 0, 8).
  * Defined by: section 5.2 (block shapes). */
-claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule);
+claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule, int32_t rows_per_wave);
 /* Advances every instance by nsteps accepted steps (adaptive dt per
  * instance, first dt from a speed pass); t[i], nreject[i] (host arrays of
  * count entries, may be NULL) receive each instance's time and rejected

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libclaw.so")
+# CLAW_LIBRARY names another build of the same library (A/B timing of kernel
+# variants); by default the in-tree build is loaded
+_LIB_PATH = os.environ.get("CLAW_LIBRARY") or os.path.join(_HERE, "libclaw.so")
 
 CLAW_OK, CLAW_E_INVALID, CLAW_E_UNSUPPORTED, CLAW_E_HIP, CLAW_E_CFL, CLAW_E_NONPHYSICAL, \
     CLAW_E_STATE = range(7)
@@ -119,8 +121,8 @@ def _load():
         "claw_stream_bench": (i32, [vp, vp, ctypes.c_size_t, i32, vp, P(dbl)]),
         "claw_batch_workspace_bytes": (i32, [P(claw_desc), i32, P(ctypes.c_size_t)]),
         "claw_batch_create": (i32, [P(claw_desc), i32, P(vp), vp, ctypes.c_size_t, vp, P(vp)]),
-        "claw_batch_tune": (i32, [vp, ctypes.c_char_p, P(i32), P(i32), P(dbl)]),
-        "claw_batch_set_tiles": (i32, [vp, i32, i32]),
+        "claw_batch_tune": (i32, [vp, ctypes.c_char_p, P(i32), P(i32), P(i32), P(dbl)]),
+        "claw_batch_set_tiles": (i32, [vp, i32, i32, i32]),
         "claw_batch_advance": (i32, [vp, i64, P(dbl), P(i64)]),
         "claw_batch_destroy": (i32, [vp]),
         "claw_lc_sizes": (i32, [P(claw_lc_desc), P(ctypes.c_size_t), P(ctypes.c_size_t)]),
@@ -294,14 +296,14 @@ def claw_batch_create(descs, qs, workspace, stream_handle):
 
 
 def claw_batch_tune(h, cache_path=None):
-    c, s, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+    c, s, r, us = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
     _check(_lib.claw_batch_tune(h, cache_path.encode() if cache_path else None, ctypes.byref(c),
-                                ctypes.byref(s), ctypes.byref(us)), "claw_batch_tune")
-    return {"chunk": c.value, "schedule": s.value, "us_per_step": us.value}
+                                ctypes.byref(s), ctypes.byref(r), ctypes.byref(us)), "claw_batch_tune")
+    return {"chunk": c.value, "schedule": s.value, "rows_per_wave": r.value, "us_per_step": us.value}
 
 
-def claw_batch_set_tiles(h, chunk, schedule):
-    _check(_lib.claw_batch_set_tiles(h, int(chunk), int(schedule)), "claw_batch_set_tiles")
+def claw_batch_set_tiles(h, chunk, schedule, rows_per_wave=8):
+    _check(_lib.claw_batch_set_tiles(h, int(chunk), int(schedule), int(rows_per_wave)), "claw_batch_set_tiles")
 
 
 def claw_batch_advance(h, count, nsteps):
@@ -338,8 +340,8 @@ class BatchSolver:
     def tune(self, cache_path=None):
         return claw_batch_tune(self.h, cache_path)
 
-    def set_tiles(self, chunk, schedule):
-        claw_batch_set_tiles(self.h, chunk, schedule)
+    def set_tiles(self, chunk, schedule, rows_per_wave=8):
+        claw_batch_set_tiles(self.h, chunk, schedule, rows_per_wave)
 
     def advance(self, nsteps):
         return claw_batch_advance(self.h, len(self.qs), nsteps)

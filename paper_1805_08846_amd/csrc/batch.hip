@@ -10,7 +10,7 @@
 
 namespace claw {
 
-template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK>
+template <typename R, int SYS, int MEQN, int CPL, bool SPEEDS, int LIMK, int RPW>
 __global__ __launch_bounds__(256) void k_batch_row(BatchLaunch<R> L) {
     const BatchBlock bb = L.blocks[blockIdx.x];
     SweepArgs<R> a = L.args[bb.inst * 2 + 0];
@@ -18,7 +18,7 @@ __global__ __launch_bounds__(256) void k_batch_row(BatchLaunch<R> L) {
     a.parity = L.parity;
     a.first = L.first;
     a.last = L.last;
-    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK, ROW_RPW_BATCH>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
+    row_body<R, SYS, MEQN, CPL, SPEEDS, LIMK, RPW>(a, bb.x, bb.y, bb.x == 0 && bb.y == 0);
 }
 
 template <typename R, int SYS, int MEQN, int NRM, int PF, bool SPEEDS, int LIMK>
@@ -94,7 +94,14 @@ static hipError_t launch_batch_kind(const BatchLaunch<R>& L, int dir, int nblock
     if (nblocks <= 0) return hipSuccess;
     if (dir == 0) {
         constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
-        hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS, LIMK>), dim3(nblocks), dim3(256), 0, s, L);
+        if (L.rpw == 2)
+            hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS, LIMK, 2>), dim3(nblocks), dim3(256), 0, s, L);
+        else if (L.rpw == 4)
+            hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS, LIMK, 4>), dim3(nblocks), dim3(256), 0, s, L);
+        else if (L.rpw == 8)
+            hipLaunchKernelGGL((k_batch_row<R, SYS, MEQN, CPL, SPEEDS, LIMK, 8>), dim3(nblocks), dim3(256), 0, s, L);
+        else
+            return hipErrorInvalidValue;
     } else {
         hipLaunchKernelGGL((k_batch_col<R, SYS, MEQN, 2, 4, SPEEDS, LIMK>), dim3(nblocks), dim3(256), 0, s, L);
     }

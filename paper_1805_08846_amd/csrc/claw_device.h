@@ -140,6 +140,56 @@ __host__ __device__ inline RowTail row_tail(int nx, int cpl) {
     return t;
 }
 
+// A value every lane of the wavefront holds alike, moved into a scalar
+// register (the compiler cannot prove that on its own for values read from
+// memory or derived from the wavefront index): addresses built from it then
+// stay scalar, and the per-lane part is a 32-bit offset.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+    return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                            __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
+// Buffer resource of one field: raw, byte addressed, offsets below 2^32 (the
+// runtime keeps every field under 4 GiB).  A load or store then takes a
+// per-lane byte offset and a scalar byte offset and costs no vector address
+// arithmetic; the resource lives in scalar registers.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+__device__ __forceinline__ Rsrc field_rsrc(const void* base, unsigned bytes) {
+    // word 3: 32-bit data format, the value gfx9-family raw buffer access takes
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_load(Rsrc r, unsigned voff, unsigned soff, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ double buf_load(Rsrc r, unsigned voff, unsigned soff, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned voff, unsigned soff, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+}
+__device__ __forceinline__ void buf_store(Rsrc r, unsigned voff, unsigned soff, double v) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+}
+
+// 16-byte vector loads and stores through a field resource (a row lane's
+// cells: four FP32 or two FP64 values).
+typedef unsigned U4 __attribute__((ext_vector_type(4)));
+template <typename V>
+__device__ __forceinline__ V buf_load16(Rsrc r, unsigned voff) {
+    static_assert(sizeof(V) == 16, "16-byte vectors only");
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+}
+template <typename V>
+__device__ __forceinline__ void buf_store16(Rsrc r, unsigned voff, V v) {
+    static_assert(sizeof(V) == 16, "16-byte vectors only");
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)voff, 0, 0);
+}
+
 // Rotation buffer i (0..2) chosen by selects rather than by indexing the
 // array: a dynamic index into a SweepArgs held in registers would force the
 // whole struct into private memory.
@@ -835,9 +885,9 @@ struct Trial {
 // committed one if nothing is pending): readable before the decision.
 template <typename R>
 __device__ __forceinline__ int predicted_cur(const SweepArgs<R>& a) {
-    if (!a.first) return a.ctrl->st[a.parity].cur;
+    if (!a.first) return wave_uniform(a.ctrl->st[a.parity].cur);
     const StepState& P = a.ctrl->st[a.parity ^ 1];
-    return (P.pending && !P.done) ? (P.cur + P.result_off) % 3 : P.cur;
+    return wave_uniform((P.pending && !P.done) ? (P.cur + P.result_off) % 3 : P.cur);
 }
 
 // lead: this workgroup is block (0, 0, 0) of its grid (it records the state).
@@ -861,6 +911,10 @@ __device__ __forceinline__ Trial<R> open_trial(const SweepArgs<R>& a, int dir, b
         t.done = S.done;
         t.nu = state_nu<R>(S, dir);
     }
+    // every lane read or decided the same step state
+    t.cur = wave_uniform(t.cur);
+    t.done = wave_uniform(t.done);
+    t.nu = wave_uniform(t.nu);
     return t;
 }
 

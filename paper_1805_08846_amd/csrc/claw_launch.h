@@ -8,12 +8,13 @@
 namespace claw {
 
 // Rows each row-sweep wavefront takes in turn: single grids (FP64 lanes hold
-// two cells, so a wavefront's fixed work is spread over two rows), batched
-// launches (a batched workgroup first loads its table entry and its
-// instance's arguments, so it pays for more rows).
+// two cells, so a wavefront's fixed work is spread over two rows); batched
+// launches take 2, 4 or 8 (a batched workgroup first loads its table entry and
+// its instance's arguments, so it pays for more rows), chosen by the tuner.
 template <typename R>
 constexpr int row_rpw_single() { return sizeof(R) == 4 ? 1 : 2; }
-constexpr int ROW_RPW_BATCH = 8;
+constexpr int ROW_RPW_BATCH_DEFAULT = 8;
+inline bool batch_rpw_ok(int rpw) { return rpw == 2 || rpw == 4 || rpw == 8; }
 
 // One directional sweep (or, with speeds, its speed-only pass) of system sys
 // with meqn fields; a.dir selects the row (0) or column (1, 2) kernel.
@@ -56,6 +57,7 @@ struct BatchLaunch {
     const SweepArgs<R>* args;
     int parity, first, last;
     int limiter;  // the limiter every instance uses, or -1 if they differ
+    int rpw;      // rows per row-sweep wavefront (2, 4 or 8; the row table is built for it)
 };
 enum { BOP_COMMIT = 0, BOP_ZERO_SPEEDS = 1, BOP_BEGIN_FIXED = 2, BOP_BEGIN_ADAPT = 3 };
 template <typename R>

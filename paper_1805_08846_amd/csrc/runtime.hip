@@ -81,6 +81,9 @@ claw_status validate(const claw_desc* d) {
     if (ncell * (int64_t)(d->meqn > 2 ? d->meqn : 2) >= ((int64_t)1 << 31) || d->n[1] > 65535 * 4 ||
         d->n[2] > 65535)
         return fail(CLAW_E_UNSUPPORTED, "grid too large for 32-bit element offsets");
+    // the sweeps address each field with 32-bit byte offsets
+    if ((uint64_t)ncell * (d->dtype == CLAW_FP64 ? 8u : 4u) > 0xffffffffull)
+        return fail(CLAW_E_UNSUPPORTED, "grid too large: a field must stay below 4 GiB");
     if (d->riemann == CLAW_RP_ACOUSTICS) {
         if (d->meqn != 1 + d->ndim) return fail(CLAW_E_INVALID, "acoustics needs meqn = 1 + ndim");
         if (d->mwaves != 2) return fail(CLAW_E_INVALID, "acoustics has mwaves = 2");
@@ -838,7 +841,7 @@ struct claw_batch {
     std::vector<Ctrl*> ctrl;
     std::vector<std::array<void*, 3>> buf;
     int n_row_blocks, n_col_blocks, max_col_blocks;
-    int chunk, schedule;
+    int chunk, schedule, rpw;
     double tuned_us;
     bool have_dt_next;
     int parity;
@@ -850,6 +853,7 @@ namespace {
 
 constexpr int kBatchChunkMin = 8;
 const int kTuneChunks[] = {16, 32, 64, 128};
+const int kTuneRpw[] = {2, 4, 8};
 
 int inst_row_blocks(const claw_desc& d, bool fp32);
 int inst_col_blocks(const claw_desc& d, int chunk);
@@ -916,9 +920,10 @@ BatchPlan batch_plan(const claw_desc* d, int count) {
     return p;
 }
 
-// Block tables and per-instance sweep arguments for column chunk `chunk` and
-// schedule 0 (largest instances first) or 1 (round-robin over instances).
-claw_status batch_tables(claw_batch* b, int chunk, int schedule) {
+// Block tables and per-instance sweep arguments for column chunk `chunk`,
+// schedule 0 (largest instances first) or 1 (round-robin over instances) and
+// rpw rows per row-sweep wavefront.
+claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
     const int n = b->count;
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
@@ -929,7 +934,6 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule) {
     const int P = 62 * row_cpl(b->fp32);
     for (int i = 0; i < n; ++i) {
         const claw_desc& d = b->d[i];
-        const int rpw = ROW_RPW_BATCH;
         const int segs = (int)((d.n[0] + P - 1) / P), groups = (int)((d.n[1] + 4 * rpw - 1) / (4 * rpw));
         const int nfull = (int)(d.n[0] / P), S = row_tail((int)d.n[0], row_cpl(b->fp32)).rows;
         for (int y = 0; y < groups; ++y)
@@ -989,6 +993,7 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule) {
     b->n_col_blocks = (int)ct.size();
     b->chunk = chunk;
     b->schedule = schedule;
+    b->rpw = rpw;
     for (int p = 0; p < 2; ++p) {  // launch sizes changed: recapture
         if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
         if (b->graph[p]) (void)hipGraphDestroy(b->graph[p]);
@@ -1007,6 +1012,7 @@ hipError_t batch_sweep(claw_batch* b, int dir, bool speeds, int parity, bool fir
     L.first = first ? 1 : 0;
     L.last = last ? 1 : 0;
     L.limiter = b->d[0].limiter;
+    L.rpw = b->rpw;
     for (const claw_desc& d : b->d)
         if (d.limiter != L.limiter) L.limiter = -1;
     return launch_batch_sweep<R>(L, SYS_SW, dir, dir == 0 ? b->n_row_blocks : b->n_col_blocks, speeds, s);
@@ -1072,7 +1078,7 @@ std::string tune_key(const claw_batch* b) {
     return key;
 }
 
-bool cache_lookup(const char* path, const std::string& key, int* chunk, int* schedule, double* us) {
+bool cache_lookup(const char* path, const std::string& key, int* chunk, int* schedule, int* rpw, double* us) {
     FILE* f = path ? fopen(path, "r") : nullptr;
     if (!f) return false;
     char line[512];
@@ -1083,16 +1089,17 @@ bool cache_lookup(const char* path, const std::string& key, int* chunk, int* sch
         if (!p) continue;
         const char* c = strstr(p, "\"chunk\":");
         const char* s = strstr(p, "\"schedule\":");
+        const char* r = strstr(p, "\"rows_per_wave\":");
         const char* u = strstr(p, "\"us_per_step\":");
-        if (c && s && u && sscanf(c + 8, "%d", chunk) == 1 && sscanf(s + 11, "%d", schedule) == 1 &&
-            sscanf(u + 14, "%lf", us) == 1)
+        if (c && s && r && u && sscanf(c + 8, "%d", chunk) == 1 && sscanf(s + 11, "%d", schedule) == 1 &&
+            sscanf(r + 16, "%d", rpw) == 1 && sscanf(u + 14, "%lf", us) == 1)
             found = true;
     }
     fclose(f);
     return found;
 }
 
-void cache_store(const char* path, const std::string& key, int chunk, int schedule, double us) {
+void cache_store(const char* path, const std::string& key, int chunk, int schedule, int rpw, double us) {
     if (!path) return;
     std::vector<std::string> keep;
     if (FILE* f = fopen(path, "r")) {
@@ -1108,8 +1115,9 @@ void cache_store(const char* path, const std::string& key, int chunk, int schedu
         fclose(f);
     }
     char entry[512];
-    snprintf(entry, sizeof entry, "  \"%s\": {\"chunk\": %d, \"schedule\": %d, \"us_per_step\": %.3f}",
-             key.c_str(), chunk, schedule, us);
+    snprintf(entry, sizeof entry,
+             "  \"%s\": {\"chunk\": %d, \"schedule\": %d, \"rows_per_wave\": %d, \"us_per_step\": %.3f}",
+             key.c_str(), chunk, schedule, rpw, us);
     keep.push_back(entry);
     FILE* f = fopen(path, "w");
     if (!f) return;
@@ -1190,21 +1198,22 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
     e = hipMemcpyAsync(b->ctrl_ptrs, b->ctrl.data(), sizeof(Ctrl*) * count, hipMemcpyHostToDevice, b->stream);
     if (e != hipSuccess) return bail(fail(CLAW_E_HIP, "upload failed: %s", hipGetErrorString(e)));
     b->parity = 0;
-    st = batch_tables(b, 32, 0);
+    st = batch_tables(b, 32, 0, ROW_RPW_BATCH_DEFAULT);
     if (st) return bail(st);
     *out = b;
     return CLAW_OK;
 }
 
 claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk_out, int32_t* schedule_out,
-                            double* us_per_step) {
+                            int32_t* rows_per_wave_out, double* us_per_step) {
     if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
     const std::string key = tune_key(b);
-    int chunk = 0, schedule = 0;
+    int chunk = 0, schedule = 0, rpw = 0;
     double best = 0;
-    bool cached = cache_lookup(cache_path, key, &chunk, &schedule, &best);
+    bool cached = cache_lookup(cache_path, key, &chunk, &schedule, &rpw, &best);
     // an entry that is no valid tile choice (an edited or damaged file) counts as a miss
-    if (cached && (chunk < kBatchChunkMin || chunk > 4096 || (schedule != 0 && schedule != 1) || !(best > 0)))
+    if (cached && (chunk < kBatchChunkMin || chunk > 4096 || (schedule != 0 && schedule != 1) ||
+                   !batch_rpw_ok(rpw) || !(best > 0)))
         cached = false;
     if (!cached) {
         // time a few state-preserving trials (dt = 0, always accepted) per candidate
@@ -1217,30 +1226,33 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
         best = 1e300;
-        for (int sched = 0; sched < 2; ++sched) {
-            for (int c : kTuneChunks) {
-                st = batch_tables(b, c, sched);
-                if (st) break;
-                const int reps = 6;
-                for (int k = 0; k < 2 + reps && st == CLAW_OK; ++k) {
-                    if (k == 2) HIP_TRY(hipEventRecord(e0, b->stream));
-                    st = batch_ctrl(b, BOP_BEGIN_FIXED, 0.0, MODE_FIXED);
-                    if (!st) st = batch_trial(b, b->stream);
-                    if (!st) st = batch_ctrl(b, BOP_COMMIT);
-                }
-                if (st) break;
-                HIP_TRY(hipEventRecord(e1, b->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                const double us = ms * 1e3 / reps;
-                if (us < best) {
-                    best = us;
-                    chunk = c;
-                    schedule = sched;
-                }
+        // candidates: schedule x column chunk x rows per row wavefront
+        std::vector<std::array<int, 3>> cand;
+        for (int sched = 0; sched < 2; ++sched)
+            for (int c : kTuneChunks)
+                for (int r : kTuneRpw) cand.push_back({sched, c, r});
+        for (const auto& cd : cand) {
+            st = batch_tables(b, cd[1], cd[0], cd[2]);
+            if (st) break;
+            const int reps = 6;
+            for (int k = 0; k < 2 + reps && st == CLAW_OK; ++k) {
+                if (k == 2) HIP_TRY(hipEventRecord(e0, b->stream));
+                st = batch_ctrl(b, BOP_BEGIN_FIXED, 0.0, MODE_FIXED);
+                if (!st) st = batch_trial(b, b->stream);
+                if (!st) st = batch_ctrl(b, BOP_COMMIT);
             }
             if (st) break;
+            HIP_TRY(hipEventRecord(e1, b->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            const double us = ms * 1e3 / reps;
+            if (us < best) {
+                best = us;
+                schedule = cd[0];
+                chunk = cd[1];
+                rpw = cd[2];
+            }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1248,21 +1260,23 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
         for (int i = 0; i < b->count; ++i)  // restore the control state the trials advanced
             HIP_TRY(hipMemcpyAsync(b->ctrl[i], &saved[i], sizeof(Ctrl), hipMemcpyHostToDevice, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
-        cache_store(cache_path, key, chunk, schedule, best);
+        cache_store(cache_path, key, chunk, schedule, rpw, best);
     }
-    claw_status st = batch_tables(b, chunk, schedule);
+    claw_status st = batch_tables(b, chunk, schedule, rpw);
     if (st) return st;
     b->tuned_us = best;
     if (chunk_out) *chunk_out = chunk;
     if (schedule_out) *schedule_out = schedule;
+    if (rows_per_wave_out) *rows_per_wave_out = rpw;
     if (us_per_step) *us_per_step = best;
     return CLAW_OK;
 }
 
-claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule) {
+claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule, int32_t rows_per_wave) {
     if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
-    if (chunk < kBatchChunkMin || (schedule != 0 && schedule != 1)) return fail(CLAW_E_INVALID, "bad tile choice");
-    return batch_tables(b, chunk, schedule);
+    if (chunk < kBatchChunkMin || (schedule != 0 && schedule != 1) || !batch_rpw_ok(rows_per_wave))
+        return fail(CLAW_E_INVALID, "bad tile choice");
+    return batch_tables(b, chunk, schedule, rows_per_wave);
 }
 
 claw_status claw_batch_advance(claw_batch* b, int64_t nsteps, double* t, int64_t* nreject) {

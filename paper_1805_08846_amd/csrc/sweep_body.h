@@ -197,7 +197,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     const int sub = (int)(((unsigned)lane * (65536u / (unsigned)width + 1u)) >> 16);
     const int l = lane - sub * width;
     // rows of this lane: row0 + i S, i < RPW
-    const int row0 = (by * 4 + (int)(threadIdx.x >> 6)) * RPW * S + sub;
+    const int row0 = (by * 4 + wave_uniform((int)(threadIdx.x >> 6))) * RPW * S + sub;
     const int x0 = bx * (62 * CPL);
     const int xl = x0 - CPL + l * CPL;
     // lane roles: useful (updates its cells), right halo of its sub-segment
@@ -213,18 +213,22 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
     // synthesised at the row ends)
     R q[CPL][MEQN];
     R zc[CPL][2];
+    // interior lanes: one 16-byte load per field through the field's buffer
+    // resource at byte offset (base + xl) sizeof(R)
+    const unsigned fbytes = (unsigned)a.ncell * (unsigned)sizeof(R);
     auto load_cells = [&](const R* __restrict__ src, unsigned base) {
         if (interior) {
+            const unsigned voff = (base + (unsigned)xl) * (unsigned)sizeof(R);
 #pragma unroll
             for (int e = 0; e < MEQN; ++e) {
-                V v = *reinterpret_cast<const V*>(src + (size_t)e * a.ncell + base + (unsigned)xl);
+                V v = buf_load16<V>(field_rsrc(src + (size_t)e * (unsigned)a.ncell, fbytes), voff);
 #pragma unroll
                 for (int c = 0; c < CPL; ++c) q[c][e] = v[c];
             }
             if constexpr (SYS == SYS_ACV) {
 #pragma unroll
                 for (int f = 0; f < 2; ++f) {
-                    V v = *reinterpret_cast<const V*>(a.zc + (size_t)f * a.ncell + base + (unsigned)xl);
+                    V v = buf_load16<V>(field_rsrc(a.zc + (size_t)f * (unsigned)a.ncell, fbytes), voff);
 #pragma unroll
                     for (int c = 0; c < CPL; ++c) zc[c][f] = v[c];
                 }
@@ -280,11 +284,18 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
         // useful lanes 1..width-2 (and by the right halo lane for j = nx when
         // the row ends exactly at its first cell)
         if (active) {
+            if (interior) {  // faces xl .. xl + CPL - 1, all inside the row
+                R m = iface_smax(f[0]);
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int j = xl + c;
-                const bool own = (useful && j >= 0 && j <= nx) || (rhalo && c == 0 && j == nx);
-                if (own) sm = rmax(sm, iface_smax(f[c]));
+                for (int c = 1; c < CPL; ++c) m = rmax(m, iface_smax(f[c]));
+                if (useful) sm = rmax(sm, m);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) {
+                    const int j = xl + c;
+                    const bool own = (useful && j >= 0 && j <= nx) || (rhalo && c == 0 && j == nx);
+                    if (own) sm = rmax(sm, iface_smax(f[c]));
+                }
             }
         }
 
@@ -309,12 +320,13 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
             }
             if (active && useful) {
                 if (interior) {
+                    const unsigned voff = (base + (unsigned)xl) * (unsigned)sizeof(R);
 #pragma unroll
                     for (int e = 0; e < MEQN; ++e) {
                         V v;
 #pragma unroll
                         for (int c = 0; c < CPL; ++c) v[c] = q[c][e];
-                        *reinterpret_cast<V*>(dst + (size_t)e * a.ncell + base + (unsigned)xl) = v;
+                        buf_store16<V>(field_rsrc(dst + (size_t)e * (unsigned)a.ncell, fbytes), voff, v);
                     }
                 } else {
 #pragma unroll
@@ -341,18 +353,27 @@ struct ColCell {
     R zc[2];
 };
 
+// Buffer resources of the fields a column sweep reads and writes.
+template <typename R, int MEQN>
+struct ColRes {
+    Rsrc src[MEQN], dst[MEQN], zc[2];
+};
+
+// Loads row y (a ghost row is mapped by the boundary rule) of the wavefront's
+// 64 columns.  plane_b: byte offset of the wavefront's outer plane (the same
+// for every lane); lane_byte: byte offset of the lane's column in a row.
 template <typename R, int SYS, int MEQN, int NRM>
-__device__ __forceinline__ void col_load(const R* __restrict__ src, const R* __restrict__ zcg,
-                                         const SweepArgs<R>& a, int colbase, int y,
-                                         ColCell<R, SYS, MEQN>& out) {
+__device__ __forceinline__ void col_load(const ColRes<R, MEQN>& res, const SweepArgs<R>& a, unsigned plane_b,
+                                         unsigned lane_byte, int y, ColCell<R, SYS, MEQN>& out) {
     bool flip;
-    const unsigned off = (unsigned)(colbase + ghost_idx(y, a.m, a.bc_lo, a.bc_hi, flip) * a.stride);
+    const unsigned soff =
+        plane_b + (unsigned)(ghost_idx(y, a.m, a.bc_lo, a.bc_hi, flip) * a.stride) * (unsigned)sizeof(R);
 #pragma unroll
-    for (int e = 0; e < MEQN; ++e) out.q[e] = src[(size_t)e * a.ncell + off];
+    for (int e = 0; e < MEQN; ++e) out.q[e] = buf_load(res.src[e], lane_byte, soff, R(0));
     if (flip) wall_flip<SYS>(out.q, NRM - 1);
     if constexpr (SYS == SYS_ACV) {
-        out.zc[0] = zcg[off];
-        out.zc[1] = zcg[(size_t)a.ncell + off];
+        out.zc[0] = buf_load(res.zc[0], lane_byte, soff, R(0));
+        out.zc[1] = buf_load(res.zc[1], lane_byte, soff, R(0));
     }
 }
 
@@ -378,11 +399,23 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     const int lane = threadIdx.x & 63;
     const int nx = a.nx, m = a.m;
     const int nstrip = (nx + 63) >> 6;
-    const int strip = bx * 4 + (int)(threadIdx.x >> 6);
+    const int strip = wave_uniform(bx * 4 + (int)(threadIdx.x >> 6));
     const bool sactive = strip < nstrip;
     const int x = strip * 64 + lane;
     const bool xin = sactive && x < nx;
-    const int colbase = bz * a.ostride + (x < nx ? x : nx - 1);
+    const unsigned plane_b = (unsigned)(bz * a.ostride) * (unsigned)sizeof(R);
+    const unsigned lane_byte = (unsigned)(x < nx ? x : nx - 1) * (unsigned)sizeof(R);
+    const unsigned fbytes = (unsigned)a.ncell * (unsigned)sizeof(R);
+    ColRes<R, MEQN> res;
+#pragma unroll
+    for (int e = 0; e < MEQN; ++e) {
+        res.src[e] = field_rsrc(src + (size_t)e * (unsigned)a.ncell, fbytes);
+        res.dst[e] = field_rsrc(dst + (size_t)e * (unsigned)a.ncell, fbytes);
+    }
+    if constexpr (SYS == SYS_ACV) {
+        res.zc[0] = field_rsrc(a.zc, fbytes);
+        res.zc[1] = field_rsrc(a.zc + (size_t)(unsigned)a.ncell, fbytes);
+    }
     const int y0 = by * a.chunk;
     const int y1 = sactive ? (y0 + a.chunk < m ? y0 + a.chunk : m) : y0;
 
@@ -395,10 +428,10 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
     {
         CC wm2, wm1;
         C cm2, cm1, c0;
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 2, wm2);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 - 1, wm1);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0, w0);
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, y0 + 1, w1);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, y0 - 2, wm2);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, y0 - 1, wm1);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, y0, w0);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, y0 + 1, w1);
         make_cell<R, SYS, MEQN>(wm2.q, wm2.zc, NRM, TNG, a.sqrt_grav, bad, cm2);
         make_cell<R, SYS, MEQN>(wm1.q, wm1.zc, NRM, TNG, a.sqrt_grav, bad, cm1);
         make_cell<R, SYS, MEQN>(w0.q, w0.zc, NRM, TNG, a.sqrt_grav, bad, c0);
@@ -423,14 +456,14 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int r = y0 + 2 + k;
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, pre[k]);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, r < ylast ? r : ylast, pre[k]);
     }
 
     // one row of the march: cell yy is finished, the window moves down by one
     auto step = [&](int yy, CC& slot) {
         CC w2 = slot;
         const int r = yy + 2 + PF;
-        col_load<R, SYS, MEQN, NRM>(src, a.zc, a, colbase, r < ylast ? r : ylast, slot);
+        col_load<R, SYS, MEQN, NRM>(res, a, plane_b, lane_byte, r < ylast ? r : ylast, slot);
         C c2;
         make_cell<R, SYS, MEQN>(w2.q, w2.zc, NRM, TNG, a.sqrt_grav, bad, c2);
         I fd;
@@ -441,9 +474,9 @@ __device__ __forceinline__ void col_body(const SweepArgs<R>& a, int bx, int by, 
             limit_contrib(fc, fb, fd, nu, limiter_of<LIMK>(a), kc);
             apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nu, NRM, TNG);
             if (xin) {
-                const unsigned off = (unsigned)(colbase + yy * a.stride);
+                const unsigned soff = plane_b + (unsigned)(yy * a.stride) * (unsigned)sizeof(R);
 #pragma unroll
-                for (int e = 0; e < MEQN; ++e) dst[(size_t)e * a.ncell + off] = w0.q[e];
+                for (int e = 0; e < MEQN; ++e) buf_store(res.dst[e], lane_byte, soff, w0.q[e]);
             }
 #pragma unroll
             for (int i = 0; i < NC; ++i) Rb[i] = kc.Rr[i];

@@ -271,3 +271,17 @@ def test_learned_scales_host_call(claw):
     assert w0[0] == pytest.approx(1e30)
     with pytest.raises(claw.ClawError):
         claw.claw_lc_scales((1.0, 1.0, 1.0), 0, 0.5, True)
+
+
+def test_fp64_field_byte_limit(claw):
+    # the sweeps address a field with 32-bit byte offsets: an FP64 field of
+    # 32768 x 16385 cells (4 GiB + 256 KiB) is refused, the FP32 one fits
+    d = _sw_desc(claw)
+    d.n[0], d.n[1] = 32768, 16385
+    assert claw.claw_workspace_bytes(d) > 0
+    d.dtype = claw.CLAW_FP64
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_workspace_bytes(d)
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+    assert "4 GiB" in claw.claw_last_error()
+

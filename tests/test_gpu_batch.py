@@ -72,8 +72,8 @@ def test_batch_equals_single_grid_bitwise(claw, dtype):
 
 def test_tiles_and_schedules_do_not_change_results(claw):
     members = inputs.sw_ensemble(sides=SIDES, seed=4, dtype="f32", nsteps=40)
-    base, _, _ = _batch(claw, members, "f32", 40, tiles=(32, 0))
-    for tiles in [(16, 1), (128, 0), (64, 1)]:
+    base, _, _ = _batch(claw, members, "f32", 40, tiles=(32, 0, 8))
+    for tiles in [(16, 1, 2), (128, 0, 4), (64, 1, 8), (32, 0, 2)]:
         outs, _, _ = _batch(claw, members, "f32", 40, tiles=tiles)
         for a, b in zip(outs, base):
             assert np.array_equal(a, b), tiles
@@ -113,13 +113,13 @@ def test_autotuner_cache_roundtrip(claw, tmp_path):
     for a, b in zip(tuned, base):
         assert np.array_equal(a, b)
     text = open(cache).read()
-    assert "gfx950/f32/sw/n7/" in text and "chunk" in text
+    assert "gfx950/f32/sw/n7/" in text and "chunk" in text and "rows_per_wave" in text
     qs = _tensors(members, "f32")
     b = claw.BatchSolver([p for p, _ in members], qs)
     first = b.tune(cache)
     again = b.tune(cache)
     b.close()
-    assert first == again and first["chunk"] in (16, 32, 64, 128)
+    assert first == again and first["chunk"] in (16, 32, 64, 128) and first["rows_per_wave"] in (2, 4, 8)
     # a damaged entry (chunk 0) is not used: the tuner times the candidates again
     with open(cache, "w") as fh:
         fh.write(re.sub(r'"chunk":\s*\d+', '"chunk": 0', text))
@@ -138,3 +138,19 @@ def test_batch_matches_oracle(claw):
         err, per = rel_linf(outs[k], ref["q"])
         assert err <= 1e-5, per
         assert rejs[k] == ref["nreject"]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_matches_oracle_across_the_size_range(claw, dtype):
+    # instances across the ensemble's side range 128 .. 1024 (one above 512,
+    # one ragged), FP32 and FP64, 40 adaptive steps each, every cell compared
+    members = inputs.sw_ensemble(sides=[128, 333, 600, 1024], seed=11, dtype=dtype, nsteps=40)
+    outs, ts, rejs = _batch(claw, members, dtype, 40)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    for k, (prob, q0) in enumerate(members):
+        ref = oracle.advance(prob, q0, None, 40)
+        err, per = rel_linf(outs[k], ref["q"])
+        print(f"batch {dtype} side {prob['n'][0]}: rel Linf {err:.3e} per field {per}", flush=True)
+        assert err <= tol, per
+        assert rejs[k] == ref["nreject"]
+        assert ts[k] == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-6)
