@@ -215,6 +215,30 @@ claw_status claw_advance_fixed(claw_solver* h, int64_t nsteps, const double* dts
 claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms,
                                int64_t* launches);
 
+/* One directional sweep like claw_sweep, without a solver handle or a
+ * workspace, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * grid is described by d (claw_create's rules; flags must not ask for
+ * Strang splitting); src and dst are device states in q's layout (16-byte
+ * aligned, not aliasing); dst receives the sweep of src in direction dir
+ * (0, 1, 2) with time step dt, always accepted; aux as for claw_create.
+ * smax_dev (device double, may be NULL) receives the largest |s| of the
+ * sweep, or a NaN if the sweep met a non-physical state (depth <= 0 or not
+ * finite).  Enqueued on stream, which must belong to the current device; no
+ * synchronisation.
+ * Scratch: the step state, the speed maxima and (maux = 2) the derived
+ * coefficients Z, c live in one static device array per GPU, held until
+ * the process ends: a 32 KiB control block plus CLAW_NOALLOC_ZC_BYTES for
+ * the coefficients; a grid whose coefficients (2 ncell sizeof(real) bytes)
+ * exceed that limit gets CLAW_E_UNSUPPORTED.  Every call clears what it
+ * uses first.  Calls on one GPU share the array: calls that overlap in time
+ * (other streams or host threads on the same GPU) race and must be
+ * serialised by the caller.  The call allocates nothing (no hipMalloc, no
+ * stream or event creation). */
+#define CLAW_NOALLOC_ZC_BYTES (16u << 20)
+claw_status claw_sweep_noalloc(const claw_desc* d, const void* src, void* dst, const void* aux, int32_t dir,
+                               double dt, double* smax_dev, void* stream);
+
 /* Enqueues a copy of the current state into q if it lives in a workspace
  * buffer; no synchronisation.
  * Defined by: section 6 (the caller's array holds the solution it evolves). */

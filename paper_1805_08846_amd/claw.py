@@ -33,7 +33,7 @@ _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDE
         "superbee": CLAW_LIM_SUPERBEE, "vanleer": CLAW_LIM_VANLEER}
 
 EXPORTED = ["claw_desc_init", "claw_plugin_info", "claw_workspace_bytes", "claw_create", "claw_cfl", "claw_step",
-            "claw_sweep", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
+            "claw_sweep", "claw_sweep_noalloc", "claw_advance", "claw_advance_fixed", "claw_advance_timed",
             "claw_sync_state", "claw_get_control", "claw_set_control", "claw_destroy",
             "claw_batch_workspace_bytes", "claw_batch_create", "claw_batch_tune",
             "claw_batch_set_tiles", "claw_batch_advance", "claw_batch_destroy",
@@ -111,6 +111,7 @@ def _load():
         "claw_cfl": (i32, [vp, P(dbl), P(dbl)]),
         "claw_step": (i32, [vp, dbl, P(dbl)]),
         "claw_sweep": (i32, [vp, i32, dbl, P(dbl)]),
+        "claw_sweep_noalloc": (i32, [P(claw_desc), vp, vp, vp, i32, dbl, vp, vp]),
         "claw_advance": (i32, [vp, i64, dbl, P(dbl), P(i64)]),
         "claw_advance_fixed": (i32, [vp, i64, P(dbl), P(dbl)]),
         "claw_advance_timed": (i32, [vp, i64, P(dbl), P(i64)]),
@@ -219,6 +220,24 @@ def claw_sweep(h, direction, dt):
     sm = ctypes.c_double(0)
     _check(_lib.claw_sweep(h, int(direction), float(dt), ctypes.byref(sm)), "claw_sweep")
     return sm.value
+
+
+def claw_sweep_noalloc(desc, src, dst, aux, direction, dt, smax_dev, stream_handle):
+    """One sweep src -> dst with no handle or workspace (scratch in the
+    library's static device memory); smax_dev: a device float64 tensor of one
+    element or None.  Enqueued, no synchronisation."""
+    import torch
+    n = desc.meqn * desc.n[0] * desc.n[1] * desc.n[2]
+    dt_ = torch.float32 if desc.dtype == CLAW_FP32 else torch.float64
+    _need(src, "src", n, dt_)
+    _need(dst, "dst", n, dt_)
+    if desc.maux:
+        _need(aux, "aux", desc.maux * desc.n[0] * desc.n[1] * desc.n[2], dt_)
+    if smax_dev is not None:
+        _need(smax_dev, "smax_dev", 1, torch.float64)
+    _check(_lib.claw_sweep_noalloc(ctypes.byref(desc), _ptr(src), _ptr(dst), _ptr(aux) if desc.maux else None,
+                                   int(direction), float(dt), _ptr(smax_dev), ctypes.c_void_p(stream_handle)),
+           "claw_sweep_noalloc")
 
 
 def claw_advance(h, nsteps, dt0=0.0):

@@ -44,6 +44,8 @@ hipError_t launch_zero_speeds(Ctrl* c, int q, hipStream_t s);
 hipError_t launch_init_dt(Ctrl* c, int q, bool fp32, int mode, int result_off, bool use_next, hipStream_t s);
 hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s);
 hipError_t launch_set_control(Ctrl* c, int q, double t, double dt_next, hipStream_t s);
+// *out = max |s| of direction dir in copy q (NaN if the copy met a non-physical state).
+hipError_t launch_report_smax(const Ctrl* c, int q, int dir, bool fp32, double* out, hipStream_t s);
 
 // Batched ensemble launches (batch.hip): blocks[i] maps workgroup i of a
 // launch to an instance and its logical block; args holds two SweepArgs per

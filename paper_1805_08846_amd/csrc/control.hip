@@ -134,6 +134,17 @@ __global__ void k_sync_state(const Ctrl* c, int q, R* b0, const R* b1, const R* 
 
 __global__ void k_reset_cur(Ctrl* c, int q) { c->st[q].cur = 0; }
 
+// Largest |s| of direction dir recorded in copy q, or a NaN when a sweep of
+// that copy met a non-physical state.
+__global__ void k_report_smax(const Ctrl* c, int q, int dir, int fp32, double* out) {
+    if (c->nonphys[q]) {
+        *out = __builtin_nan("");
+        return;
+    }
+    *out = fp32 ? (double)__uint_as_float(smax32_of(c, q, dir))
+                : __longlong_as_double((long long)smax64_of(c, q, dir));
+}
+
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired, double cfl_max,
                             double dt_max, bool strang, int result_off, hipStream_t s) {
     hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(1), 0, s, c, dx[0], dx[1], dx[2], ndim, cfl_desired,
@@ -163,6 +174,11 @@ hipError_t launch_set_target(Ctrl* c, int q, long long nsteps, hipStream_t s) {
 }
 hipError_t launch_set_control(Ctrl* c, int q, double t, double dt_next, hipStream_t s) {
     hipLaunchKernelGGL(k_set_control, dim3(1), dim3(1), 0, s, c, q, t, dt_next);
+    return hipGetLastError();
+}
+
+hipError_t launch_report_smax(const Ctrl* c, int q, int dir, bool fp32, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_report_smax, dim3(1), dim3(1), 0, s, c, q, dir, fp32 ? 1 : 0, out);
     return hipGetLastError();
 }
 

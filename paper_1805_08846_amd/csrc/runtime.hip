@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -803,6 +804,94 @@ claw_status claw_destroy(claw_solver* h) {
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     delete h;
     if (e != hipSuccess) return fail(CLAW_E_HIP, "stream sync failed: %s", hipGetErrorString(e));
+    return CLAW_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Sweep without allocation: the control block and the derived acoustic
+// coefficients of claw_sweep_noalloc live in `scratch`, a static device array
+// each GPU holds for the life of the process.  Host code never passes the
+// array's name to a kernel (in host code it is only a stand-in for the symbol):
+// its device address is looked up once per device with hipGetSymbolAddress
+// and kept in g_scratch_ptr.  Calls that overlap on one GPU share the array.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchCtrlBytes = 32768;  // the control block, rounded up
+static_assert(sizeof(Ctrl) <= kScratchCtrlBytes, "control block exceeds its scratch slot");
+constexpr size_t kScratchBytes = kScratchCtrlBytes + ((size_t)CLAW_NOALLOC_ZC_BYTES);
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device).
+claw_status scratch_of_current_device(char** out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CLAW_E_UNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(CLAW_E_HIP, "scratch symbol lookup failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (char*)g_scratch_ptr[dev];
+    return CLAW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+claw_status claw_sweep_noalloc(const claw_desc* d, const void* src, void* dst, const void* aux, int32_t dir,
+                               double dt, double* smax_dev, void* stream) {
+    claw_status st = validate(d);
+    if (st) return st;
+    if (!src || !dst) return fail(CLAW_E_INVALID, "src and dst must be device pointers");
+    if (src == dst) return fail(CLAW_E_INVALID, "src and dst must not alias");
+    if (dir < 0 || dir >= d->ndim) return fail(CLAW_E_INVALID, "direction %d out of range", dir);
+    if (!(dt >= 0) || !isfinite(dt)) return fail(CLAW_E_INVALID, "dt must be finite and >= 0");
+    if ((d->maux != 0) != (aux != nullptr)) return fail(CLAW_E_INVALID, "aux must be given iff maux = 2");
+    if (d->flags & CLAW_FLAG_STRANG) return fail(CLAW_E_INVALID, "a single sweep takes no splitting flag");
+    if (((uintptr_t)src % 16) || ((uintptr_t)dst % 16) || (aux && ((uintptr_t)aux % 16)))
+        return fail(CLAW_E_INVALID, "src, dst and aux must be 16-byte aligned");
+    const Plan p = make_plan(d);
+    const size_t zc_bytes = d->maux ? (size_t)p.ncell * 2 * p.elem : 0;
+    if (zc_bytes > (size_t)CLAW_NOALLOC_ZC_BYTES)
+        return fail(CLAW_E_UNSUPPORTED,
+                    "claw_sweep_noalloc: %zu bytes of derived coefficients exceed the %zu-byte scratch "
+                    "limit (use claw_create with a workspace)",
+                    zc_bytes, (size_t)CLAW_NOALLOC_ZC_BYTES);
+    char* sp = nullptr;
+    st = scratch_of_current_device(&sp);
+    if (st) return st;
+    // a handle on the stack over the scratch array: control block first, then
+    // the coefficient fields; rotation buffers 0 = src, 1 = dst (2 unused)
+    claw_solver h{};
+    claw_desc dd = *d;
+    dd.flags = 0;
+    bind_solver(&h, &dd, p, const_cast<void*>(src), sp, (hipStream_t)stream);
+    h.ctrl = (Ctrl*)sp;
+    h.buf[1] = dst;
+    h.buf[2] = dst;
+    h.zc = d->maux ? (void*)(sp + kScratchCtrlBytes) : nullptr;
+    // fresh control block (speed slots and flags cleared by the kernel: no
+    // memset node for a caller that captures this call), then the trial
+    HIP_TRY(setup_kernels(&h, aux));
+    const int q = committed(&h);
+    HIP_TRY(launch_begin(h.ctrl, q, dt, MODE_FIXED, 1, h.stream));
+    HIP_TRY(enqueue_sweep(&h, dir, 0, 1, false, h.parity, true, true, h.stream));
+    h.parity ^= 1;
+    HIP_TRY(launch_commit(h.ctrl, committed(&h), h.fp32, h.stream));
+    if (smax_dev) HIP_TRY(launch_report_smax(h.ctrl, committed(&h), dir, h.fp32, smax_dev, h.stream));
     return CLAW_OK;
 }
 

@@ -285,3 +285,28 @@ def test_fp64_field_byte_limit(claw):
     assert e.value.status == claw.CLAW_E_UNSUPPORTED
     assert "4 GiB" in claw.claw_last_error()
 
+
+def test_noalloc_sweep_rejects_on_the_host(claw):
+    # bad arguments and grids beyond the scratch limit fail before any HIP
+    # call (the pointers below are never dereferenced)
+    fake_a, fake_b, fake_aux = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20), ctypes.c_void_p(3 << 20)
+    d = _sw_desc(claw)
+    lib = claw._lib
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), None, fake_b, None, 0, 0.1, None, None) == claw.CLAW_E_INVALID
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_a, None, 0, 0.1, None, None) == claw.CLAW_E_INVALID
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_b, None, 2, 0.1, None, None) == claw.CLAW_E_INVALID
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_b, None, 0, -1.0, None, None) == claw.CLAW_E_INVALID
+    d.flags = claw.CLAW_FLAG_STRANG
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_b, None, 0, 0.1, None, None) == claw.CLAW_E_INVALID
+    # acoustics with per-cell coefficients: 2 ncell sizeof(real) bytes of
+    # scratch; 1024^2 FP64 (16 MiB) fits the limit, one more row does not
+    from paper_1805_08846_amd import inputs
+    prob, _, _ = inputs.acoustics3d_layers(n=8, dtype="f64", nsteps=1)
+    d = claw.desc_from_problem(prob)
+    assert d.maux == 2
+    d.ndim, d.meqn = 2, 3
+    d.n[0], d.n[1], d.n[2] = 1024, 1025, 1
+    assert lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_b, None, 0, 0.1, None, None) == claw.CLAW_E_INVALID
+    st = lib.claw_sweep_noalloc(ctypes.byref(d), fake_a, fake_b, fake_aux, 0, 0.1, None, None)
+    assert st == claw.CLAW_E_UNSUPPORTED
+    assert "scratch limit" in claw.claw_last_error()
