@@ -41,7 +41,7 @@ def kernel_source_hash():
     """Hash of the sweep kernels' sources with comments and blank lines removed
     (a PMC summary stays valid across comment edits, not across code edits)."""
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h"):
+    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h", "fused.hip"):
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -465,8 +465,11 @@ def main():
                     help="skip the 2048^2 run that follows the headline size (profiling runs)")
     ap.add_argument("--traffic-file", default=None)
     ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d", "sizes"])
-    ap.add_argument("--fused-step", action="store_true",
-                    help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) instead of x and y sweeps")
+    ap.add_argument("--fused-step", dest="fused_step", action="store_const", const=True, default=None,
+                    help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) at every size")
+    ap.add_argument("--split-step", dest="fused_step", action="store_const", const=False,
+                    help="x and y sweep kernels at every size (CLAW_FLAG_SPLIT_STEP); by default the "
+                         "library fuses FP32 steps for states of 96 MiB and more")
     ap.add_argument("--count", type=int, default=256, help="ensemble instances")
     ap.add_argument("--train-runs", type=int, default=200, help="learned: training runs")
     ap.add_argument("--eval-seeds", type=int, default=5, help="learned: held-out evaluation seeds")
@@ -519,14 +522,17 @@ def main():
         bw = achievable_bandwidth(torch, claw)
         line["achievable_GBps"] = bw
         best_rw = max(bw["copy"], bw["copy_nt"])
-        line["roofline"]["frac_of_achievable_copy"] = line["roofline"]["achieved"] / best_rw
-        # the same copy kernels at one sweep's size (one state read, one written),
-        # back to back like the sweeps: launch gaps and ramp included
-        alg_bytes = line["roofline"]["alg_bytes_per_launch"]
-        bw_s = achievable_bandwidth(torch, claw, nbytes=alg_bytes // 2, reps=50 if n >= 4096 else 200)
+        # a sweep and the fused step both read the state once and write it once:
+        # that copy rate of the dominant kernel against the copy kernels
+        rf = line["roofline"]
+        state_rate = 2 * rf["state_bytes"] / (rf["avg_launch_us"] * 1e-6) / 1e9
+        rf["state_copy_GBps"] = state_rate
+        rf["frac_of_achievable_copy"] = state_rate / best_rw
+        # the same copy kernels at the state's size, back to back like the
+        # sweeps: launch gaps and ramp included
+        bw_s = achievable_bandwidth(torch, claw, nbytes=rf["state_bytes"], reps=50 if n >= 4096 else 200)
         line["achievable_GBps_sweep_size"] = bw_s
-        line["roofline"]["frac_of_copy_at_sweep_size"] = line["roofline"]["achieved"] / max(
-            bw_s["copy"], bw_s["copy_nt"])
+        rf["frac_of_copy_at_sweep_size"] = state_rate / max(bw_s["copy"], bw_s["copy_nt"])
     if not args.no_cpu_baseline:
         prob, q0, _ = inputs.sw_radial_dam(n=n, dtype=args.dtype, nsteps=steps)
         csteps = args.cpu_steps if args.cpu_steps else max(2, int(round(1e9 / (n * n))))
@@ -574,17 +580,22 @@ def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):
     timed = args.timed_steps if n < 4096 else min(args.timed_steps, 100)
     ms, cnt = solver.advance_timed(timed)
     names = ["x_sweep", "y_sweep", "z_sweep", "control"]
-    if args.fused_step:
-        names[0] = "step2d"  # one fused kernel per step: same algorithmic bytes per launch
+    fused = cnt[0] > 0 and cnt[1] == 0  # the library ran one fused kernel per step
+    if fused:
+        names[0] = "step2d"
     avg_us = {names[k]: (ms[k] / cnt[k] * 1e3 if cnt[k] else None) for k in range(4)}
     sweeps = [k for k in range(2) if cnt[k]]
     dom = max(sweeps, key=lambda k: ms[k] / cnt[k])
-    alg_bytes = 2 * 3 * real_bytes * ncell
+    # algorithmic bytes of the method per launch: each sweep reads and writes
+    # every field of every cell once (2 meqn sizeof(real) per cell per sweep);
+    # a fused launch carries both sweeps of a step
+    alg_bytes = (2 if fused else 1) * 2 * 3 * real_bytes * ncell
     dom_s = ms[dom] / cnt[dom] * 1e-3
     achieved = alg_bytes / dom_s / 1e9
     pmc_file = args.traffic_file or os.path.join(ROOT, "profiles", f"pmc_sweeps_sw{n}_{args.dtype}.txt")
     traffic = load_traffic(pmc_file, names[dom], kernel_source_hash())
     valu = load_pmc(pmc_file, names[dom], "valu_insts", kernel_source_hash())
+    valu_frac = load_pmc(pmc_file, names[dom], "valu_issue_frac", kernel_source_hash())
     print(f"# kernel averages (us): {avg_us}", file=sys.stderr, flush=True)
     solver.close()
     del q, q_init
@@ -593,7 +604,11 @@ def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                 "kernel": names[dom], "alg_bytes_per_launch": alg_bytes,
-                "avg_launch_us": dom_s * 1e6}
+                "state_bytes": 3 * real_bytes * ncell, "avg_launch_us": dom_s * 1e6}
+    if fused:
+        roofline["note"] = ("one fused kernel per step: it carries both sweeps' algorithmic bytes and "
+                            "moves about half of them (the intermediate state stays in LDS); "
+                            "traffic gives the measured HBM bytes")
     figures = {
         "value": value,
         "ms_per_step": elapsed / steps * 1e3,
@@ -601,12 +616,13 @@ def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):
         "warmup": warmup,
         "roofline": roofline,
         "kernel_avg_us": avg_us,
-        # the same kernel against the VALU issue rate: SQ_INSTS_VALU (wave
-        # instructions per launch, committed PMC summary) x 64 lanes over the
-        # live launch time
+        # the same kernel against the VALU issue rate, from the committed PMC
+        # summary: SQ_INSTS_VALU per launch and its fraction of the issue peak
+        # over the profiled run's own traced durations (its steps are the run's
+        # first ones, not the event-timed window above)
         "valu_issue": None if valu is None else {
-            "wave_insts_per_launch": valu, "lane_ops_per_s": valu * 64 / dom_s,
-            "peak": VALU_LANE_OPS_PEAK, "frac": valu * 64 / dom_s / VALU_LANE_OPS_PEAK},
+            "wave_insts_per_launch": valu, "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+            "frac_in_profiled_run": valu_frac, "source": os.path.relpath(pmc_file, ROOT)},
         "hbm_frac_whole_step": value * 1e9 * sum(1 for k in range(4) if cnt[k]) * alg_bytes / ncell /
         (HBM_PEAK_GBPS * 1e9),
         "rejected_trials": nrej,

@@ -47,10 +47,18 @@ extern "C" {
 typedef struct claw_solver claw_solver; /* opaque */
 
 /* claw_desc.flags: CLAW_FLAG_FUSED_STEP runs each 2D shallow-water step as one
- * kernel (the x sweep kept in LDS, then the y sweep) instead of an x and a y
- * sweep kernel; same results to rounding, one read and one write of the state
- * per step.  Needs non-periodic y boundaries; ignored for other problems. */
+ * kernel (rows x-swept into LDS, then y-swept out of it) instead of an x and a
+ * y sweep kernel; the same results, one read and one write of the state per
+ * step.  CLAW_FLAG_SPLIT_STEP asks for the x and y sweep kernels.  With
+ * neither flag an FP32 2D shallow-water grid (Godunov splitting) takes the
+ * fused step when its state holds at least CLAW_FUSED_AUTO_BYTES (measured on
+ * MI355X: fused faster from 3072^2 (108 MiB) up, the sweeps faster at 2048^2,
+ * whose source and destination stay in the 256 MB Infinity Cache), else the x
+ * and y sweeps; FP64 grids take the sweeps (measured faster at every size).  Other problems ignore
+ * both flags. */
 #define CLAW_FLAG_FUSED_STEP 1
+#define CLAW_FLAG_SPLIT_STEP 4
+#define CLAW_FUSED_AUTO_BYTES (96ull << 20)
 /* claw_desc.flags: CLAW_FLAG_STRANG replaces Godunov splitting (x, y (, z)
  * sweeps of dt) by Strang splitting: sweeps of dt/2 around a full-dt sweep of
  * the last direction (x/2 y x/2 in 2D, x/2 y/2 z y/2 x/2 in 3D), second order

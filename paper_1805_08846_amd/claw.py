@@ -27,6 +27,7 @@ CLAW_BC_EXTRAP, CLAW_BC_WALL, CLAW_BC_PERIODIC = 0, 1, 2
 CLAW_LIM_MC, CLAW_LIM_NONE, CLAW_FIRST_ORDER, CLAW_LIM_MINMOD, CLAW_LIM_SUPERBEE, CLAW_LIM_VANLEER = range(6)
 CLAW_FLAG_FUSED_STEP = 1
 CLAW_FLAG_STRANG = 2
+CLAW_FLAG_SPLIT_STEP = 4
 
 _BC = {"extrap": CLAW_BC_EXTRAP, "wall": CLAW_BC_WALL, "periodic": CLAW_BC_PERIODIC}
 _LIM = {"mc": CLAW_LIM_MC, "none": CLAW_LIM_NONE, "first_order": CLAW_FIRST_ORDER, "minmod": CLAW_LIM_MINMOD,
@@ -591,7 +592,8 @@ def desc_from_problem(prob):
     d.cfl_max = float(prob.get("cfl_max", 1.0))
     dm = prob.get("dt_max", float("inf"))
     d.dt_max = float(dm) if dm is not None else math.inf
-    d.flags = (CLAW_FLAG_FUSED_STEP if prob.get("fused_step") else 0) | \
+    fs = prob.get("fused_step")  # True: fused, False: x and y sweeps, None: the library's choice
+    d.flags = (CLAW_FLAG_FUSED_STEP if fs else (CLAW_FLAG_SPLIT_STEP if fs is False else 0)) | \
         (CLAW_FLAG_STRANG if prob.get("splitting", "godunov") == "strang" else 0)
     return d
 

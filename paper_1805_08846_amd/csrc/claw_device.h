@@ -727,11 +727,45 @@ __device__ __forceinline__ void iface_next(const Iface<R, SYS>& in, Iface<R, SYS
     }
 }
 
+__device__ __forceinline__ float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                            __builtin_amdgcn_readlane(__double2loint(v), 63));
+}
+
+// Wavefront maximum of non-negative values (speeds): DPP prefix maxima within
+// each 16-lane row (shifts 1, 2, 4, 8), then row broadcasts 15 and 31, which
+// leave the maximum in lane 63.  Lanes without a source read 0, the identity
+// of max on non-negative values.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_move(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, true);
+}
+// FP32: non-negative values order like their bit patterns, so an unsigned
+// integer max does it (no canonicalising of the float operands)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_max_step(float v) {
+    const unsigned a = (unsigned)__float_as_int(v);
+    const unsigned b = (unsigned)dpp_move<CTRL, ROWS>(__float_as_int(v));
+    return __int_as_float((int)(a > b ? a : b));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_max_step(double v) {
+    const double o = __hiloint2double(dpp_move<CTRL, ROWS>(__double2hiint(v)),
+                                      dpp_move<CTRL, ROWS>(__double2loint(v)));
+    return rmax(v, o);
+}
 template <typename R>
 __device__ __forceinline__ R wave_max(R v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = rmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return lane63(v);
 }
 
 // Per-direction speed maximum: non-negative IEEE values order like their bit

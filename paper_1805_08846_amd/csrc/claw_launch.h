@@ -21,19 +21,21 @@ inline bool batch_rpw_ok(int rpw) { return rpw == 2 || rpw == 4 || rpw == 8; }
 template <typename R>
 hipError_t launch_sweep(const SweepArgs<R>& a, int sys, int meqn, bool speeds, hipStream_t s);
 
-// Fused 2D shallow-water step (fused.hip): x sweep into an LDS tile, y sweep
-// out of it.  a: the x-sweep arguments (grid, buffers, control, x boundaries,
-// parity); ny and the y boundaries complete the grid.
+// Fused 2D shallow-water step (fused.hip): each workgroup marches a strip of
+// columns down a chunk of rows, x-sweeping rows into LDS and y-sweeping them
+// out.  a: the x-sweep arguments (grid, buffers, control, x boundaries,
+// parity, limiter); ny and the y boundaries complete the grid; chunk: rows
+// per workgroup.
 template <typename R>
 struct FusedArgs {
     SweepArgs<R> a;
-    int32_t ny, bcy_lo, bcy_hi, pad;
+    int32_t ny, bcy_lo, bcy_hi, chunk;
 };
 template <typename R>
 hipError_t launch_step2d(const FusedArgs<R>& F, hipStream_t s);
 // Decides the previous trial into step-state copy p and clears p's speed slots.
 hipError_t launch_open(Ctrl* c, int p, bool fp32, hipStream_t s);
-int fused_tile_rows();
+int fused_rows_per_iteration();
 
 // One-thread step-control kernels on step-state copy q (see control.hip).
 hipError_t launch_ctrl_init(Ctrl* c, const double* dx, int ndim, double cfl_desired,

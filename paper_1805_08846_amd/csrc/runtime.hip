@@ -71,8 +71,10 @@ claw_status validate(const claw_desc* d) {
     }
     if (d->ndim == 2 && d->n[2] != 1) return fail(CLAW_E_INVALID, "2D grids need n[2] = 1");
     if (d->num_ghost != 2) return fail(CLAW_E_INVALID, "num_ghost must be 2 (got %d)", d->num_ghost);
-    if (d->flags & ~(CLAW_FLAG_FUSED_STEP | CLAW_FLAG_STRANG))
+    if (d->flags & ~(CLAW_FLAG_FUSED_STEP | CLAW_FLAG_STRANG | CLAW_FLAG_SPLIT_STEP))
         return fail(CLAW_E_INVALID, "unknown flags 0x%x", (unsigned)d->flags);
+    if ((d->flags & CLAW_FLAG_FUSED_STEP) && (d->flags & CLAW_FLAG_SPLIT_STEP))
+        return fail(CLAW_E_INVALID, "CLAW_FLAG_FUSED_STEP and CLAW_FLAG_SPLIT_STEP exclude each other");
     if (d->dtype != CLAW_FP32 && d->dtype != CLAW_FP64) return fail(CLAW_E_INVALID, "unknown dtype");
     if (d->limiter < 0 || d->limiter > 5) return fail(CLAW_E_INVALID, "unknown limiter");
     if (!(d->cfl_desired > 0) || !(d->cfl_max >= d->cfl_desired))
@@ -275,6 +277,36 @@ int result_offset_of(const claw_solver* h) {
     return dof[k - 1];
 }
 
+// Rows per workgroup of the fused 2D step: about four rounds of the
+// workgroups a device holds at once (four per CU: one wavefront per SIMD each,
+// four wavefronts per SIMD), so the last round leaves few CUs idle, and at
+// least 24 rows so the four halo rows a chunk sweeps twice stay a small share
+// (measured at 4096^2 FP32: 16 / 24 / 32 / 48 rows give 165.8 / 154.4 / 158.4 /
+// 169.6 us per step; at 8192^2 the rule's 68 rows 551 us, 32 / 64 / 96 rows
+// 559 / 544 / 551 us).
+// CLAW_FUSED_CHUNK overrides the choice for tuning (read once per process;
+// values <= 0 are ignored).
+int fused_chunk(int64_t nx, int64_t ny, bool fp32) {
+    static const int64_t target = [] {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        return (int64_t)16 * cus;
+    }();
+    static const int64_t forced = [] {
+        const char* e = getenv("CLAW_FUSED_CHUNK");
+        return e ? (int64_t)atoll(e) : (int64_t)0;
+    }();
+    const int64_t w = fp32 ? 248 : 124;
+    const int64_t strips = (nx + w - 1) / w;
+    int64_t chunk = forced > 0 ? forced : (strips * ny + target - 1) / target;
+    if (forced <= 0 && chunk < 24) chunk = 24;
+    if (chunk > ny) chunk = ny;
+    if (chunk < 1) chunk = 1;
+    return (int)chunk;
+}
+
 template <typename R>
 FusedArgs<R> fused_args(const claw_solver* h, int parity) {
     FusedArgs<R> F;
@@ -284,6 +316,7 @@ FusedArgs<R> fused_args(const claw_solver* h, int parity) {
     F.ny = (int32_t)h->d.n[1];
     F.bcy_lo = h->d.bc_lo[1];
     F.bcy_hi = h->d.bc_hi[1];
+    F.chunk = fused_chunk(h->d.n[0], h->d.n[1], h->fp32);
     return F;
 }
 
@@ -439,8 +472,9 @@ void bind_solver(claw_solver* h, const claw_desc* d, const Plan& p, void* q, cha
     h->sys = d->riemann >= CLAW_RP_PLUGIN_BASE ? d->riemann
              : (d->riemann == CLAW_RP_SHALLOW_WATER ? SYS_SW : (d->maux ? SYS_ACV : SYS_AC));
     h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
-    h->fused = (d->flags & CLAW_FLAG_FUSED_STEP) && !h->strang && h->sys == SYS_SW && d->ndim == 2 &&
-               d->bc_lo[1] != CLAW_BC_PERIODIC && d->bc_hi[1] != CLAW_BC_PERIODIC;
+    const bool fusable = !h->strang && h->sys == SYS_SW && d->ndim == 2;
+    const bool big = d->dtype == CLAW_FP32 && (uint64_t)p.state_bytes >= (uint64_t)CLAW_FUSED_AUTO_BYTES;
+    h->fused = fusable && ((d->flags & CLAW_FLAG_FUSED_STEP) || (big && !(d->flags & CLAW_FLAG_SPLIT_STEP)));
     h->stream = stream;
     h->ctrl = (Ctrl*)(ws + p.off_ctrl);
     h->buf[0] = q;
@@ -877,7 +911,7 @@ claw_status claw_sweep_noalloc(const claw_desc* d, const void* src, void* dst, c
     // the coefficient fields; rotation buffers 0 = src, 1 = dst (2 unused)
     claw_solver h{};
     claw_desc dd = *d;
-    dd.flags = 0;
+    dd.flags = CLAW_FLAG_SPLIT_STEP;
     bind_solver(&h, &dd, p, const_cast<void*>(src), sp, (hipStream_t)stream);
     h.ctrl = (Ctrl*)sp;
     h.buf[1] = dst;

@@ -50,7 +50,7 @@ def kernel_source_hash():
     """Hash of the sweep kernels' sources without comments and blank lines
     (the same function bench.py uses to accept a summary)."""
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h"):
+    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h", "fused.hip"):
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -85,7 +85,7 @@ def trace(path, title, command):
 
 
 def read_counters(paths):
-    """(kernel name, counter) -> list of per-dispatch values."""
+    """(kernel name, counter) -> list of per-dispatch values in dispatch order."""
     vals = defaultdict(dict)
     for p in paths:
         with open(p) as fh:
@@ -93,7 +93,7 @@ def read_counters(paths):
                 key = (row["Kernel_Name"], row["Counter_Name"])
                 d = int(row["Dispatch_Id"])
                 vals[key][d] = vals[key].get(d, 0.0) + float(row["Counter_Value"])
-    return {k: list(v.values()) for k, v in vals.items()}
+    return {k: [v[d] for d in sorted(v)] for k, v in vals.items()}
 
 
 def _median(v):
@@ -104,7 +104,7 @@ def pmc(args):
     c = read_counters(args.csv)
     kernels = sorted({k for k, _ in c})
     copy = [k for k in kernels if "k_copy<false>" in k]
-    alg = 2 * 3 * args.real_bytes * args.ncell
+    alg = 2 * 3 * args.real_bytes * args.ncell  # one sweep; the fused step carries two
     out = [f"# rocprofv3 counters: {args.title}", ""]
     if args.commands_file:
         with open(args.commands_file) as fh:
@@ -112,22 +112,24 @@ def pmc(args):
         out.append("")
     scale = {"FETCH_SIZE": 1.0, "WRITE_SIZE": 1.0}
     if copy:
-        # the largest copy dispatches are the 1 GiB ones (2^20 KiB read and written)
+        # the benchmark's first copy dispatches (warm-up and repetitions of the
+        # achievable-bandwidth run) move 1 GiB each way (2^20 KiB read and written)
         for cn in scale:
-            v = c.get((copy[0], cn), [])
-            if v and max(v) > 0.25 * 2 ** 20:
-                scale[cn] = 2 ** 20 / max(v)
+            v = c.get((copy[0], cn), [])[:3]
+            if v and statistics.median(v) > 0.25 * 2 ** 20:
+                scale[cn] = 2 ** 20 / statistics.median(v)
         out.append("calibration: plain copy kernel k_copy<false> (claw_stream_bench), 1 GiB read + 1 GiB "
-                   "written per dispatch, same runs")
+                   "written per dispatch (the run's first copy dispatches), same runs")
         for cn in scale:
-            v = c.get((copy[0], cn), [])
-            if v and max(v) > 0.25 * 2 ** 20:
-                out.append(f"- {cn} per copy dispatch (KiB): {max(v):.1f} -> scale {scale[cn]:.4f}")
+            v = c.get((copy[0], cn), [])[:3]
+            if v and statistics.median(v) > 0.25 * 2 ** 20:
+                out.append(f"- {cn} per copy dispatch (KiB): {statistics.median(v):.1f} -> scale {scale[cn]:.4f}")
         out.append("")
     out.append(f"algorithmic bytes per sweep launch: {alg}")
     stats = read_stats(args.trace) if args.trace else {}
     for pat, cls in SWEEP_CLASSES:
-        names = [k for k in kernels if pat in k and ", false, 0>" in k]
+        # the MC-specialised kernels: sweeps <..., false (no speed pass), 0>, fused step <..., 0>
+        names = [k for k in kernels if pat in k and (", false, 0>" in k or (cls == "step2d" and ", 0>" in k))]
         if not names:
             continue
         name = names[0]
@@ -135,13 +137,15 @@ def pmc(args):
         n = len(c.get((name, "SQ_WAVES"), []) or c.get((name, "FETCH_SIZE"), []))
         out.append(f"{cls} kernel {name}: {n} dispatches (medians per dispatch)")
         fs, ws = _median(c.get((name, "FETCH_SIZE"), [])), _median(c.get((name, "WRITE_SIZE"), []))
+        alg_k = alg * (2 if cls == "step2d" else 1)
         if fs is not None and ws is not None:
             rb, wb = fs * scale["FETCH_SIZE"] * 1024, ws * scale["WRITE_SIZE"] * 1024
+            out.append(f"- algorithmic bytes per launch: {alg_k}")
             out.append(f"- FETCH_SIZE KiB: {fs:.1f} (scaled {rb / 1024:.1f})")
             out.append(f"- WRITE_SIZE KiB: {ws:.1f} (scaled {wb / 1024:.1f})")
             out.append(f"- {cls}_hbm_bytes_per_launch: {rb + wb:.0f}")
-            out.append(f"- ratio to algorithmic bytes: {(rb + wb) / alg:.3f} (read {2 * rb / alg:.3f}, "
-                       f"written {2 * wb / alg:.3f})")
+            out.append(f"- ratio to algorithmic bytes: {(rb + wb) / alg_k:.3f} (read {2 * rb / alg_k:.3f}, "
+                       f"written {2 * wb / alg_k:.3f})")
         waves = _median(c.get((name, "SQ_WAVES"), []))
         valu = _median(c.get((name, "SQ_INSTS_VALU"), []))
         if waves:
@@ -157,9 +161,10 @@ def pmc(args):
             tr = [v for k, v in stats.items() if k.startswith(name.split("(")[0])]
             if tr:
                 avg_s = tr[0][1] * 1e-9
+                frac = 4 * valu / (VALU_PEAK_SIMD_CLOCKS * avg_s)
                 out.append(f"- traced average duration: {tr[0][1] / 1e3:.2f} us -> VALU issue fraction = "
-                           f"4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x duration) = "
-                           f"{4 * valu / (VALU_PEAK_SIMD_CLOCKS * avg_s):.3f}")
+                           f"4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x duration) = {frac:.3f}")
+                out.append(f"- {cls}_valu_issue_frac_per_launch: {frac:.4f}")
     out.append("")
     out.append(f"kernel_source_hash: {kernel_source_hash()}")
     return "\n".join(out) + "\n"

@@ -103,3 +103,16 @@ def test_acoustics3d_256_fp32_200_steps(claw):
     assert nrej == 0 == ref["nreject"]
     assert t == ref["t"] and abs(t - 0.703125) <= 1e-12
     assert err <= 1e-5
+
+
+def test_sw8192_fp32_fused_step_20_adaptive_steps(claw):
+    # the benchmark's headline configuration and launch (8192^2 FP32: the
+    # library takes the fused step by itself), every cell against the oracle
+    prob, q0, _ = inputs.sw_radial_dam(n=8192, dtype="f32", nsteps=20, seed=0)
+    ref = _oracle_run("sw8192_f32_20", prob, q0, None, 20)
+    out, t, nrej = _run(claw, prob, q0, None)
+    err, per = rel_linf(out, ref["q"])
+    print(f"sw8192 fp32 fused, 20 adaptive steps: rel Linf {err:.3e} per field {per}, t {t} vs {ref['t']}")
+    assert nrej == ref["nreject"]
+    assert t == pytest.approx(ref["t"], rel=1e-6)
+    assert err <= 1e-5

@@ -1,8 +1,10 @@
-"""The fused 2D shallow-water step (CLAW_FLAG_FUSED_STEP: x sweep kept in LDS,
-then the y sweep, one kernel per step) against the CPU oracle and against the
-two-kernel path: same tolerances as the two-kernel path (FP64 1e-12, FP32 1e-5
-relative L-infinity of the whole state); tile edges in x and y, ragged tiles,
-FP32 and FP64 tile widths, walls and extrapolation in y."""
+"""The fused 2D shallow-water step (CLAW_FLAG_FUSED_STEP: rows x-swept into
+LDS, then y-swept out of it, one kernel per step) against the CPU oracle and
+against the two-kernel path: same tolerances as the two-kernel path (FP64
+1e-12, FP32 1e-5 relative L-infinity of the whole state); strip and chunk
+edges in x and y, ragged strips, FP32 and FP64 strip widths, walls,
+extrapolation and periodic boundaries in y; the library's automatic choice
+of the fused step for large states."""
 import numpy as np
 import pytest
 
@@ -81,11 +83,38 @@ def test_fused_prescribed_steps_fp32(claw):
     assert rel_linf(out, qf)[0] <= 1e-5
 
 
-def test_periodic_y_falls_back_to_two_kernels(claw):
-    prob, q0, _ = inputs.sw_radial_dam(n=64, dtype="f64", nsteps=5, seed=1)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_periodic_y(claw, dtype):
+    # ghost rows of a periodic y boundary come from the far end of the grid
+    prob, q0, _ = inputs.sw_radial_dam(n=64, dtype=dtype, nsteps=5, seed=1)
+    prob["n"] = (300, 45, 1)
     prob["bc_lo"] = ("wall", "periodic", "periodic")
     prob["bc_hi"] = ("wall", "periodic", "periodic")
-    out, _, _, cnt = _run(claw, prob, q0, True, steps=5)
-    assert cnt[1] >= 1  # x and y sweep kernels
-    ref = oracle.advance(prob, q0, None, 5)
-    assert rel_linf(out, ref["q"])[0] <= 1e-12
+    rng = np.random.default_rng(12)
+    q0 = np.zeros((3, 1, 45, 300))
+    q0[0] = 1.0 + 0.5 * rng.uniform(size=(1, 45, 300))
+    q0[1] = 0.2 * rng.uniform(-1, 1, size=(1, 45, 300))
+    q0[2] = 0.2 * rng.uniform(-1, 1, size=(1, 45, 300))
+    if dtype == "f32":
+        q0 = q0.astype(np.float32).astype(np.float64)
+    out, _, _, cnt = _run(claw, prob, q0, True, steps=25)
+    assert cnt[0] >= 1 and cnt[1] == 0  # one kernel per step
+    ref = oracle.advance(prob, q0, None, 25)
+    assert rel_linf(out, ref["q"])[0] <= TOL[dtype]
+    split, _, _, _ = _run(claw, prob, q0, False, steps=25)
+    assert rel_linf(out, split)[0] <= (1e-13 if dtype == "f64" else 1e-6)
+
+
+def test_large_states_take_the_fused_step_by_default(claw):
+    # 4800^2 FP32 (264 MiB of state, above CLAW_FUSED_AUTO_BYTES): the library
+    # chooses the fused step by itself; same result as the forced split path
+    prob, q0, _ = inputs.sw_radial_dam(n=4800, dtype="f32", nsteps=4, seed=2)
+    prob = dict(prob, fused_step=None)
+    out, _, _, cnt = _run(claw, prob, q0, None, steps=4)
+    assert cnt[0] >= 1 and cnt[1] == 0
+    split, _, _, cnt2 = _run(claw, prob, q0, False, steps=4)
+    assert cnt2[1] >= 1
+    assert rel_linf(out, split)[0] <= 1e-6
+    small, qs, _ = inputs.sw_radial_dam(n=512, dtype="f32", nsteps=2, seed=2)
+    _, _, _, cnt3 = _run(claw, small, qs, None, steps=2)
+    assert cnt3[1] >= 1  # a small state keeps the x and y sweep kernels
