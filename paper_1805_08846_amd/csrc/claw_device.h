@@ -199,12 +199,31 @@ __device__ __forceinline__ R* pick_buf(const SweepArgs<R>& a, int i) {
 }
 
 // ---------------------------------------------------------------------------
-// Precision helpers.  FP64 keeps correctly rounded division and square root;
-// FP32 uses the hardware reciprocal and square root (about 1 ulp).
+// Precision helpers.  FP64 divisions and square roots off the hot path (the
+// entropy fix's transonic branch, plug-in solvers) are correctly rounded; the
+// hot path's reciprocals and reciprocal square roots are Newton-refined
+// hardware approximations.  FP32 uses the hardware reciprocal and square root
+// (about 1 ulp).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
-__device__ __forceinline__ double frcp(double a) { return 1.0 / a; }
 __device__ __forceinline__ double fsqrt(double a) { return __builtin_sqrt(a); }
+// FP64 reciprocal and reciprocal square root on the hot path: the hardware
+// approximations refined by two Newton-Raphson steps (each about doubles the
+// correct bits), within a few ulp instead of correctly rounded, for a
+// fraction of the instructions of IEEE division and square root.
+__device__ __forceinline__ double frcp(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-a, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ double frsq(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    const double h = 0.5 * a;
+    y = y * __builtin_fma(-h * y, y, 1.5);  // y (3 - a y^2) / 2
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    return y;
+}
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ float frcp(float a) { return __builtin_amdgcn_rcpf(a); }
 __device__ __forceinline__ float fsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
@@ -278,8 +297,9 @@ struct Cell<R, SYS_ACV> {
 // shallow water: depth, normal and tangential momentum plus derived per-cell
 // values shared by both interfaces of the cell
 __device__ __forceinline__ void sw_cell_derive(double h, double sg, double& ih, double& sqh, double& c) {
-    ih = 1.0 / h;
-    sqh = __builtin_sqrt(h);
+    const double r = frsq(h);  // 1/sqrt(h): sqrt(h) = h r, 1/h = r r
+    ih = r * r;
+    sqh = h * r;
     c = sg * sqh;
 }
 __device__ __forceinline__ void sw_cell_derive(float h, float sg, float& ih, float& sqh, float& c) {
@@ -362,8 +382,9 @@ __device__ __forceinline__ void riemann(const Cell<R, SYS_ACV>& l, const Cell<R,
 
 // Roe speed of sound c^ = sqrt(g hbar) and 1 / (2 c^)
 __device__ __forceinline__ void roe_c(double x, double& c, double& i2c) {
-    c = __builtin_sqrt(x);
-    i2c = 0.5 / c;
+    const double r = frsq(x);
+    c = x * r;
+    i2c = 0.5 * r;
 }
 __device__ __forceinline__ void roe_c(float x, float& c, float& i2c) {
     float r = frsq(x);

@@ -110,6 +110,11 @@ struct LcNet {
     const float* g;  // training: cell gradients (3, ny, nx)
     float nux, nuy;
     float* partial;  // training: [direction][wave][LC_NET]
+    // mask != 0: the forward pass writes zero on faces that fail the
+    // fallback's indicator test (tau, kappa as in LcApply), for an
+    // application that then skips that test (LcApply::premasked)
+    int mask;
+    float tau, kappa;
 };
 struct LcCell {
     const float *dF, *dG, *target, *plain;
@@ -134,6 +139,7 @@ struct LcApply {
     int nx, ny, ncell;
     float nux, nuy, tau, kappa;
     float s_out[3];  // output scales per frame channel (magnitude test)
+    int premasked;   // dF / dG already zero where the indicator test fails
 };
 struct LcParams {
     float *theta, *m, *v;

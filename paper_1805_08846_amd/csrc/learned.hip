@@ -25,6 +25,16 @@
 // dimension: the D tile of a layer is then exactly the B operand of the next
 // layer, so activations never leave registers.  Weight gradients need the
 // faces on the K dimension and go through a per-wavefront LDS transpose.
+//
+// The forward pass takes gfx950's v_mfma_f32_16x16x32_bf16 for the two
+// 64-wide products: a lane holds 8 K values.  Lane group kb joins the D
+// elements of two consecutive 16-unit tiles, so K block s (units 32 s ..
+// 32 s + 31) gives lane group kb units 32 s + 4 kb + {0..3} and
+// 32 s + 16 + 4 kb + {0..3}; the weight operands use the same K order (a
+// product sums over K, any order shared by both operands gives the same
+// sum).  The BF16 weight copies are stored in exactly these operand layouts
+// (w1_slot, w2_slot, w3_slot), so every lane loads its operands with 8- and
+// 16-byte loads.
 #include "claw_launch.h"
 
 namespace claw {
@@ -34,16 +44,47 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 hbf16x8 __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ f32x4 mma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
-
-// FP32 -> BF16, round to nearest even (finite inputs).
-__device__ __forceinline__ short to_bf16(float x) {
-    unsigned u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
+__device__ __forceinline__ f32x4 mma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(hbf16x8, a), __builtin_bit_cast(hbf16x8, b),
+                                                   c, 0, 0, 0);
 }
+__device__ __forceinline__ bf16x8 join(bf16x4 lo, bf16x4 hi) {
+    return bf16x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+}
+
+// Slots of the BF16 operand copies (one network): W1 as the A operand of
+// the 16x16x16 product per unit tile t, W2 and W3 as the A operands of the
+// 16x16x32 products per unit tile t and K block s.  Slots no weight maps to
+// (features 12 .. 15, output rows 3 .. 15) hold zeros.
+__device__ __forceinline__ int kblock_lane(int v, int& e) {  // unit v within its K block -> lane group, element
+    const int w = v & 31;
+    e = (w & 3) + (w & 16 ? 4 : 0);
+    return (w & 15) >> 2;
+}
+__device__ __forceinline__ int w1_slot(int u, int f) {
+    return ((u >> 4) * 64 + (u & 15) + 16 * (f >> 2)) * 4 + (f & 3);
+}
+__device__ __forceinline__ int w2_slot(int u, int v) {
+    int e;
+    const int kb = kblock_lane(v, e);
+    return (((u >> 4) * 2 + (v >> 5)) * 64 + (u & 15) + 16 * kb) * 8 + e;
+}
+__device__ __forceinline__ int w3_slot(int o, int v) {
+    int e;
+    const int kb = kblock_lane(v, e);
+    return ((v >> 5) * 64 + o + 16 * kb) * 8 + e;
+}
+
+// FP32 -> BF16, round to nearest even (gfx950's v_cvt_pk_bf16_f32 under the
+// default rounding mode; the same bits as adding 0x7FFF plus the kept lowest
+// bit and truncating, for finite inputs).
+__device__ __forceinline__ short to_bf16(float x) { return __builtin_bit_cast(short, (__bf16)x); }
 
 __device__ __forceinline__ bf16x4 pack4(f32x4 v) {
     bf16x4 r;
@@ -60,6 +101,21 @@ __device__ __forceinline__ f32x4 relu4(f32x4 v) {
 }
 
 constexpr int WAVES = 4;  // wavefronts per workgroup
+
+// FP32 arithmetic of the fallback, no contraction: its decisions must not
+// depend on how the compiler fuses the products.
+__device__ __forceinline__ float fmul(float x, float y) { return __fmul_rn(x, y); }
+__device__ __forceinline__ float fsub(float x, float y) { return __fsub_rn(x, y); }
+__device__ __forceinline__ float fadd(float x, float y) { return __fadd_rn(x, y); }
+
+// Fallback indicator of one face: the depth jump at most tau times the
+// smaller depth, and each correction component d[c] at most bound[c].
+__device__ __forceinline__ bool indicator_ok(float hl, float hr, float tau, const float d[3], const float bound[3]) {
+    const float lo = hl < hr ? hl : hr;
+    bool ok = fabsf(fsub(hr, hl)) <= fmul(tau, lo);
+    for (int c = 0; c < 3; ++c) ok = ok && (fabsf(d[c]) <= bound[c]);
+    return ok;
+}
 
 // Geometry of one face tile of 64 consecutive faces along a line.
 struct FaceTile {
@@ -135,13 +191,13 @@ __device__ __forceinline__ void load_net(const NetPtr& N, int lane, NetRegs& R) 
     const int i = lane & 15, kb = lane >> 4;
     for (int t = 0; t < 4; ++t) {
         for (int e = 0; e < 4; ++e) {
-            R.A1[t][e] = (short)N.w1b[(16 * t + i) * 16 + 4 * kb + e];
+            R.A1[t][e] = (short)N.w1b[w1_slot(16 * t + i, 4 * kb + e)];
             R.B1[t][e] = N.theta[LC_OFF_B1 + 16 * t + 4 * kb + e];
             R.B2[t][e] = N.theta[LC_OFF_B2 + 16 * t + 4 * kb + e];
-            R.A3[t][e] = (short)N.w3b[i * 64 + 16 * t + 4 * kb + e];
+            R.A3[t][e] = (short)N.w3b[w3_slot(i, 16 * t + 4 * kb + e)];
         }
         for (int s = 0; s < 4; ++s)
-            for (int e = 0; e < 4; ++e) R.A2[t][s][e] = (short)N.w2b[(16 * t + i) * 64 + 16 * s + 4 * kb + e];
+            for (int e = 0; e < 4; ++e) R.A2[t][s][e] = (short)N.w2b[w2_slot(16 * t + i, 16 * s + 4 * kb + e)];
     }
     for (int e = 0; e < 4; ++e) {
         const int o = 4 * kb + e;
@@ -155,29 +211,74 @@ __device__ __forceinline__ void axis_tiles(const LcNet& a, int axis, int& first,
     end = axis == 0 ? a.ntiles_x : a.ntiles;
 }
 
+// Channel kb's feature scales and their FP64 reciprocals (lane group kb;
+// lane group 3 carries no channel).
+struct FeatScale {
+    double s[4], r[4], mu;
+};
+__device__ __forceinline__ FeatScale feat_scale(const LcNet& a, int kb) {
+    FeatScale F;
+    const int c = kb < 3 ? kb : 0;
+    F.s[0] = a.nm.sl[c];
+    F.s[1] = a.nm.sd1[c];
+    F.s[2] = a.nm.sd2[c];
+    F.s[3] = a.nm.sd3[c];
+    for (int k = 0; k < 4; ++k) F.r[k] = __ddiv_rn(1.0, F.s[k]);
+    F.mu = kb == 0 ? (double)a.nm.mu_h : 0.0;
+    return F;
+}
+// v / s from the reciprocal r = 1/s and one residual correction (the
+// quotient rounded to nearest apart from rare last-bit cases, invisible after
+// the rounding to FP32 and BF16).
+__device__ __forceinline__ double qdiv(double v, double s, double r) {
+    const double q = __dmul_rn(v, r);
+    const double e = __builtin_fma(-q, s, v);
+    return __builtin_fma(e, r, q);
+}
+
+// A tile whose every face has its four stencil cells inside the grid (no
+// wall mirror): x faces first .. first + 63 need first >= 2 and
+// first + 63 <= nx - 2, a y face row k needs 2 <= k <= ny - 2.
+__device__ __forceinline__ bool tile_interior(const LcNet& a, const FaceTile& ft) {
+    return ft.axis == 0 ? (ft.first >= 2 && ft.first + 63 <= a.nx - 2) : (ft.line >= 2 && ft.line <= a.ny - 2);
+}
+
 // Inputs of 16 faces (group g of the tile) as the B operand: lane n + 16 kb
 // holds the four features of channel kb (none for kb = 3).  The features are
 // formed in FP64 without contraction (the higher differences cancel; FP32
 // would round them coarsely) and rounded FP64 -> FP32 -> BF16.
 __device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
-                                           int pos, int lane) {
+                                           int pos, int lane, bool interior, const FeatScale& F, float& hl,
+                                           float& hr) {
     const int kb = lane >> 4;
     bf16x4 x = {0, 0, 0, 0};
+    hl = hr = 0.0f;
     if (kb < 3) {
-        const double v0 = stencil(a, q, ft, pos, kb, 0);
-        const double v1 = stencil(a, q, ft, pos, kb, 1);
-        const double v2 = stencil(a, q, ft, pos, kb, 2);
-        const double v3 = stencil(a, q, ft, pos, kb, 3);
-        const double mu = kb == 0 ? (double)a.nm.mu_h : 0.0;
-        const double jump = __dsub_rn(v2, v1);
-        const double mid = __dadd_rn(v1, v2);
-        const double lvl = __dsub_rn(__dmul_rn(mid, 0.5), mu);
-        const double curv = __dsub_rn(__dadd_rn(v0, v3), mid);
-        const double third = __dsub_rn(__dsub_rn(v3, v0), __dmul_rn(3.0, jump));
-        x[0] = to_bf16((float)__ddiv_rn(lvl, (double)a.nm.sl[kb]));
-        x[1] = to_bf16((float)__ddiv_rn(jump, (double)a.nm.sd1[kb]));
-        x[2] = to_bf16((float)__ddiv_rn(curv, (double)a.nm.sd2[kb]));
-        x[3] = to_bf16((float)__ddiv_rn(third, (double)a.nm.sd3[kb]));
+        double v[4];
+        if (interior) {
+            const int f = frame_field(ft.axis, kb);
+            const float* p = q + (size_t)f * a.ncell;
+            if (ft.axis == 0) {
+                p += (size_t)ft.line * a.nx + pos - 2;
+                for (int k = 0; k < 4; ++k) v[k] = p[k];
+            } else {
+                p += (size_t)(ft.line - 2) * a.nx + pos;
+                for (int k = 0; k < 4; ++k) v[k] = p[(size_t)k * a.nx];
+            }
+        } else {
+            for (int k = 0; k < 4; ++k) v[k] = stencil(a, q, ft, pos, kb, k);
+        }
+        hl = (float)v[1];  // lane group 0: the depths on either side of the face
+        hr = (float)v[2];
+        const double jump = __dsub_rn(v[2], v[1]);
+        const double mid = __dadd_rn(v[1], v[2]);
+        const double lvl = __dsub_rn(__dmul_rn(mid, 0.5), F.mu);
+        const double curv = __dsub_rn(__dadd_rn(v[0], v[3]), mid);
+        const double third = __dsub_rn(__dsub_rn(v[3], v[0]), __dmul_rn(3.0, jump));
+        x[0] = to_bf16((float)qdiv(lvl, F.s[0], F.r[0]));
+        x[1] = to_bf16((float)qdiv(jump, F.s[1], F.r[1]));
+        x[2] = to_bf16((float)qdiv(curv, F.s[2], F.r[2]));
+        x[3] = to_bf16((float)qdiv(third, F.s[3], F.r[3]));
     }
     return x;
 }
@@ -227,6 +328,8 @@ __device__ __forceinline__ const float* resolve_state(const LcNet& a, bool& skip
 
 // Forward pass over every interior face: corrections dF (3, ny, nx+1) and
 // dG (3, ny+1, nx) in state component order; wall faces written as zero.
+// Per 16 faces: 4 products of 16x16x16 (layer 1, K = 12 features padded to
+// 16) and 8 + 2 of 16x16x32 (layers 2 and 3, K = 64 in two blocks).
 __global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
     bool skip;
     const float* __restrict__ q = resolve_state(a, skip);
@@ -234,8 +337,26 @@ __global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
     const int lane = threadIdx.x & 63;
     const int n = lane & 15, kb = lane >> 4;
     const int axis = blockIdx.y;
-    NetRegs R;
-    load_net(net_of(a, axis), lane, R);
+    const NetPtr N = net_of(a, axis);
+    bf16x4 A1[4];
+    bf16x8 A2[4][2], A3[2];
+    f32x4 B1[4], B2[4], B3;
+    for (int t = 0; t < 4; ++t) {
+        A1[t] = *reinterpret_cast<const bf16x4*>(N.w1b + (t * 64 + lane) * 4);
+        for (int s = 0; s < 2; ++s) A2[t][s] = *reinterpret_cast<const bf16x8*>(N.w2b + ((t * 2 + s) * 64 + lane) * 8);
+        for (int e = 0; e < 4; ++e) {
+            B1[t][e] = N.theta[LC_OFF_B1 + 16 * t + 4 * kb + e];
+            B2[t][e] = N.theta[LC_OFF_B2 + 16 * t + 4 * kb + e];
+        }
+    }
+    for (int s = 0; s < 2; ++s) A3[s] = *reinterpret_cast<const bf16x8*>(N.w3b + (s * 64 + lane) * 8);
+    for (int e = 0; e < 4; ++e) {
+        const int o = 4 * kb + e;
+        B3[e] = o < 3 ? N.theta[LC_OFF_B3 + o] : 0.0f;
+    }
+    const FeatScale F = feat_scale(a, kb);
+    const float so[3] = {a.nm.s_out[0], a.nm.s_out[1], a.nm.s_out[2]};
+    const float bound[3] = {fmul(a.kappa, so[0]), fmul(a.kappa, so[1]), fmul(a.kappa, so[2])};
     const int wave = blockIdx.x * WAVES + (threadIdx.x >> 6);
     const int nwaves = gridDim.x * WAVES;
     const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
@@ -243,20 +364,29 @@ __global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
     axis_tiles(a, axis, t0, t1);
     for (int t = t0 + wave; t < t1; t += nwaves) {
         const FaceTile ft = tile_of(a, t);
+        const bool interior = tile_interior(a, ft);
+#pragma unroll 2
         for (int g = 0; g < 4; ++g) {
             bool valid;
             const int pos = face_pos(a, ft, g, n, valid);
-            const bf16x4 x = features(a, q, ft, pos, lane);
-            Acts A;
-            net_forward(R, x, A);
+            float hl, hr;
+            const bf16x4 x = features(a, q, ft, pos, lane, interior, F, hl, hr);
+            bf16x4 h1[4], h2[4];
+            for (int u = 0; u < 4; ++u) h1[u] = pack4(relu4(mma(A1[u], x, B1[u])));
+            const bf16x8 k0 = join(h1[0], h1[1]), k1 = join(h1[2], h1[3]);
+            for (int u = 0; u < 4; ++u) h2[u] = pack4(relu4(mma32(A2[u][1], k1, mma32(A2[u][0], k0, B2[u]))));
+            const f32x4 y = mma32(A3[1], join(h2[2], h2[3]), mma32(A3[0], join(h2[0], h2[1]), B3));
             if (kb == 0 && valid) {
+                float v[3];
+                for (int c = 0; c < 3; ++c) v[c] = so[c] * y[c];
+                const bool drop = a.mask && !indicator_ok(hl, hr, a.tau, v, bound);
                 for (int c = 0; c < 3; ++c) {
-                    const float v = a.nm.s_out[c] * A.y[c];
                     const int f = frame_field(ft.axis, c);
+                    const float w = drop ? 0.0f : v[c];
                     if (ft.axis == 0)
-                        a.dF[f * fx + (size_t)ft.line * (a.nx + 1) + pos] = v;
+                        a.dF[f * fx + (size_t)ft.line * (a.nx + 1) + pos] = w;
                     else
-                        a.dG[f * fy + (size_t)ft.line * a.nx + pos] = v;
+                        a.dG[f * fy + (size_t)ft.line * a.nx + pos] = w;
                 }
             }
         }
@@ -324,10 +454,10 @@ __global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
     for (int t = 0; t < 4; ++t) {
         for (int e = 0; e < 4; ++e) {
             const int o = 4 * kb + e;
-            T3[t][e] = o < 3 ? (short)N.w3b[o * 64 + 16 * t + n] : (short)0;
+            T3[t][e] = o < 3 ? (short)N.w3b[w3_slot(o, 16 * t + n)] : (short)0;
         }
         for (int s = 0; s < 4; ++s)
-            for (int e = 0; e < 4; ++e) T2[t][s][e] = (short)N.w2b[(16 * s + 4 * kb + e) * 64 + 16 * t + n];
+            for (int e = 0; e < 4; ++e) T2[t][s][e] = (short)N.w2b[w2_slot(16 * s + 4 * kb + e, 16 * t + n)];
     }
     const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
     f32x4 acc1[4], acc2[4][4], acc3[4], sb1[4], sb2[4];
@@ -343,13 +473,16 @@ __global__ __launch_bounds__(256) void k_lc_backward(LcNet a) {
     const int nwaves = gridDim.x * WAVES;
     int t0, t1;
     axis_tiles(a, axis, t0, t1);
+    const FeatScale F = feat_scale(a, kb);
     for (int t = t0 + wave; t < t1; t += nwaves) {
         const FaceTile ft = tile_of(a, t);
+        const bool interior = tile_interior(a, ft);
         const float nu = ft.axis == 0 ? a.nux : a.nuy;
         for (int grp = 0; grp < 4; ++grp) {
             bool valid;
             const int pos = face_pos(a, ft, grp, n, valid);
-            const bf16x4 x = features(a, q, ft, pos, lane);
+            float hl, hr;
+            const bf16x4 x = features(a, q, ft, pos, lane, interior, F, hl, hr);
             Acts A;
             net_forward(R, x, A);
             // output gradient (lanes kb = 0 hold the three channels of face n)
@@ -477,39 +610,56 @@ __global__ __launch_bounds__(256) void k_lc_cellgrad(LcCell a) {
 
 // Sum of the per-wavefront partial gradients (fixed order; nparts
 // wavefronts per direction) into grad, and of the loss partials into
-// loss[0..3] (the first block's spare threads).
-__global__ __launch_bounds__(256) void k_lc_reduce(const float* __restrict__ partial, int nparts, float* grad,
-                                                   const double* __restrict__ loss_part, int nloss, double inv3n,
-                                                   double* loss) {
-    __shared__ float red[4][64];
-    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+// loss[0..3] (the first block's first four wavefronts).  A block sums 64 parameters:
+// its 16 wavefronts take every 16th partial each, eight independent running
+// sums per lane (so eight loads are in flight), combined in a fixed order.
+constexpr int RED_PARTS = 16;
+__global__ __launch_bounds__(64 * RED_PARTS) void k_lc_reduce(const float* __restrict__ partial, int nparts,
+                                                              float* grad, const double* __restrict__ loss_part,
+                                                              int nloss, double inv3n, double* loss) {
+    __shared__ float red[RED_PARTS][64];
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 64 + lane;
     const int part = threadIdx.x >> 6;
     float s = 0.0f;
     if (p < LC_NPARAM) {
         const int axis = p / LC_NET, local = p - axis * LC_NET;
         const float* base = partial + (size_t)axis * nparts * LC_NET + local;
-        for (int w = part; w < nparts; w += 4) s += base[(size_t)w * LC_NET];
+        float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int w = part;
+        for (; w + 7 * RED_PARTS < nparts; w += 8 * RED_PARTS)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[k] += base[(size_t)(w + k * RED_PARTS) * LC_NET];
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if (w + k * RED_PARTS < nparts) acc[k] += base[(size_t)(w + k * RED_PARTS) * LC_NET];
+        s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     }
-    red[part][threadIdx.x & 63] = s;
+    red[part][lane] = s;
     __syncthreads();
-    if (part == 0 && p < LC_NPARAM) grad[p] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                               red[3][threadIdx.x];
-    if (blockIdx.x == 0 && threadIdx.x < 4 && loss) {
+    if (part == 0 && p < LC_NPARAM) {
+        float t = 0.0f;
+        for (int k = 0; k < RED_PARTS; ++k) t += red[k][lane];
+        grad[p] = t;
+    }
+    if (blockIdx.x == 0 && part < 4 && loss) {  // wavefront `part` sums loss component `part`
         double v = 0.0;
-        for (int b = 0; b < nloss; ++b) v += loss_part[b * 4 + threadIdx.x];
-        loss[threadIdx.x] = threadIdx.x == 0 ? v * inv3n : v;
+        for (int b = lane; b < nloss; b += 64) v += loss_part[b * 4 + part];
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if (lane == 0) loss[part] = part == 0 ? v * inv3n : v;
     }
 }
 
 __device__ __forceinline__ void emit_bf16(LcParams a, int p, float v) {
     const int axis = p / LC_NET, r = p - axis * LC_NET;
     if (r < LC_OFF_B1) {
-        a.w1b[axis * LC_W1B + (r / 12) * 16 + r % 12] = (unsigned short)to_bf16(v);
+        a.w1b[axis * LC_W1B + w1_slot(r / 12, r % 12)] = (unsigned short)to_bf16(v);
     } else if (r >= LC_OFF_W2 && r < LC_OFF_B2) {
-        a.w2b[axis * LC_W2B + r - LC_OFF_W2] = (unsigned short)to_bf16(v);
+        const int k = r - LC_OFF_W2;
+        a.w2b[axis * LC_W2B + w2_slot(k / 64, k % 64)] = (unsigned short)to_bf16(v);
     } else if (r >= LC_OFF_W3 && r < LC_OFF_B3) {
-        const int o = (r - LC_OFF_W3) / 64, k = (r - LC_OFF_W3) % 64;
-        a.w3b[axis * LC_W3B + o * 64 + k] = (unsigned short)to_bf16(v);
+        const int k = r - LC_OFF_W3;
+        a.w3b[axis * LC_W3B + w3_slot(k / 64, k % 64)] = (unsigned short)to_bf16(v);
     }
 }
 
@@ -548,9 +698,6 @@ __global__ void k_lc_adam(LcParams a, const float* __restrict__ grad, float lr, 
 // Fallback and application (FP32, no contraction: the decisions must not
 // depend on how the compiler fuses the products).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float fmul(float x, float y) { return __fmul_rn(x, y); }
-__device__ __forceinline__ float fsub(float x, float y) { return __fsub_rn(x, y); }
-__device__ __forceinline__ float fadd(float x, float y) { return __fadd_rn(x, y); }
 
 struct ApplyState {
     const float* qn;
@@ -575,10 +722,8 @@ __device__ __forceinline__ bool resolve_apply(const LcApply& a, ApplyState& S) {
 // bound[c]: kappa times the output scale of state component c on this face's axis.
 __device__ __forceinline__ bool face_ok(const LcApply& a, float hl, float hr, const float* __restrict__ d,
                                         size_t stride, const float* bound) {
-    const float lo = hl < hr ? hl : hr;
-    bool ok = fabsf(fsub(hr, hl)) <= fmul(a.tau, lo);
-    for (int c = 0; c < 3; ++c) ok = ok && (fabsf(d[c * stride]) <= bound[c]);
-    return ok;
+    const float dd[3] = {d[0], d[stride], d[2 * stride]};
+    return indicator_ok(hl, hr, a.tau, dd, bound);
 }
 
 struct FaceKeep {
@@ -588,11 +733,18 @@ struct FaceKeep {
 __device__ __forceinline__ FaceKeep keep_of(const LcApply& a, const float* __restrict__ h, int i, int j) {
     const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
     const int nx = a.nx, ny = a.ny;
+    FaceKeep k;
+    if (a.premasked) {  // the forward pass zeroed the faces that fail the test
+        k.l = i > 0;
+        k.r = i < nx - 1;
+        k.b = j > 0;
+        k.t = j < ny - 1;
+        return k;
+    }
     const float hc = h[j * nx + i];
     // x faces: components (h, hu, hv) are frame (h, m_n, m_t); y faces (h, m_t, m_n)
     const float bx[3] = {fmul(a.kappa, a.s_out[0]), fmul(a.kappa, a.s_out[1]), fmul(a.kappa, a.s_out[2])};
     const float by[3] = {bx[0], bx[2], bx[1]};
-    FaceKeep k;
     k.l = i > 0 && face_ok(a, h[j * nx + i - 1], hc, a.dF + (size_t)j * (nx + 1) + i, fx, bx);
     k.r = i < nx - 1 && face_ok(a, hc, h[j * nx + i + 1], a.dF + (size_t)j * (nx + 1) + i + 1, fx, bx);
     k.b = j > 0 && face_ok(a, h[(j - 1) * nx + i], hc, a.dG + (size_t)j * nx + i, fy, by);
@@ -619,8 +771,9 @@ __device__ __forceinline__ float corrected(const LcApply& a, float plain, int f,
 __global__ __launch_bounds__(256) void k_lc_apply1(LcApply a) {
     ApplyState S;
     if (!resolve_apply(a, S)) return;
-    for (int c = blockIdx.x * 256 + threadIdx.x; c < a.ncell; c += gridDim.x * 256) {
-        const int j = c / a.nx, i = c - j * a.nx;
+    for (int j = blockIdx.y; j < a.ny; j += gridDim.y)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < a.nx; i += gridDim.x * 256) {
+        const int c = j * a.nx + i;
         const FaceKeep k = keep_of(a, S.qn, i, j);
         const float p = S.plain[c];
         const float* F = a.dF + (size_t)j * (a.nx + 1);
@@ -640,8 +793,9 @@ __global__ __launch_bounds__(256) void k_lc_apply2(LcApply a) {
     ApplyState S;
     if (!resolve_apply(a, S)) return;
     const int nx = a.nx;
-    for (int c = blockIdx.x * 256 + threadIdx.x; c < a.ncell; c += gridDim.x * 256) {
-        const int j = c / nx, i = c - j * nx;
+    for (int j = blockIdx.y; j < a.ny; j += gridDim.y)
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < nx; i += gridDim.x * 256) {
+        const int c = j * nx + i;
         FaceKeep k = keep_of(a, S.qn, i, j);
         const bool me = a.bad[c] != 0;
         k.l = k.l && !me && !a.bad[c - 1 + (i == 0)];
@@ -769,8 +923,8 @@ hipError_t launch_lc_cellgrad(const LcCell& a, hipStream_t s) {
 
 hipError_t launch_lc_reduce(const float* partial, int nparts, float* grad, const double* loss_part, int nloss,
                             double inv3n, double* loss, hipStream_t s) {
-    hipLaunchKernelGGL(k_lc_reduce, dim3((LC_NPARAM + 63) / 64), dim3(256), 0, s, partial, nparts, grad, loss_part,
-                       nloss, inv3n, loss);
+    hipLaunchKernelGGL(k_lc_reduce, dim3((LC_NPARAM + 63) / 64), dim3(64 * RED_PARTS), 0, s, partial, nparts, grad,
+                       loss_part, nloss, inv3n, loss);
     return hipGetLastError();
 }
 
@@ -790,11 +944,12 @@ hipError_t launch_lc_adam(const LcParams& a, const float* grad, float lr, float 
 }
 
 hipError_t launch_lc_apply(const LcApply& a, hipStream_t s) {
-    const int b = blocks_for(a.ncell);
-    hipLaunchKernelGGL(k_lc_apply1, dim3(b), dim3(256), 0, s, a);
+    // one row of cells per block row (up to 256 columns per block, rows strided beyond 65535)
+    const dim3 b((unsigned)((a.nx + 255) / 256), (unsigned)(a.ny < 65535 ? a.ny : 65535));
+    hipLaunchKernelGGL(k_lc_apply1, b, dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lc_apply2, dim3(b), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_lc_apply2, b, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1785,6 +1785,12 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
     ap.ctrl = h->ctrl;
     ap.qsel = 0;
     ap.rsel = result_offset_of(h);  // the plain result, corrected in place
+    // the forward pass applies the indicator test itself (zero on the faces
+    // that fail it), so the application reads no depths for it
+    a.mask = 1;
+    a.tau = ap.tau;
+    a.kappa = ap.kappa;
+    ap.premasked = 1;
     // One learned step: the plain fixed-dt trial, then the corrections from
     // Q^n applied to its result before the next trial's first sweep accepts it.
     auto enqueue_step = [&](hipStream_t s) -> claw_status {
