@@ -440,6 +440,19 @@ claw_status claw_lc_advance(claw_solver* h, const claw_lc_desc* d, const void* p
 claw_status claw_stream_bench(void* a, void* b, size_t bytes, int32_t reps, void* stream,
                               double* gbps);
 
+/* Range checks of a debug build (libclaw_debug.so, compiled with CLAW_DEBUG),
+ * for callers hunting an indexing error: every buffer load and store of the
+ * kernels checks its byte range against the field it addresses, and the
+ * boundary index map checks the cell it resolves (the boundary-condition
+ * stage of section 4.1).
+ * A failed check is counted on the device and the kernel carries on as a
+ * release build would.  Returns in *count the number of failed checks since
+ * the last call (over every kernel file) and in *first_line the source line
+ * of the first one (0 if none), then clears the counts; synchronises the
+ * current device.  Either pointer may be NULL.  A release build returns
+ * CLAW_E_UNSUPPORTED. */
+claw_status claw_debug_take(uint64_t* count, uint32_t* first_line);
+
 /* Defined by: section 4.1 (the CFL revert and failure outcomes of a step). */
 const char* claw_status_string(claw_status s);
 /* Defined by: section 4.1 (why the last call failed). */

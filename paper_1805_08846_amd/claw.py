@@ -40,7 +40,7 @@ EXPORTED = ["claw_desc_init", "claw_plugin_info", "claw_workspace_bytes", "claw_
             "claw_batch_set_tiles", "claw_batch_advance", "claw_batch_destroy",
             "claw_lc_sizes", "claw_lc_init", "claw_lc_forward", "claw_lc_loss_grad", "claw_lc_adam",
             "claw_lc_apply", "claw_lc_coarsen", "claw_lc_advance", "claw_lc_perturb", "claw_lc_scales",
-            "claw_stream_bench", "claw_status_string", "claw_last_error"]
+            "claw_stream_bench", "claw_debug_take", "claw_status_string", "claw_last_error"]
 
 CLAW_LC_NET = 5187
 CLAW_LC_NPARAM = 2 * CLAW_LC_NET  # x-face network, then y-face network
@@ -137,6 +137,7 @@ def _load():
         "claw_lc_advance": (i32, [vp, P(claw_lc_desc), vp, i64, dbl, dbl, dbl, vp]),
         "claw_lc_perturb": (i32, [i64, i64, vp, vp, P(ctypes.c_float), ctypes.c_uint32, ctypes.c_uint32, vp]),
         "claw_lc_scales": (i32, [P(dbl), i64, dbl, i32, P(ctypes.c_float), P(dbl)]),
+        "claw_debug_take": (i32, [P(ctypes.c_uint64), P(ctypes.c_uint32)]),
         "claw_status_string": (ctypes.c_char_p, [i32]),
         "claw_last_error": (ctypes.c_char_p, []),
     }
@@ -152,6 +153,14 @@ _lib = _load()
 
 def library_path():
     return _LIB_PATH
+
+
+def claw_debug_take():
+    """(failed range checks since the last call, source line of the first) of
+    a debug build; raises ClawError(CLAW_E_UNSUPPORTED) on a release build."""
+    n, line = ctypes.c_uint64(0), ctypes.c_uint32(0)
+    _check(_lib.claw_debug_take(ctypes.byref(n), ctypes.byref(line)), "claw_debug_take")
+    return int(n.value), int(line.value)
 
 
 def _check(status, where):

@@ -25,6 +25,47 @@
 
 namespace claw {
 
+// Debug builds (compiled with CLAW_DEBUG, as libclaw_debug.so): every buffer
+// load and store checks its byte range against the extent of the field it
+// addresses, and the boundary index map checks the cell it resolves.  A
+// failed check adds one to a device counter of its translation unit and
+// records the source line of the first failure; the kernel then carries on as
+// a release build would (a buffer access out of range reads zero and drops the
+// store), so a wrong index shows up as a count instead of a silent zero.
+// claw_debug_take reads and clears the counters.  Release builds compile the
+// checks away.
+#ifdef CLAW_DEBUG
+typedef unsigned (*DebugTake)(unsigned* first_line);
+void debug_register(DebugTake take);  // collects every translation unit's reader (runtime.hip)
+namespace {
+__device__ unsigned dbg_word[2];  // failed checks, source line of the first
+__device__ __noinline__ void dbg_fail(unsigned line) {
+    atomicAdd(&dbg_word[0], 1u);
+    atomicCAS(&dbg_word[1], 0u, line);
+}
+unsigned dbg_take(unsigned* first_line) {
+    unsigned w[2] = {0u, 0u};
+    if (hipMemcpyFromSymbol(w, HIP_SYMBOL(dbg_word), sizeof w, 0, hipMemcpyDeviceToHost) != hipSuccess) return 0u;
+    const unsigned z[2] = {0u, 0u};
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(dbg_word), z, sizeof z, 0, hipMemcpyHostToDevice);
+    if (first_line) *first_line = w[1];
+    return w[0];
+}
+struct DbgRegistrar {
+    DbgRegistrar() { debug_register(dbg_take); }
+};
+DbgRegistrar dbg_registrar;
+}  // namespace
+#define CLAW_CHECK(cond)                              \
+    do {                                              \
+        if (!(cond)) ::claw::dbg_fail(__LINE__);      \
+    } while (0)
+#else
+#define CLAW_CHECK(cond) \
+    do {                 \
+    } while (0)
+#endif
+
 enum { BC_EXTRAP = 0, BC_WALL = 1, BC_PERIODIC = 2 };
 enum { LIM_MC = 0, LIM_NONE = 1, LIM_FIRST = 2, LIM_MINMOD = 3, LIM_SUPERBEE = 4, LIM_VANLEER = 5 };
 // system kinds as compiled: constant-coefficient acoustics, acoustics with
@@ -157,23 +198,43 @@ __device__ __forceinline__ double wave_uniform(double v) {
 // runtime keeps every field under 4 GiB).  A load or store then takes a
 // per-lane byte offset and a scalar byte offset and costs no vector address
 // arithmetic; the resource lives in scalar registers.
+#ifdef CLAW_DEBUG
+struct Rsrc {
+    __amdgpu_buffer_rsrc_t r;
+    unsigned bytes;
+};
+__device__ __forceinline__ Rsrc field_rsrc(const void* base, unsigned bytes) {
+    return Rsrc{__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000), bytes};
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t hw(Rsrc r) { return r.r; }
+__device__ __forceinline__ void check_range(Rsrc r, unsigned voff, unsigned soff, unsigned size) {
+    CLAW_CHECK((unsigned long long)voff + soff + size <= r.bytes);
+}
+#else
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 __device__ __forceinline__ Rsrc field_rsrc(const void* base, unsigned bytes) {
     // word 3: 32-bit data format, the value gfx9-family raw buffer access takes
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
+__device__ __forceinline__ Rsrc hw(Rsrc r) { return r; }
+__device__ __forceinline__ void check_range(Rsrc, unsigned, unsigned, unsigned) {}
+#endif
 __device__ __forceinline__ float buf_load(Rsrc r, unsigned voff, unsigned soff, float) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    check_range(r, voff, soff, 4);
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(hw(r), (int)voff, (int)soff, 0));
 }
 __device__ __forceinline__ double buf_load(Rsrc r, unsigned voff, unsigned soff, double) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    check_range(r, voff, soff, 8);
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(hw(r), (int)voff, (int)soff, 0));
 }
 __device__ __forceinline__ void buf_store(Rsrc r, unsigned voff, unsigned soff, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)voff, (int)soff, 0);
+    check_range(r, voff, soff, 4);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), hw(r), (int)voff, (int)soff, 0);
 }
 __device__ __forceinline__ void buf_store(Rsrc r, unsigned voff, unsigned soff, double v) {
     typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+    check_range(r, voff, soff, 8);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), hw(r), (int)voff, (int)soff, 0);
 }
 
 // 16-byte vector loads and stores through a field resource (a row lane's
@@ -182,12 +243,14 @@ typedef unsigned U4 __attribute__((ext_vector_type(4)));
 template <typename V>
 __device__ __forceinline__ V buf_load16(Rsrc r, unsigned voff) {
     static_assert(sizeof(V) == 16, "16-byte vectors only");
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, 0));
+    check_range(r, voff, 0, 16);
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(hw(r), (int)voff, 0, 0));
 }
 template <typename V>
 __device__ __forceinline__ void buf_store16(Rsrc r, unsigned voff, V v) {
     static_assert(sizeof(V) == 16, "16-byte vectors only");
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), r, (int)voff, 0, 0);
+    check_range(r, voff, 0, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U4, v), hw(r), (int)voff, 0, 0);
 }
 
 // Rotation buffer i (0..2) chosen by selects rather than by indexing the
@@ -243,7 +306,7 @@ __device__ __forceinline__ double rsign1(double a) { return __builtin_copysign(1
 // Source index of cell i along a line of m cells under the boundary rules;
 // only -2 <= i <= m + 1 matter, other indices are clamped into that range
 // first.  flip = the normal component changes sign (wall).
-__device__ __forceinline__ int ghost_idx(int i, int m, int bc_lo, int bc_hi, bool& flip) {
+__device__ __forceinline__ int ghost_idx_of(int i, int m, int bc_lo, int bc_hi, bool& flip) {
     i = i < -2 ? -2 : (i > m + 1 ? m + 1 : i);
     flip = false;
     if (i < 0) {
@@ -271,6 +334,11 @@ __device__ __forceinline__ int ghost_idx(int i, int m, int bc_lo, int bc_hi, boo
         return m - 1;
     }
     return i;
+}
+__device__ __forceinline__ int ghost_idx(int i, int m, int bc_lo, int bc_hi, bool& flip) {
+    const int r = ghost_idx_of(i, m, bc_lo, bc_hi, flip);
+    CLAW_CHECK(r >= 0 && r < m);
+    return r;
 }
 
 // ---------------------------------------------------------------------------

@@ -72,8 +72,10 @@ hipError_t launch_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, doubl
 
 // Learned coarse correction (learned.hip).  Two 12-64-64-3 networks, one
 // per sweep direction (x faces, then y faces), each flat: W1 (64, 12), b1,
-// W2 (64, 64), b2, W3 (3, 64), b3.  BF16 copies per network: W1 padded
-// [64][16], W2 [64][64], W3 padded [16][64].
+// W2 (64, 64), b2, W3 (3, 64), b3.  BF16 copies per network, each in the
+// order its matrix-core operand takes (learned.hip: w1_slot, w2_slot,
+// w3_slot): W1 with its 12 features padded to 16, W2, W3 with its 3 outputs
+// padded to 16 rows.
 enum {
     LC_NET = 5187,
     LC_NPARAM = 2 * LC_NET,

@@ -123,6 +123,7 @@ void k_step2d(FusedArgs<R> F) {
             for (int c = 0; c < CPL; ++c) {
                 bool flip;
                 const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
+                CLAW_CHECK(sidx < (unsigned)a.ncell);
 #pragma unroll
                 for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * (unsigned)a.ncell + sidx];
                 if (flip) q[c][nrm] = -q[c][nrm];
@@ -259,6 +260,7 @@ void k_step2d(FusedArgs<R> F) {
                 apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nuy, NRM, TNG);
                 if (xin) {
                     const unsigned off = (unsigned)(yy * nx + x);
+                    CLAW_CHECK(off < (unsigned)a.ncell);
 #pragma unroll
                     for (int e = 0; e < MEQN; ++e) dst[(size_t)e * (unsigned)a.ncell + off] = w0.q[e];
                 }

@@ -94,11 +94,15 @@ __device__ __forceinline__ bf16x4 pack4(f32x4 v) {
     r[3] = to_bf16(v[3]);
     return r;
 }
+// ReLU as a signed integer max with 0 on the FP32 bit patterns (one
+// v_max_i32 per value, no NaN canonicalisation): a value with its sign bit
+// set, -0 included, is a negative integer and becomes +0, the same bits as
+// v > 0 ? v : 0 for every non-NaN v.
 __device__ __forceinline__ f32x4 relu4(f32x4 v) {
-    f32x4 r;
-    for (int e = 0; e < 4; ++e) r[e] = v[e] > 0.0f ? v[e] : 0.0f;
-    return r;
+    typedef int i32x4 __attribute__((ext_vector_type(4)));
+    return __builtin_bit_cast(f32x4, __builtin_elementwise_max(__builtin_bit_cast(i32x4, v), i32x4{0, 0, 0, 0}));
 }
+__device__ __forceinline__ bf16x4 relu_pack4(f32x4 v) { return pack4(relu4(v)); }
 
 constexpr int WAVES = 4;  // wavefronts per workgroup
 
@@ -162,6 +166,7 @@ __device__ __forceinline__ float stencil(const LcNet& a, const float* __restrict
         if (c == 1) sign = -1.0f;
     }
     const int cell = ft.axis == 0 ? ft.line * a.nx + idx : idx * a.nx + pos;
+    CLAW_CHECK(idx >= 0 && idx < n && cell >= 0 && cell < a.ncell);
     return sign * q[(size_t)f * a.ncell + cell];
 }
 
@@ -238,43 +243,45 @@ __device__ __forceinline__ double qdiv(double v, double s, double r) {
 
 // A tile whose every face has its four stencil cells inside the grid (no
 // wall mirror): x faces first .. first + 63 need first >= 2 and
-// first + 63 <= nx - 2, a y face row k needs 2 <= k <= ny - 2.
+// first + 63 <= nx - 2, a y face row k needs 2 <= k <= ny - 2 (its columns
+// past nx - 1, in the row's last tile, are clamped by face_pos).
 __device__ __forceinline__ bool tile_interior(const LcNet& a, const FaceTile& ft) {
     return ft.axis == 0 ? (ft.first >= 2 && ft.first + 63 <= a.nx - 2) : (ft.line >= 2 && ft.line <= a.ny - 2);
 }
 
-// Inputs of 16 faces (group g of the tile) as the B operand: lane n + 16 kb
-// holds the four features of channel kb (none for kb = 3).  The features are
-// formed in FP64 without contraction (the higher differences cancel; FP32
-// would round them coarsely) and rounded FP64 -> FP32 -> BF16.
-__device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
-                                           int pos, int lane, bool interior, const FeatScale& F, float& hl,
-                                           float& hr) {
-    const int kb = lane >> 4;
-    bf16x4 x = {0, 0, 0, 0};
-    hl = hr = 0.0f;
-    if (kb < 3) {
-        double v[4];
-        if (interior) {
-            const int f = frame_field(ft.axis, kb);
-            const float* p = q + (size_t)f * a.ncell;
-            if (ft.axis == 0) {
-                p += (size_t)ft.line * a.nx + pos - 2;
-                for (int k = 0; k < 4; ++k) v[k] = p[k];
-            } else {
-                p += (size_t)(ft.line - 2) * a.nx + pos;
-                for (int k = 0; k < 4; ++k) v[k] = p[(size_t)k * a.nx];
-            }
+// Stencil values (cells k-2 .. k+1) of channel kb < 3 around face `pos`.
+__device__ __forceinline__ void stencil_vals(const LcNet& a, const float* __restrict__ q, const FaceTile& ft, int pos,
+                                             int kb, bool interior, float (&v)[4]) {
+    if (interior) {
+        const int f = frame_field(ft.axis, kb);
+        const float* p = q + (size_t)f * a.ncell;
+        if (ft.axis == 0) {
+            CLAW_CHECK(pos >= 2 && pos + 1 < a.nx && ft.line < a.ny);
+            p += (size_t)ft.line * a.nx + pos - 2;
+            for (int k = 0; k < 4; ++k) v[k] = p[k];
         } else {
-            for (int k = 0; k < 4; ++k) v[k] = stencil(a, q, ft, pos, kb, k);
+            CLAW_CHECK(ft.line >= 2 && ft.line + 1 < a.ny && pos < a.nx);
+            p += (size_t)(ft.line - 2) * a.nx + pos;
+            for (int k = 0; k < 4; ++k) v[k] = p[(size_t)k * a.nx];
         }
-        hl = (float)v[1];  // lane group 0: the depths on either side of the face
-        hr = (float)v[2];
-        const double jump = __dsub_rn(v[2], v[1]);
-        const double mid = __dadd_rn(v[1], v[2]);
+    } else {
+        for (int k = 0; k < 4; ++k) v[k] = stencil(a, q, ft, pos, kb, k);
+    }
+}
+
+// The four features of one channel as the B operand elements of lane group
+// kb (zeros for kb = 3).  They are formed in FP64 without contraction (the
+// higher differences cancel; FP32 would round them coarsely) and rounded
+// FP64 -> FP32 -> BF16.
+__device__ __forceinline__ bf16x4 feat_of(const float (&s)[4], int kb, const FeatScale& F) {
+    bf16x4 x = {0, 0, 0, 0};
+    if (kb < 3) {
+        const double v0 = s[0], v1 = s[1], v2 = s[2], v3 = s[3];
+        const double jump = __dsub_rn(v2, v1);
+        const double mid = __dadd_rn(v1, v2);
         const double lvl = __dsub_rn(__dmul_rn(mid, 0.5), F.mu);
-        const double curv = __dsub_rn(__dadd_rn(v[0], v[3]), mid);
-        const double third = __dsub_rn(__dsub_rn(v[3], v[0]), __dmul_rn(3.0, jump));
+        const double curv = __dsub_rn(__dadd_rn(v0, v3), mid);
+        const double third = __dsub_rn(__dsub_rn(v3, v0), __dmul_rn(3.0, jump));
         x[0] = to_bf16((float)qdiv(lvl, F.s[0], F.r[0]));
         x[1] = to_bf16((float)qdiv(jump, F.s[1], F.r[1]));
         x[2] = to_bf16((float)qdiv(curv, F.s[2], F.r[2]));
@@ -283,17 +290,31 @@ __device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restri
     return x;
 }
 
+// Inputs of 16 faces (group g of the tile) as the B operand: lane n + 16 kb
+// holds the four features of channel kb; lane group 0 also returns the
+// depths on either side of its face.
+__device__ __forceinline__ bf16x4 features(const LcNet& a, const float* __restrict__ q, const FaceTile& ft,
+                                           int pos, int lane, bool interior, const FeatScale& F, float& hl,
+                                           float& hr) {
+    const int kb = lane >> 4;
+    float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (kb < 3) stencil_vals(a, q, ft, pos, kb, interior, v);
+    hl = v[1];
+    hr = v[2];
+    return feat_of(v, kb, F);
+}
+
 struct Acts {
     bf16x4 h1[4], h2[4];
     f32x4 y;
 };
 
 __device__ __forceinline__ void net_forward(const NetRegs& R, bf16x4 x, Acts& A) {
-    for (int t = 0; t < 4; ++t) A.h1[t] = pack4(relu4(mma(R.A1[t], x, R.B1[t])));
+    for (int t = 0; t < 4; ++t) A.h1[t] = relu_pack4(mma(R.A1[t], x, R.B1[t]));
     for (int t = 0; t < 4; ++t) {
         f32x4 z = R.B2[t];
         for (int s = 0; s < 4; ++s) z = mma(R.A2[t][s], A.h1[s], z);
-        A.h2[t] = pack4(relu4(z));
+        A.h2[t] = relu_pack4(z);
     }
     f32x4 y = R.B3;
     for (int s = 0; s < 4; ++s) y = mma(R.A3[s], A.h2[s], y);
@@ -362,32 +383,51 @@ __global__ __launch_bounds__(256) void k_lc_forward(LcNet a) {
     const size_t fx = (size_t)a.ny * (a.nx + 1), fy = (size_t)(a.ny + 1) * a.nx;
     int t0, t1;
     axis_tiles(a, axis, t0, t1);
+    // the network on 16 faces and the store of their corrections
+    auto run_group = [&](const FaceTile& ft, int pos, bool valid, bf16x4 x, float hl, float hr) {
+        bf16x4 h1[4], h2[4];
+        for (int u = 0; u < 4; ++u) h1[u] = relu_pack4(mma(A1[u], x, B1[u]));
+        const bf16x8 k0 = join(h1[0], h1[1]), k1 = join(h1[2], h1[3]);
+        for (int u = 0; u < 4; ++u) h2[u] = relu_pack4(mma32(A2[u][1], k1, mma32(A2[u][0], k0, B2[u])));
+        const f32x4 y = mma32(A3[1], join(h2[2], h2[3]), mma32(A3[0], join(h2[0], h2[1]), B3));
+        if (kb == 0 && valid) {
+            float v[3];
+            for (int c = 0; c < 3; ++c) v[c] = so[c] * y[c];
+            const bool drop = a.mask && !indicator_ok(hl, hr, a.tau, v, bound);
+            for (int c = 0; c < 3; ++c) {
+                const int f = frame_field(ft.axis, c);
+                const float w = drop ? 0.0f : v[c];
+                CLAW_CHECK(ft.axis == 0 ? (pos <= a.nx && ft.line < a.ny) : (pos < a.nx && ft.line <= a.ny));
+                if (ft.axis == 0)
+                    a.dF[f * fx + (size_t)ft.line * (a.nx + 1) + pos] = w;
+                else
+                    a.dG[f * fy + (size_t)ft.line * a.nx + pos] = w;
+            }
+        }
+    };
     for (int t = t0 + wave; t < t1; t += nwaves) {
         const FaceTile ft = tile_of(a, t);
-        const bool interior = tile_interior(a, ft);
-#pragma unroll 2
-        for (int g = 0; g < 4; ++g) {
-            bool valid;
-            const int pos = face_pos(a, ft, g, n, valid);
-            float hl, hr;
-            const bf16x4 x = features(a, q, ft, pos, lane, interior, F, hl, hr);
-            bf16x4 h1[4], h2[4];
-            for (int u = 0; u < 4; ++u) h1[u] = pack4(relu4(mma(A1[u], x, B1[u])));
-            const bf16x8 k0 = join(h1[0], h1[1]), k1 = join(h1[2], h1[3]);
-            for (int u = 0; u < 4; ++u) h2[u] = pack4(relu4(mma32(A2[u][1], k1, mma32(A2[u][0], k0, B2[u]))));
-            const f32x4 y = mma32(A3[1], join(h2[2], h2[3]), mma32(A3[0], join(h2[0], h2[1]), B3));
-            if (kb == 0 && valid) {
-                float v[3];
-                for (int c = 0; c < 3; ++c) v[c] = so[c] * y[c];
-                const bool drop = a.mask && !indicator_ok(hl, hr, a.tau, v, bound);
-                for (int c = 0; c < 3; ++c) {
-                    const int f = frame_field(ft.axis, c);
-                    const float w = drop ? 0.0f : v[c];
-                    if (ft.axis == 0)
-                        a.dF[f * fx + (size_t)ft.line * (a.nx + 1) + pos] = w;
-                    else
-                        a.dG[f * fy + (size_t)ft.line * a.nx + pos] = w;
-                }
+        if (tile_interior(a, ft)) {
+            // every load of the tile first (no wall mirror: the stencils lie
+            // inside the grid; faces past the end of a y-face row are clamped
+            // onto its last column and not stored)
+            float sv[4][4];
+            int pos[4];
+            bool valid[4];
+            for (int g = 0; g < 4; ++g) {
+                pos[g] = face_pos(a, ft, g, n, valid[g]);
+                for (int k = 0; k < 4; ++k) sv[g][k] = 0.0f;
+            }
+            if (kb < 3)
+                for (int g = 0; g < 4; ++g) stencil_vals(a, q, ft, pos[g], kb, true, sv[g]);
+            for (int g = 0; g < 4; ++g) run_group(ft, pos[g], valid[g], feat_of(sv[g], kb, F), sv[g][1], sv[g][2]);
+        } else {
+            for (int g = 0; g < 4; ++g) {
+                bool valid;
+                const int pos = face_pos(a, ft, g, n, valid);
+                float hl, hr;
+                const bf16x4 x = features(a, q, ft, pos, lane, false, F, hl, hr);
+                run_group(ft, pos, valid, x, hl, hr);
             }
         }
         // wall faces: x faces 0 and nx of this row; y face rows 0 and ny

@@ -546,6 +546,18 @@ claw_status run_adaptive(claw_solver* h, int64_t nsteps, double dt0, bool graphs
 
 }  // namespace
 
+#ifdef CLAW_DEBUG
+namespace claw {
+namespace {
+DebugTake g_debug_take[16];  // one reader per kernel file, filled during static initialisation
+int g_debug_n = 0;
+}  // namespace
+void debug_register(DebugTake take) {
+    if (g_debug_n < 16) g_debug_take[g_debug_n++] = take;
+}
+}  // namespace claw
+#endif
+
 extern "C" {
 
 claw_status claw_plugin_info(int32_t id, int32_t* meqn, int32_t* mwaves, int32_t* ndim_max,
@@ -927,6 +939,26 @@ claw_status claw_sweep_noalloc(const claw_desc* d, const void* src, void* dst, c
     HIP_TRY(launch_commit(h.ctrl, committed(&h), h.fp32, h.stream));
     if (smax_dev) HIP_TRY(launch_report_smax(h.ctrl, committed(&h), dir, h.fp32, smax_dev, h.stream));
     return CLAW_OK;
+}
+
+claw_status claw_debug_take(uint64_t* count, uint32_t* first_line) {
+#ifdef CLAW_DEBUG
+    if (hipDeviceSynchronize() != hipSuccess) return fail(CLAW_E_HIP, "device synchronisation failed");
+    uint64_t n = 0;
+    uint32_t first = 0;
+    for (int k = 0; k < g_debug_n; ++k) {
+        unsigned line = 0;
+        n += g_debug_take[k](&line);
+        if (!first && line) first = line;
+    }
+    if (count) *count = n;
+    if (first_line) *first_line = first;
+    return CLAW_OK;
+#else
+    if (count) *count = 0;
+    if (first_line) *first_line = 0;
+    return fail(CLAW_E_UNSUPPORTED, "not a debug build: the range checks are in libclaw_debug.so (CLAW_DEBUG)");
+#endif
 }
 
 const char* claw_status_string(claw_status s) {

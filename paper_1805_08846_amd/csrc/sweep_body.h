@@ -238,6 +238,7 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
             for (int c = 0; c < CPL; ++c) {
                 bool flip;
                 const unsigned sidx = base + (unsigned)ghost_idx(xl + c, nx, a.bc_lo, a.bc_hi, flip);
+                CLAW_CHECK(sidx < (unsigned)a.ncell);
 #pragma unroll
                 for (int e = 0; e < MEQN; ++e) q[c][e] = src[(size_t)e * a.ncell + sidx];
                 if (flip) wall_flip<SYS>(q[c], 0);
@@ -333,8 +334,10 @@ __device__ __forceinline__ void row_body(const SweepArgs<R>& a, int bx, int by, 
                     for (int c = 0; c < CPL; ++c) {
                         if (xl + c < nx) {
 #pragma unroll
-                            for (int e = 0; e < MEQN; ++e)
+                            for (int e = 0; e < MEQN; ++e) {
+                                CLAW_CHECK(base + (unsigned)(xl + c) < (unsigned)a.ncell);
                                 dst[(size_t)e * a.ncell + base + (unsigned)(xl + c)] = q[c][e];
+                            }
                         }
                     }
                 }

@@ -37,6 +37,22 @@ def test_library_exports_every_declared_function(claw):
     assert sorted(claw.EXPORTED) == declared
 
 
+def test_debug_library_exports_every_declared_function(claw):
+    # the range-checked build (CLAW_DEBUG) has the same ABI
+    path = os.path.join(ROOT, "paper_1805_08846_amd", "libclaw_debug.so")
+    if not os.path.exists(path):
+        pytest.skip("libclaw_debug.so not built")
+    lib = ctypes.CDLL(path)
+    for name in _declared_functions():
+        assert hasattr(lib, name), f"{name} declared in claw.h but not exported by the debug build"
+
+
+def test_release_build_reports_no_range_checks(claw):
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_debug_take()
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+
+
 @pytest.mark.parametrize("struct", ["claw_desc", "claw_lc_desc"])
 def test_descriptor_layout_matches_header(claw, tmp_path, struct):
     cls = getattr(claw, struct)
