@@ -43,7 +43,14 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 VALU_PEAK_SIMD_CLOCKS = 1024 * 2.4e9  # SIMDs x clock (Hz)
-SWEEP_CLASSES = (("k_sweep_row<", "x_sweep"), ("k_sweep_col<", "y_sweep"), ("k_step2d<", "step2d"))
+SWEEP_CLASSES = (("k_sweep_row<", "x_sweep"), ("k_sweep_col<", "y_sweep"), ("k_sweep_col<", "z_sweep"),
+                 ("k_step2d<", "step2d"))
+
+
+def _col_normal(name):
+    """Normal component (2: y sweep, 3: z sweep) of a k_sweep_col<R, SYS, MEQN, NRM, ...> name."""
+    args = name.split("<", 1)[1].split(">", 1)[0].split(",")
+    return args[3].strip() if len(args) > 3 else None
 
 
 def kernel_source_hash():
@@ -103,8 +110,13 @@ def _median(v):
 def pmc(args):
     c = read_counters(args.csv)
     kernels = sorted({k for k, _ in c})
-    copy = [k for k in kernels if "k_copy<false>" in k]
-    alg = 2 * 3 * args.real_bytes * args.ncell  # one sweep; the fused step carries two
+    # the copy calibration comes from these runs, or from --calib runs (the
+    # same counters for a workload whose command runs no copy kernel)
+    cal = read_counters(args.calib) if args.calib else c
+    copy = [k for k, _ in cal if "k_copy<false>" in k][:1]
+    # one sweep reads and writes every field and reads the coefficient fields;
+    # the fused step carries two sweeps
+    alg = (2 * args.meqn + args.maux) * args.real_bytes * args.ncell
     out = [f"# rocprofv3 counters: {args.title}", ""]
     if args.commands_file:
         with open(args.commands_file) as fh:
@@ -115,13 +127,14 @@ def pmc(args):
         # the benchmark's first copy dispatches (warm-up and repetitions of the
         # achievable-bandwidth run) move 1 GiB each way (2^20 KiB read and written)
         for cn in scale:
-            v = c.get((copy[0], cn), [])[:3]
+            v = cal.get((copy[0], cn), [])[:3]
             if v and statistics.median(v) > 0.25 * 2 ** 20:
                 scale[cn] = 2 ** 20 / statistics.median(v)
+        src = ("runs " + " ".join(os.path.relpath(x, ROOT) for x in args.calib)) if args.calib else "same runs"
         out.append("calibration: plain copy kernel k_copy<false> (claw_stream_bench), 1 GiB read + 1 GiB "
-                   "written per dispatch (the run's first copy dispatches), same runs")
+                   f"written per dispatch (the run's first copy dispatches), {src}")
         for cn in scale:
-            v = c.get((copy[0], cn), [])[:3]
+            v = cal.get((copy[0], cn), [])[:3]
             if v and statistics.median(v) > 0.25 * 2 ** 20:
                 out.append(f"- {cn} per copy dispatch (KiB): {statistics.median(v):.1f} -> scale {scale[cn]:.4f}")
         out.append("")
@@ -130,6 +143,8 @@ def pmc(args):
     for pat, cls in SWEEP_CLASSES:
         # the MC-specialised kernels: sweeps <..., false (no speed pass), 0>, fused step <..., 0>
         names = [k for k in kernels if pat in k and (", false, 0>" in k or (cls == "step2d" and ", 0>" in k))]
+        if pat == "k_sweep_col<":
+            names = [k for k in names if _col_normal(k) == ("2" if cls == "y_sweep" else "3")]
         if not names:
             continue
         name = names[0]
@@ -144,8 +159,11 @@ def pmc(args):
             out.append(f"- FETCH_SIZE KiB: {fs:.1f} (scaled {rb / 1024:.1f})")
             out.append(f"- WRITE_SIZE KiB: {ws:.1f} (scaled {wb / 1024:.1f})")
             out.append(f"- {cls}_hbm_bytes_per_launch: {rb + wb:.0f}")
-            out.append(f"- ratio to algorithmic bytes: {(rb + wb) / alg_k:.3f} (read {2 * rb / alg_k:.3f}, "
-                       f"written {2 * wb / alg_k:.3f})")
+            k = 2 if cls == "step2d" else 1
+            alg_r = k * (args.meqn + args.maux) * args.real_bytes * args.ncell
+            alg_w = k * args.meqn * args.real_bytes * args.ncell
+            out.append(f"- ratio to algorithmic bytes: {(rb + wb) / alg_k:.3f} (read {rb / alg_r:.3f}, "
+                       f"written {wb / alg_w:.3f})")
         waves = _median(c.get((name, "SQ_WAVES"), []))
         valu = _median(c.get((name, "SQ_INSTS_VALU"), []))
         if waves:
@@ -183,6 +201,9 @@ def main():
     p.add_argument("--commands-file")
     p.add_argument("--ncell", type=int, required=True)
     p.add_argument("--real-bytes", type=int, default=4)
+    p.add_argument("--meqn", type=int, default=3, help="fields per cell (3 shallow water, 4 3D acoustics)")
+    p.add_argument("--maux", type=int, default=0, help="coefficient fields a sweep reads per cell")
+    p.add_argument("--calib", nargs="+", help="counter CSVs of runs with the copy kernel, for the calibration")
     p.add_argument("--trace")
     a = ap.parse_args()
     if a.cmd == "trace":
