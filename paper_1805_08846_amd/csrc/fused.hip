@@ -246,19 +246,24 @@ void k_step2d(FusedArgs<R> F) {
         } else {
 #pragma unroll
             for (int k = 0; k < FR; ++k) {
+                // rows past the chunk (only in the last iteration) run on stale
+                // ring rows and are neither stored nor counted: a march with no
+                // early exit keeps the window in the same registers step to step
                 const int yy = y0 + FR * (t - 1) + k;
-                if (yy >= y1) break;  // uniform
+                const bool live = yy < y1;  // uniform
                 CC w2;
                 ld(slot[k], w2);  // row yy + 2
                 C c2;
-                make_cell<R, SYS, MEQN>(w2.q, zc0, NRM, TNG, a.sqrt_grav, bad, c2);
+                bool rb = false;
+                make_cell<R, SYS, MEQN>(w2.q, zc0, NRM, TNG, a.sqrt_grav, rb, c2);
+                bad = bad || (live && rb);
                 I fd;
                 riemann(c1, c2, a.Z0, a.c0, R(0), a.grav, a.efix, fd);
-                smy = rmax(smy, iface_smax(fc));
+                smy = live ? rmax(smy, iface_smax(fc)) : smy;
                 Contrib<R> kc;
                 limit_contrib(fc, fb, fd, nuy, limiter_of<LIMK>(a), kc);
                 apply_update<R, SYS, MEQN>(w0.q, Rb, kc.L, nuy, NRM, TNG);
-                if (xin) {
+                if (xin && live) {
                     const unsigned off = (unsigned)(yy * nx + x);
                     CLAW_CHECK(off < (unsigned)a.ncell);
 #pragma unroll
