@@ -232,14 +232,6 @@ __device__ __forceinline__ FeatScale feat_scale(const LcNet& a, int kb) {
     F.mu = kb == 0 ? (double)a.nm.mu_h : 0.0;
     return F;
 }
-// v / s from the reciprocal r = 1/s and one residual correction (the
-// quotient rounded to nearest apart from rare last-bit cases, invisible after
-// the rounding to FP32 and BF16).
-__device__ __forceinline__ double qdiv(double v, double s, double r) {
-    const double q = __dmul_rn(v, r);
-    const double e = __builtin_fma(-q, s, v);
-    return __builtin_fma(e, r, q);
-}
 
 // A tile whose every face has its four stencil cells inside the grid (no
 // wall mirror): x faces first .. first + 63 need first >= 2 and
@@ -270,22 +262,24 @@ __device__ __forceinline__ void stencil_vals(const LcNet& a, const float* __rest
 }
 
 // The four features of one channel as the B operand elements of lane group
-// kb (zeros for kb = 3).  They are formed in FP64 without contraction (the
-// higher differences cancel; FP32 would round them coarsely) and rounded
-// FP64 -> FP32 -> BF16.
+// kb (zeros for kb = 3).  They are formed in FP64 (the higher differences
+// cancel; FP32 would round them coarsely) and rounded FP64 -> FP32 -> BF16.
 __device__ __forceinline__ bf16x4 feat_of(const float (&s)[4], int kb, const FeatScale& F) {
     bf16x4 x = {0, 0, 0, 0};
     if (kb < 3) {
         const double v0 = s[0], v1 = s[1], v2 = s[2], v3 = s[3];
         const double jump = __dsub_rn(v2, v1);
         const double mid = __dadd_rn(v1, v2);
-        const double lvl = __dsub_rn(__dmul_rn(mid, 0.5), F.mu);
+        const double lvl = __builtin_fma(mid, 0.5, -F.mu);  // mid / 2 is exact
         const double curv = __dsub_rn(__dadd_rn(v0, v3), mid);
-        const double third = __dsub_rn(__dsub_rn(v3, v0), __dmul_rn(3.0, jump));
-        x[0] = to_bf16((float)qdiv(lvl, F.s[0], F.r[0]));
-        x[1] = to_bf16((float)qdiv(jump, F.s[1], F.r[1]));
-        x[2] = to_bf16((float)qdiv(curv, F.s[2], F.r[2]));
-        x[3] = to_bf16((float)qdiv(third, F.s[3], F.r[3]));
+        const double third = __builtin_fma(-3.0, jump, __dsub_rn(v3, v0));
+        // divisions by the scales as products with their reciprocals: a last-bit
+        // difference in FP64 at most, gone after the rounding to FP32 and BF16
+        // except in rare ties
+        x[0] = to_bf16((float)__dmul_rn(lvl, F.r[0]));
+        x[1] = to_bf16((float)__dmul_rn(jump, F.r[1]));
+        x[2] = to_bf16((float)__dmul_rn(curv, F.r[2]));
+        x[3] = to_bf16((float)__dmul_rn(third, F.r[3]));
     }
     return x;
 }
