@@ -206,6 +206,8 @@ def bench_learned(args, torch, claw, inputs):
     tr = learned.Trainer(n_fine=1024, total_samples=runs * 250)
     for k in range(runs):
         tr.run(seed=1000 + k)
+        if (k + 1) % 25 == 0:
+            print(f"# learned: {k + 1} of {runs} training runs", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print(f"# learned: trained on {runs} runs ({tr.samples} Adam steps) in {t_train:.1f} s", file=sys.stderr,

@@ -318,8 +318,10 @@ def one_step_gain(lc, seeds, n_fine=1024, steps_fine=500, every=10, tau=TAU, kap
             if k % every == every // 2:
                 lc.forward(qcn, dF, dG)
                 lc.apply(qcn, plain, dF, dG, nu, nu, tau, kappa, out)
-                e_plain += (plain - target).abs().mean(dim=(1, 2)).double().cpu().numpy()
-                e_learned += (out - target).abs().mean(dim=(1, 2)).double().cpu().numpy()
+                torch.cuda.synchronize()
+                tg = target.cpu().numpy().astype(np.float64)
+                e_plain += np.abs(plain.cpu().numpy() - tg).mean(axis=(1, 2))
+                e_learned += np.abs(out.cpu().numpy() - tg).mean(axis=(1, 2))
                 count += 1
             qcn, target = target, qcn
         fine.close()
