@@ -37,11 +37,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
-def kernel_source_hash():
-    """Hash of the sweep kernels' sources with comments and blank lines removed
-    (a PMC summary stays valid across comment edits, not across code edits)."""
+# the sources each kernel class is built from (the shared headers and its own file)
+SOURCE_FILES = {"step2d": ("fused.hip", "sweep_body.h", "claw_device.h", "plugins.h"),
+                "sweeps": ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h")}
+
+
+def kernel_source_hash(kernel_class):
+    """Hash of the sources of a kernel class (step2d: the fused step; x_sweep,
+    y_sweep, z_sweep: the sweeps) with comments and blank lines removed (a
+    PMC summary stays valid across comment edits, not across code edits)."""
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h", "fused.hip"):
+    for f in SOURCE_FILES["step2d" if kernel_class == "step2d" else "sweeps"]:
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -50,10 +56,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_pmc(path, kernel_class, quantity, source_hash):
+def load_pmc(path, kernel_class, quantity):
     """A per-launch figure (quantity: "hbm_bytes", "valu_insts") of a kernel
     class from a committed rocprofv3 PMC summary, or None if missing or taken
-    on other kernel sources."""
+    on other sources of that kernel class."""
     if not path or not os.path.exists(path):
         return None
     vals = {}
@@ -63,7 +69,7 @@ def load_pmc(path, kernel_class, quantity, source_hash):
             if ":" in line:
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_hash") != source_hash:
+    if vals.get(f"{kernel_class}_source_hash") != kernel_source_hash(kernel_class):
         return None
     key = f"{kernel_class}_{quantity}_per_launch"
     try:
@@ -72,9 +78,9 @@ def load_pmc(path, kernel_class, quantity, source_hash):
         return None
 
 
-def load_traffic(path, kernel_class, source_hash):
+def load_traffic(path, kernel_class):
     """HBM bytes per launch of a kernel class (calibrated FETCH_SIZE + WRITE_SIZE)."""
-    return load_pmc(path, kernel_class, "hbm_bytes", source_hash)
+    return load_pmc(path, kernel_class, "hbm_bytes")
 
 
 # VALU issue peak of MI355X without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
@@ -595,9 +601,9 @@ def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):
     dom_s = ms[dom] / cnt[dom] * 1e-3
     achieved = alg_bytes / dom_s / 1e9
     pmc_file = args.traffic_file or os.path.join(ROOT, "profiles", f"pmc_sweeps_sw{n}_{args.dtype}.txt")
-    traffic = load_traffic(pmc_file, names[dom], kernel_source_hash())
-    valu = load_pmc(pmc_file, names[dom], "valu_insts", kernel_source_hash())
-    valu_frac = load_pmc(pmc_file, names[dom], "valu_issue_frac", kernel_source_hash())
+    traffic = load_traffic(pmc_file, names[dom])
+    valu = load_pmc(pmc_file, names[dom], "valu_insts")
+    valu_frac = load_pmc(pmc_file, names[dom], "valu_issue_frac")
     print(f"# kernel averages (us): {avg_us}", file=sys.stderr, flush=True)
     solver.close()
     del q, q_init

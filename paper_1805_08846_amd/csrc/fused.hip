@@ -244,15 +244,17 @@ void k_step2d(FusedArgs<R> F) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) Rb[i] = kb.Rr[i];
         } else {
+            // rows past the chunk (only in the last iteration) march on a copy of
+            // the last row this iteration swept (row y1 + 1) and are neither
+            // stored nor counted: a march with no early exit keeps the window in
+            // the same registers step to step
+            const int klast = y1 + 1 - (y0 - 2 + FR * t);  // uniform
 #pragma unroll
             for (int k = 0; k < FR; ++k) {
-                // rows past the chunk (only in the last iteration) run on stale
-                // ring rows and are neither stored nor counted: a march with no
-                // early exit keeps the window in the same registers step to step
                 const int yy = y0 + FR * (t - 1) + k;
                 const bool live = yy < y1;  // uniform
                 CC w2;
-                ld(slot[k], w2);  // row yy + 2
+                ld(slot[live ? k : klast], w2);  // row yy + 2
                 C c2;
                 bool rb = false;
                 make_cell<R, SYS, MEQN>(w2.q, zc0, NRM, TNG, a.sqrt_grav, rb, c2);

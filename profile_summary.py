@@ -53,11 +53,15 @@ def _col_normal(name):
     return args[3].strip() if len(args) > 3 else None
 
 
-def kernel_source_hash():
-    """Hash of the sweep kernels' sources without comments and blank lines
+SOURCE_FILES = {"step2d": ("fused.hip", "sweep_body.h", "claw_device.h", "plugins.h"),
+                "sweeps": ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h")}
+
+
+def kernel_source_hash(kernel_class):
+    """Hash of a kernel class's sources without comments and blank lines
     (the same function bench.py uses to accept a summary)."""
     h = hashlib.sha256()
-    for f in ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h", "fused.hip"):
+    for f in SOURCE_FILES["step2d" if kernel_class == "step2d" else "sweeps"]:
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -140,6 +144,7 @@ def pmc(args):
         out.append("")
     out.append(f"algorithmic bytes per sweep launch: {alg}")
     stats = read_stats(args.trace) if args.trace else {}
+    classes = []
     for pat, cls in SWEEP_CLASSES:
         # the MC-specialised kernels: sweeps <..., false (no speed pass), 0>, fused step <..., 0>
         names = [k for k in kernels if pat in k and (", false, 0>" in k or (cls == "step2d" and ", 0>" in k))]
@@ -148,6 +153,7 @@ def pmc(args):
         if not names:
             continue
         name = names[0]
+        classes.append(cls)
         out.append("")
         n = len(c.get((name, "SQ_WAVES"), []) or c.get((name, "FETCH_SIZE"), []))
         out.append(f"{cls} kernel {name}: {n} dispatches (medians per dispatch)")
@@ -184,7 +190,8 @@ def pmc(args):
                            f"4 x SQ_INSTS_VALU / (1024 SIMDs x 2.4 GHz x duration) = {frac:.3f}")
                 out.append(f"- {cls}_valu_issue_frac_per_launch: {frac:.4f}")
     out.append("")
-    out.append(f"kernel_source_hash: {kernel_source_hash()}")
+    for cls in classes:
+        out.append(f"{cls}_source_hash: {kernel_source_hash(cls)}")
     return "\n".join(out) + "\n"
 
 
