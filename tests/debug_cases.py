@@ -91,6 +91,19 @@ def run(claw, take=None):
                 s.sync_state()
                 done(f"sweep3d_{dtype}_{n[0]}x{n[1]}x{n[2]}_d{direction}", host(q))
                 s.close()
+    # acoustics x sweeps on rows of 64 cells per wavefront, extrapolation at both ends (whole-row kernel)
+    for nx, dtype in ((256, "f32"), (128, "f64")):
+        rng = np.random.default_rng(_seed("whole", nx, dtype))
+        prob = inputs._base(3, (nx, 5, 3), (0, 0, 0), (1.0, 0.8, 0.6), "acoustics", 4, "extrap", rho=1.7, bulk=2.9,
+                            has_aux=True, dtype=dtype)
+        shape = (3, 5, nx)
+        q = dev(inputs.round_to(rng.uniform(-1, 1, (4,) + shape), dtype), dtype)
+        a = dev(inputs.round_to(rng.uniform(0.5, 2.0, (2,) + shape), dtype), dtype)
+        s = claw.Solver(prob, q, a)
+        s.sweep(0, 0.3 / nx / 2.0)
+        s.sync_state()
+        done(f"sweep3d_whole_{dtype}_{nx}", host(q))
+        s.close()
     # fused steps (walls, and periodic in y), adaptive
     for dtype in ("f32", "f64"):
         for ybc in ("wall", "periodic"):
