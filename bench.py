@@ -43,11 +43,12 @@ SOURCE_FILES = {"step2d": ("fused.hip", "sweep_body.h", "claw_device.h", "plugin
 
 
 def kernel_source_hash(kernel_class):
-    """Hash of the sources of a kernel class (step2d: the fused step; x_sweep,
-    y_sweep, z_sweep: the sweeps) with comments and blank lines removed (a
+    """Hash of the sources of a kernel class (step2d, xy_step: the fused 2D step
+    and the fused x and y step of 3D acoustics; x_sweep, y_sweep, z_sweep: the
+    sweeps) with comments and blank lines removed (a
     PMC summary stays valid across comment edits, not across code edits)."""
     h = hashlib.sha256()
-    for f in SOURCE_FILES["step2d" if kernel_class == "step2d" else "sweeps"]:
+    for f in SOURCE_FILES["step2d" if kernel_class in ("step2d", "xy_step") else "sweeps"]:
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -339,6 +340,7 @@ def bench_ac3d(args, torch, claw, inputs):
     steps = args.steps if args.steps_given else 200
     warmup = args.warmup if args.warmup_given else 200
     prob, q0, aux = inputs.acoustics3d_layers(n=n, dtype=args.dtype, nsteps=steps)
+    prob["fused_step"] = args.fused_step  # None: the library's choice (the fused x and y step at 256^3 FP32)
     ncell = n ** 3
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
     q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
@@ -352,13 +354,17 @@ def bench_ac3d(args, torch, claw, inputs):
     elapsed = time.perf_counter() - t0
     ms, cnt = solver.advance_timed(args.timed_steps)
     solver.close()
-    names = ["x_sweep", "y_sweep", "z_sweep", "control"]
-    avg_us = {names[k]: (ms[k] / cnt[k] * 1e3 if cnt[k] else None) for k in range(4)}
+    fused = cnt[0] > 0 and cnt[1] == 0  # slot 0 holds the fused x and y step
+    names = ["xy_step" if fused else "x_sweep", "y_sweep", "z_sweep", "control"]
+    avg_us = {names[k]: (ms[k] / cnt[k] * 1e3 if cnt[k] else None) for k in range(4) if cnt[k] or k != 1}
     dom = max(range(3), key=lambda k: ms[k] / cnt[k] if cnt[k] else 0.0)
     real_bytes = 4 if args.dtype == "f32" else 8
-    alg_bytes = (2 * 4 + 2) * real_bytes * ncell  # p, u, v, w read and written, rho and K read
+    # per launch, a sweep and the fused x and y step alike: p, u, v, w read and
+    # written, Z and c read
+    alg_bytes = (2 * 4 + 2) * real_bytes * ncell
     dom_s = ms[dom] / cnt[dom] * 1e-3
     achieved = alg_bytes / dom_s / 1e9
+    pmc_file = os.path.join(ROOT, "profiles", f"pmc_sweeps_ac3d{n}_{args.dtype}.txt")
     line = {
         "metric": "Gcell-updates/s + % HBM roofline", "value": ncell * steps / elapsed / 1e9,
         "unit": "Gcell-updates/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -368,9 +374,10 @@ def bench_ac3d(args, torch, claw, inputs):
         "config": {"workload": "3D linear acoustics, two-layer medium (rho 1 / 4, K 1), extrapolation, "
                                "MC, CFL 0.9", "grid": [n, n, n], "cells": ncell, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None, "kernel": names[dom],
-                     "alg_bytes_per_launch": alg_bytes, "avg_launch_us": dom_s * 1e6},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": load_traffic(pmc_file, names[dom]),
+                     "kernel": names[dom], "alg_bytes_per_launch": alg_bytes, "avg_launch_us": dom_s * 1e6},
         "kernel_avg_us": avg_us, "rejected_trials": nrej,
+        "path": "fused x and y step, then the z sweep" if fused else "x, y and z sweeps",
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps or 10, aux)

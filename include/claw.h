@@ -54,8 +54,12 @@ typedef struct claw_solver claw_solver; /* opaque */
  * fused step when its state holds at least CLAW_FUSED_AUTO_BYTES (measured on
  * MI355X: fused faster from 3072^2 (108 MiB) up, the sweeps faster at 2048^2,
  * whose source and destination stay in the 256 MB Infinity Cache), else the x
- * and y sweeps; FP64 grids take the sweeps (measured faster at every size).  Other problems ignore
- * both flags. */
+ * and y sweeps; FP64 grids take the sweeps (measured faster at every size).
+ * 3D acoustics grids whose rows hold 256 FP32 (128 FP64) cells with
+ * extrapolation at both x ends follow the same rule with one kernel for the x
+ * and y sweeps of every z plane, then the z sweep kernel (same results; at
+ * 256^3 FP32 about 1.5x the three sweep kernels).  Other problems ignore both
+ * flags. */
 #define CLAW_FLAG_FUSED_STEP 1
 #define CLAW_FLAG_SPLIT_STEP 4
 #define CLAW_FUSED_AUTO_BYTES (96ull << 20)

@@ -33,6 +33,18 @@ struct FusedArgs {
 };
 template <typename R>
 hipError_t launch_step2d(const FusedArgs<R>& F, hipStream_t s);
+// The x and y sweeps of a 3D acoustics step fused (fused.hip), for rows of
+// exactly 64 CPL cells (256 FP32, 128 FP64) with extrapolation at both x ends;
+// the z sweep follows as a column sweep.  a: the x-sweep arguments; ny, nz
+// and the y boundaries complete the grid; chunk: rows of one z plane per
+// workgroup.  The result goes to buffer cur + 1, as the 2D step's does.
+template <typename R>
+struct Fused3Args {
+    SweepArgs<R> a;
+    int32_t ny, nz, bcy_lo, bcy_hi, chunk;
+};
+template <typename R>
+hipError_t launch_step_xy3(const Fused3Args<R>& F, int sys, hipStream_t s);
 // Decides the previous trial into step-state copy p and clears p's speed slots.
 hipError_t launch_open(Ctrl* c, int p, bool fp32, hipStream_t s);
 int fused_rows_per_iteration();

@@ -289,6 +289,247 @@ void k_step2d(FusedArgs<R> F) {
     block_finish2(a, smx, smy, bad);
 }
 
+// ---------------------------------------------------------------------------
+// 3D acoustics: x and y sweeps of one z plane fused
+// ---------------------------------------------------------------------------
+// Neither the x nor the y sweep couples z planes, so each plane's pair of
+// sweeps is a 2D fused step.  The rows are exactly 64 CPL cells with
+// extrapolation at both ends, so a wavefront x-sweeps a whole row with no halo
+// lanes (the ghost cells equal the end cells: lane 0 takes its own first cell
+// as its left neighbour, and the shifted neighbour faces and contributions
+// that lanes 0 and 63 receive as zeros are faces without waves), and the four
+// wavefronts' lanes are the row's columns in the y march.  Phase A writes p
+// and the y velocity of Q*, with Z and c of per-cell coefficients, into the
+// LDS rows; the x velocity of Q* and the z velocity go straight to the
+// destination (the y sweep leaves both unchanged).  Phase B marches p and v
+// down the columns.  Same arithmetic per interface as the x and y sweeps.
+template <typename R, int SYS, int CPL, int LIMK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED_WPE)))
+void k_step_xy3(Fused3Args<R> F) {
+    static_assert(SYS == SYS_AC || SYS == SYS_ACV, "the 3D fused step is for acoustics");
+    constexpr int MEQN = 4;
+    constexpr int NX = 64 * CPL;                 // cells per row
+    constexpr int NL = SYS == SYS_ACV ? 4 : 2;   // LDS fields: p, v (, Z, c)
+    constexpr int NC = contrib_width<SYS>();
+    using C = Cell<R, SYS>;
+    using I = Iface<R, SYS>;
+    typedef typename VecOf<R, CPL>::type V;
+    __shared__ R ring[2][FR][NL][NX];
+
+    const SweepArgs<R>& a = F.a;
+    const StepState& S = a.ctrl->st[a.parity];
+    if (S.done) return;  // the whole grid skips
+    const int cur = wave_uniform(S.cur);
+    const R nux = wave_uniform(state_nu<R>(S, 0)), nuy = wave_uniform(state_nu<R>(S, 1));
+    const R* __restrict__ src = pick_buf(a, cur);
+    R* __restrict__ dst = pick_buf(a, (cur + 1) % 3);
+    const R inv2Z = ac_inv2Z<R, SYS>(a);
+
+    const int lane = threadIdx.x & 63, wave = wave_uniform((int)(threadIdx.x >> 6));
+    const int ny = F.ny;
+    const int y0 = blockIdx.x * F.chunk;
+    const int y1 = y0 + F.chunk < ny ? y0 + F.chunk : ny;
+    const unsigned plane = (unsigned)blockIdx.y * (unsigned)ny * (unsigned)NX;  // first cell of the plane
+    const int nt = (y1 - y0 + FR - 1) / FR + 1;  // iterations (the first only fills the window)
+    const unsigned fbytes = (unsigned)a.ncell * (unsigned)sizeof(R);
+    const unsigned xoff = (unsigned)(lane * CPL);
+
+    // ---- x sweep of one whole row per wavefront (phase A) ------------------
+    // loads the lane's cells of virtual row v (a ghost row loads its source row)
+    auto row_base = [&](int v, bool& fy) { return plane + (unsigned)(ghost_idx(v, ny, F.bcy_lo, F.bcy_hi, fy) * NX); };
+    auto load_row = [&](int v, R (&q)[CPL][MEQN], R (&zc)[CPL][2]) {
+        bool fy;
+        const unsigned voff = (row_base(v, fy) + xoff) * (unsigned)sizeof(R);
+#pragma unroll
+        for (int e = 0; e < MEQN; ++e) {
+            V vv = buf_load16<V>(field_rsrc(src + (size_t)e * (unsigned)a.ncell, fbytes), voff);
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) q[c][e] = vv[c];
+        }
+        if constexpr (SYS == SYS_ACV) {
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                V vv = buf_load16<V>(field_rsrc(a.zc + (size_t)f * (unsigned)a.ncell, fbytes), voff);
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) zc[c][f] = vv[c];
+            }
+        }
+    };
+    R smx = R(0);
+    bool bad = false;
+    auto sweep_row = [&](int v, R (&q)[CPL][MEQN], const R (&zc)[CPL][2], R (*out)[NX]) {
+        constexpr int nrm = 1, tng = 2;
+        C cell[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) make_cell<R, SYS, MEQN>(q[c], zc[c], nrm, tng, a.sqrt_grav, bad, cell[c]);
+        C left;
+        cell_prev(cell[CPL - 1], left);
+        if (lane == 0) left = cell[0];  // ghost cell -1 = cell 0 (extrapolation)
+        I f[CPL];
+        solve_iface<R, SYS, 0>(left, cell[0], a, inv2Z, f[0]);
+#pragma unroll
+        for (int c = 1; c < CPL; ++c) solve_iface<R, SYS, 0>(cell[c - 1], cell[c], a, inv2Z, f[c]);
+        const bool real = v >= y0 && v < y1;  // uniform: a row of this chunk (each row counts once)
+        if (real) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) smx = rmax(smx, iface_smax(f[c]));
+        }
+        I fprev, fnext;
+        iface_prev(f[CPL - 1], fprev);  // lane 0: zeros, face -1 without waves
+        iface_next(f[0], fnext);        // lane 63: zeros, face nx without waves
+        Contrib<R, NC> k[CPL];
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const I& km = c == 0 ? fprev : f[c - 1];
+            const I& kp = c == CPL - 1 ? fnext : f[c + 1];
+            limit_contrib(f[c], km, kp, nux, limiter_of<LIMK>(a), k[c]);
+        }
+        R Lnext[NC];
+#pragma unroll
+        for (int n = 0; n < NC; ++n) Lnext[n] = lane_next(k[0].L[n]);  // lane 63: face nx contributes 0
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            if (c < CPL - 1) apply_update<R, SYS, MEQN>(q[c], k[c].Rr, k[c + 1].L, nux, nrm, tng);
+            else apply_update<R, SYS, MEQN>(q[c], k[c].Rr, Lnext, nux, nrm, tng);
+        }
+        // a wall ghost row of Q* is its source row with the y velocity negated
+        bool fy;
+        const unsigned base = row_base(v, fy);
+        V vp, vv;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            vp[c] = q[c][0];
+            vv[c] = fy ? -q[c][2] : q[c][2];
+        }
+        *reinterpret_cast<V*>(&out[0][xoff]) = vp;
+        *reinterpret_cast<V*>(&out[1][xoff]) = vv;
+        if constexpr (SYS == SYS_ACV) {
+            V vz, vc;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                vz[c] = zc[c][0];
+                vc[c] = zc[c][1];
+            }
+            *reinterpret_cast<V*>(&out[2][xoff]) = vz;
+            *reinterpret_cast<V*>(&out[3][xoff]) = vc;
+        }
+        if (real) {  // the x and z velocities of Q** are those of Q*
+            const unsigned voff = (base + xoff) * (unsigned)sizeof(R);
+#pragma unroll
+            for (int e = 1; e < MEQN; e += 2) {
+                V vo;
+#pragma unroll
+                for (int c = 0; c < CPL; ++c) vo[c] = q[c][e];
+                buf_store16<V>(field_rsrc(dst + (size_t)e * (unsigned)a.ncell, fbytes), voff, vo);
+            }
+        }
+    };
+
+    // ---- y march of one column per lane (phase B) --------------------------
+    // the column's cells carry p and v in a two-field state (normal field 1)
+    constexpr int NRM = 1, TNG = 0;
+    const int lc = (int)threadIdx.x;
+    const bool xin = lc < NX;  // FP64 rows (128 cells) leave wavefronts 2 and 3 idle here
+    const int lcc = xin ? lc : 0;
+    struct YC {
+        R q[2];
+        R zc[2];
+    };
+    auto ld = [&](R (*row)[NX], YC& o) {
+        o.q[0] = row[0][lcc];
+        o.q[1] = row[1][lcc];
+        if constexpr (SYS == SYS_ACV) {
+            o.zc[0] = row[2][lcc];
+            o.zc[1] = row[3][lcc];
+        } else {
+            o.zc[0] = R(0);
+            o.zc[1] = R(0);
+        }
+    };
+    auto mk = [&](const YC& w, C& c) { make_cell<R, SYS, 2>(w.q, w.zc, NRM, TNG, a.sqrt_grav, bad, c); };
+    const Rsrc rp = field_rsrc(dst, fbytes);
+    const Rsrc rv = field_rsrc(dst + (size_t)2 * (unsigned)a.ncell, fbytes);
+    YC w0, w1;
+    C c1;
+    I fb, fc;
+    R Rb[NC];
+    R smy = R(0);
+
+    R qa[CPL][MEQN], qn[CPL][MEQN];
+    R za[CPL][2] = {}, zn[CPL][2] = {};
+    load_row(y0 - 2 + wave, qa, za);
+    for (int t = 0; t < nt; ++t) {
+        const int v = y0 - 2 + FR * t + wave;
+        if (t + 1 < nt) load_row(v + FR, qn, zn);  // the next row's loads overlap this iteration
+        R (*slot)[NL][NX] = ring[t & 1];
+        if (v <= y1 + 1) sweep_row(v, qa, za, slot[wave]);
+        __syncthreads();
+        if (t == 0) {
+            // window of rows y0 - 2 .. y0 + 1
+            YC wm2, wm1;
+            C cm2, cm1, c0;
+            ld(slot[0], wm2);
+            ld(slot[1], wm1);
+            ld(slot[2], w0);
+            ld(slot[3], w1);
+            mk(wm2, cm2);
+            mk(wm1, cm1);
+            mk(w0, c0);
+            mk(w1, c1);
+            I fa;
+            solve_iface<R, SYS, 1>(cm2, cm1, a, inv2Z, fa);
+            solve_iface<R, SYS, 1>(cm1, c0, a, inv2Z, fb);
+            solve_iface<R, SYS, 1>(c0, c1, a, inv2Z, fc);
+            if (y0 == 0) smy = iface_smax(fb);
+            Contrib<R, NC> kb;
+            limit_contrib(fb, fa, fc, nuy, limiter_of<LIMK>(a), kb);
+#pragma unroll
+            for (int i = 0; i < NC; ++i) Rb[i] = kb.Rr[i];
+        } else {
+            // rows past the chunk (only in the last iteration) march on a copy of
+            // the last row this iteration swept (row y1 + 1) and are neither
+            // stored nor counted
+            const int klast = y1 + 1 - (y0 - 2 + FR * t);  // uniform
+#pragma unroll
+            for (int k = 0; k < FR; ++k) {
+                const int yy = y0 + FR * (t - 1) + k;
+                const bool live = yy < y1;  // uniform
+                YC w2;
+                ld(slot[live ? k : klast], w2);  // row yy + 2
+                C c2;
+                mk(w2, c2);
+                I fd;
+                solve_iface<R, SYS, 1>(c1, c2, a, inv2Z, fd);
+                smy = live ? rmax(smy, iface_smax(fc)) : smy;
+                Contrib<R, NC> kc;
+                limit_contrib(fc, fb, fd, nuy, limiter_of<LIMK>(a), kc);
+                apply_update<R, SYS, 2>(w0.q, Rb, kc.L, nuy, NRM, TNG);
+                if (xin && live) {
+                    const unsigned off = (plane + (unsigned)(yy * NX + lc)) * (unsigned)sizeof(R);
+                    buf_store(rp, off, 0u, w0.q[0]);
+                    buf_store(rv, off, 0u, w0.q[1]);
+                }
+#pragma unroll
+                for (int i = 0; i < NC; ++i) Rb[i] = kc.Rr[i];
+                fb = fc;
+                fc = fd;
+                w0 = w1;
+                w1 = w2;
+                c1 = c2;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+#pragma unroll
+            for (int e = 0; e < MEQN; ++e) qa[c][e] = qn[c][e];
+#pragma unroll
+            for (int f = 0; f < 2; ++f) za[c][f] = zn[c][f];
+        }
+    }
+    if (!xin) smy = R(0);
+    block_finish2(a, smx, smy, bad);
+}
+
 }  // namespace
 
 int fused_rows_per_iteration() { return FR; }
@@ -309,7 +550,26 @@ hipError_t launch_step2d(const FusedArgs<R>& F, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_step_xy3(const Fused3Args<R>& F, int sys, hipStream_t s) {
+    constexpr int CPL = sizeof(R) == 4 ? 4 : 2;
+    if (F.chunk < 1 || F.a.nx != 64 * CPL || F.nz < 1 || F.nz > 65535 || (sys != SYS_AC && sys != SYS_ACV))
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((F.ny + F.chunk - 1) / F.chunk), (unsigned)F.nz);
+    const bool mc = F.a.limiter == LIM_MC;
+    if (sys == SYS_ACV) {
+        if (mc) hipLaunchKernelGGL((k_step_xy3<R, SYS_ACV, CPL, LIM_MC>), grid, dim3(256), 0, s, F);
+        else hipLaunchKernelGGL((k_step_xy3<R, SYS_ACV, CPL, LIM_RUNTIME>), grid, dim3(256), 0, s, F);
+    } else {
+        if (mc) hipLaunchKernelGGL((k_step_xy3<R, SYS_AC, CPL, LIM_MC>), grid, dim3(256), 0, s, F);
+        else hipLaunchKernelGGL((k_step_xy3<R, SYS_AC, CPL, LIM_RUNTIME>), grid, dim3(256), 0, s, F);
+    }
+    return hipGetLastError();
+}
+
 template hipError_t launch_step2d<float>(const FusedArgs<float>&, hipStream_t);
 template hipError_t launch_step2d<double>(const FusedArgs<double>&, hipStream_t);
+template hipError_t launch_step_xy3<float>(const Fused3Args<float>&, int, hipStream_t);
+template hipError_t launch_step_xy3<double>(const Fused3Args<double>&, int, hipStream_t);
 
 }  // namespace claw

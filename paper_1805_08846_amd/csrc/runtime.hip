@@ -135,6 +135,7 @@ struct claw_solver {
     int sys;
     bool fp32;
     bool fused;   // one fused kernel per 2D step (fused.hip) instead of an x and a y sweep
+    bool fused3;  // 3D acoustics: one fused x and y kernel (fused.hip), then the z sweep
     bool strang;  // Strang splitting: half-step sweeps around a full step of the last direction
     hipStream_t stream;
     hipStream_t cap_stream;
@@ -269,9 +270,11 @@ int trial_sweeps(const claw_solver* h, int* dirs, int* so, int* dof) {
     return k;
 }
 
-// Buffer offset of a step's result: the fused 2D step writes cur + 1.
+// Buffer offset of a step's result: the fused 2D step writes cur + 1; the
+// fused 3D x and y step writes cur + 1 and the z sweep cur + 2.
 int result_offset_of(const claw_solver* h) {
     if (h->fused) return 1;
+    if (h->fused3) return 2;
     int dirs[5], so[5], dof[5];
     const int k = trial_sweeps(h, dirs, so, dof);
     return dof[k - 1];
@@ -307,6 +310,47 @@ int fused_chunk(int64_t nx, int64_t ny, bool fp32) {
     return (int)chunk;
 }
 
+// Rows of one z plane per workgroup of the fused 3D acoustics x and y step:
+// the planes split into as many chunks as three workgroups per CU allow, at
+// least 16 rows each (measured at 256^3 FP32: 24 / 32 / 52 / 64 / 86 rows
+// give 142.3 / 141.5 / 146.9 / 139.6 / 136.4 us per launch; 86 rows are three
+// chunks per plane, 768 workgroups).  CLAW_FUSED_CHUNK overrides it as for
+// the 2D step.
+int fused3_chunk(int64_t ny, int64_t nz) {
+    static const int64_t cus = [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0)
+            n = 256;
+        return (int64_t)n;
+    }();
+    static const int64_t forced = [] {
+        const char* e = getenv("CLAW_FUSED_CHUNK");
+        return e ? (int64_t)atoll(e) : (int64_t)0;
+    }();
+    int64_t per_plane = 3 * cus / (nz > 0 ? nz : 1);
+    if (per_plane < 1) per_plane = 1;
+    int64_t chunk = forced > 0 ? forced : (ny + per_plane - 1) / per_plane;
+    if (forced <= 0 && chunk < 16) chunk = 16;
+    if (chunk > ny) chunk = ny;
+    if (chunk < 1) chunk = 1;
+    return (int)chunk;
+}
+
+template <typename R>
+Fused3Args<R> fused3_args(const claw_solver* h, int parity) {
+    Fused3Args<R> F;
+    memset(&F, 0, sizeof F);
+    F.a = sweep_args<R>(h, 0, 0, 1);
+    F.a.parity = parity;
+    F.ny = (int32_t)h->d.n[1];
+    F.nz = (int32_t)h->d.n[2];
+    F.bcy_lo = h->d.bc_lo[1];
+    F.bcy_hi = h->d.bc_hi[1];
+    F.chunk = fused3_chunk(h->d.n[1], h->d.n[2]);
+    return F;
+}
+
 template <typename R>
 FusedArgs<R> fused_args(const claw_solver* h, int parity) {
     FusedArgs<R> F;
@@ -331,6 +375,17 @@ claw_status enqueue_trial(claw_solver* h, hipStream_t s, hipEvent_t* ev) {
         if (h->fp32) HIP_TRY(launch_step2d<float>(fused_args<float>(h, h->parity), s));
         else HIP_TRY(launch_step2d<double>(fused_args<double>(h, h->parity), s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+        h->parity ^= 1;
+        return CLAW_OK;
+    }
+    if (h->fused3) {
+        HIP_TRY(launch_open(h->ctrl, h->parity, h->fp32, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+        if (h->fp32) HIP_TRY(launch_step_xy3<float>(fused3_args<float>(h, h->parity), h->sys, s));
+        else HIP_TRY(launch_step_xy3<double>(fused3_args<double>(h, h->parity), h->sys, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(enqueue_sweep(h, 2, 1, 2, false, h->parity, false, false, s));
+        if (ev) HIP_TRY(hipEventRecord(ev[2], s));
         h->parity ^= 1;
         return CLAW_OK;
     }
@@ -474,7 +529,13 @@ void bind_solver(claw_solver* h, const claw_desc* d, const Plan& p, void* q, cha
     h->strang = (d->flags & CLAW_FLAG_STRANG) != 0;
     const bool fusable = !h->strang && h->sys == SYS_SW && d->ndim == 2;
     const bool big = d->dtype == CLAW_FP32 && (uint64_t)p.state_bytes >= (uint64_t)CLAW_FUSED_AUTO_BYTES;
-    h->fused = fusable && ((d->flags & CLAW_FLAG_FUSED_STEP) || (big && !(d->flags & CLAW_FLAG_SPLIT_STEP)));
+    const bool want = (d->flags & CLAW_FLAG_FUSED_STEP) || (big && !(d->flags & CLAW_FLAG_SPLIT_STEP));
+    h->fused = fusable && want;
+    // 3D acoustics with rows of one wavefront's cells and extrapolation at both x ends
+    const bool fusable3 = !h->strang && (h->sys == SYS_AC || h->sys == SYS_ACV) && d->ndim == 3 &&
+                          d->n[0] == (d->dtype == CLAW_FP32 ? 256 : 128) && d->n[2] <= 65535 &&
+                          d->bc_lo[0] == CLAW_BC_EXTRAP && d->bc_hi[0] == CLAW_BC_EXTRAP;
+    h->fused3 = fusable3 && want;
     h->stream = stream;
     h->ctrl = (Ctrl*)(ws + p.off_ctrl);
     h->buf[0] = q;
@@ -776,13 +837,14 @@ claw_status claw_advance_timed(claw_solver* h, int64_t nsteps, double* kernel_ms
             if (st) return st;
             HIP_TRY(hipStreamSynchronize(h->stream));
             int dirs[5], so[5], dof[5];
-            const int nk = h->fused ? 1 : trial_sweeps(h, dirs, so, dof);  // timed kernels per trial
+            // timed kernels per trial (the fused 3D x and y step counts in slot 0)
+            const int nk = h->fused ? 1 : (h->fused3 ? 2 : trial_sweeps(h, dirs, so, dof));
             for (int64_t k = 0; k < n; ++k) {
                 hipEvent_t* ev = &h->events[k * per];
                 for (int j = 0; j < nk; ++j) {
                     float v = 0;
                     HIP_TRY(hipEventElapsedTime(&v, ev[j], ev[j + 1]));
-                    const int slot = h->fused ? 0 : dirs[j];
+                    const int slot = h->fused ? 0 : (h->fused3 ? 2 * j : dirs[j]);
                     ms[slot] += v;
                     cnt[slot] += 1;
                 }

@@ -43,8 +43,11 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 VALU_PEAK_SIMD_CLOCKS = 1024 * 2.4e9  # SIMDs x clock (Hz)
-SWEEP_CLASSES = (("k_sweep_row<", "x_sweep"), ("k_sweep_col<", "y_sweep"), ("k_sweep_col<", "z_sweep"),
-                 ("k_step2d<", "step2d"))
+# kernel name patterns of each class (the whole-row x sweep is an x sweep; the
+# fused x and y step of 3D acoustics moves as many bytes per launch as a sweep)
+SWEEP_CLASSES = ((("k_sweep_row<", "k_sweep_row_whole<"), "x_sweep"), (("k_sweep_col<",), "y_sweep"),
+                 (("k_sweep_col<",), "z_sweep"), (("k_step2d<",), "step2d"), (("k_step_xy3<",), "xy_step"))
+FUSED_CLASSES = ("step2d", "xy_step")
 
 
 def _col_normal(name):
@@ -61,7 +64,7 @@ def kernel_source_hash(kernel_class):
     """Hash of a kernel class's sources without comments and blank lines
     (the same function bench.py uses to accept a summary)."""
     h = hashlib.sha256()
-    for f in SOURCE_FILES["step2d" if kernel_class == "step2d" else "sweeps"]:
+    for f in SOURCE_FILES["step2d" if kernel_class in FUSED_CLASSES else "sweeps"]:
         with open(os.path.join(ROOT, "paper_1805_08846_amd", "csrc", f)) as fh:
             for line in fh:
                 code = line.split("//", 1)[0].strip()
@@ -145,10 +148,11 @@ def pmc(args):
     out.append(f"algorithmic bytes per sweep launch: {alg}")
     stats = read_stats(args.trace) if args.trace else {}
     classes = []
-    for pat, cls in SWEEP_CLASSES:
-        # the MC-specialised kernels: sweeps <..., false (no speed pass), 0>, fused step <..., 0>
-        names = [k for k in kernels if pat in k and (", false, 0>" in k or (cls == "step2d" and ", 0>" in k))]
-        if pat == "k_sweep_col<":
+    for pats, cls in SWEEP_CLASSES:
+        # the MC-specialised kernels: sweeps <..., false (no speed pass), 0>, fused steps <..., 0>
+        names = [k for k in kernels if any(p in k for p in pats) and
+                 (", false, 0>" in k or (cls in FUSED_CLASSES and ", 0>" in k))]
+        if cls in ("y_sweep", "z_sweep"):
             names = [k for k in names if _col_normal(k) == ("2" if cls == "y_sweep" else "3")]
         if not names:
             continue

@@ -104,6 +104,21 @@ def run(claw, take=None):
         s.sync_state()
         done(f"sweep3d_whole_{dtype}_{nx}", host(q))
         s.close()
+    # fused x and y steps of 3D acoustics (rows of 64 cells per wavefront), adaptive
+    for nx, ny, aux, dtype, ybc in ((256, 5, True, "f32", "wall"), (128, 3, False, "f64", "periodic")):
+        rng = np.random.default_rng(_seed("fused3", nx, dtype))
+        prob = inputs._base(3, (nx, ny, 3), (0, 0, 0), (1.0, 0.8, 0.6), "acoustics", 4, "extrap", rho=1.7,
+                            bulk=2.9, has_aux=aux, dtype=dtype)
+        prob["bc_lo"] = ("extrap", ybc, "wall")
+        prob["bc_hi"] = ("extrap", ybc, "periodic")
+        prob["fused_step"] = True
+        shape = (3, ny, nx)
+        q = dev(inputs.round_to(rng.uniform(-1, 1, (4,) + shape), dtype), dtype)
+        a = dev(inputs.round_to(rng.uniform(0.5, 2.0, (2,) + shape), dtype), dtype) if aux else None
+        s = claw.Solver(prob, q, a)
+        s.advance(3)
+        done(f"fused3_{dtype}_{nx}x{ny}", host(q))
+        s.close()
     # fused steps (walls, and periodic in y), adaptive
     for dtype in ("f32", "f64"):
         for ybc in ("wall", "periodic"):

@@ -1,0 +1,123 @@
+"""The fused x and y step of 3D acoustics (CLAW_FLAG_FUSED_STEP, or an FP32
+state of at least CLAW_FUSED_AUTO_BYTES): rows of exactly 64 CPL cells (256
+FP32, 128 FP64) with extrapolation at both x ends, one kernel for the x and y
+sweeps of every z plane, then the z sweep.  Against the CPU oracle (FP64
+1e-12, FP32 1e-5 relative L-infinity of the whole state) and against the
+split sweeps (FP64 1e-13, FP32 1e-6); constant and per-cell coefficients,
+every y and z boundary rule, chunk edges (a ragged last chunk, planes of one
+and two rows), adaptive and prescribed steps, and the library's choice of the
+path by grid and size."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_08846_amd import inputs
+from helpers import rel_linf
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+TOL = {"f64": 1e-12, "f32": 1e-5}
+SPLIT_TOL = {"f64": 1e-13, "f32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def claw():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_08846_amd import claw as c
+    return c
+
+
+def _prob(n, aux, dtype, bcy, bcz, seed):
+    nx, ny, nz = n
+    prob = inputs._base(3, n, (0, 0, 0), (1.0, 0.7, 0.5), "acoustics", 4, "extrap", rho=1.7, bulk=2.9,
+                        has_aux=aux, dtype=dtype)
+    prob["bc_lo"] = ("extrap", bcy[0], bcz[0])
+    prob["bc_hi"] = ("extrap", bcy[1], bcz[1])
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    pulse = np.exp(-40.0 * ((x[None, None, :] - 0.4) ** 2 + (y[None, :, None] - 0.6) ** 2))
+    q0 = 0.2 * rng.uniform(-1, 1, (4,) + shape)
+    q0[0] += np.broadcast_to(pulse, shape)
+    a0 = rng.uniform(0.5, 2.0, (2,) + shape) if aux else None
+    return prob, inputs.round_to(q0, dtype), None if a0 is None else inputs.round_to(a0, dtype)
+
+
+def _run(claw, prob, q0, a0, fused, steps=None, dts=None):
+    prob = dict(prob, fused_step=fused)
+    dt = torch.float64 if prob["dtype"] == "f64" else torch.float32
+    q = torch.tensor(q0, dtype=dt, device="cuda").contiguous()
+    a = None if a0 is None else torch.tensor(a0, dtype=dt, device="cuda").contiguous()
+    s = claw.Solver(prob, q, a)
+    if dts is None:
+        t, nrej = s.advance(steps)
+    else:
+        s.advance_fixed(dts)
+        t, nrej = s.control()["t"], 0
+    torch.cuda.synchronize()
+    out = q.double().cpu().numpy()
+    ms, cnt = s.advance_timed(1)
+    s.close()
+    return out, t, nrej, cnt
+
+
+CASES = [
+    ((256, 20, 6), True, "f32", ("wall", "periodic"), ("periodic", "periodic")),
+    ((128, 23, 5), True, "f64", ("periodic", "periodic"), ("wall", "extrap")),
+    ((256, 17, 4), False, "f32", ("extrap", "wall"), ("wall", "wall")),
+    ((128, 9, 3), False, "f64", ("wall", "wall"), ("extrap", "periodic")),
+    ((256, 37, 3), True, "f32", ("extrap", "extrap"), ("extrap", "extrap")),
+    ((256, 1, 5), True, "f32", ("wall", "extrap"), ("periodic", "periodic")),
+    ((128, 2, 4), True, "f64", ("periodic", "periodic"), ("wall", "wall")),
+]
+
+
+@pytest.mark.parametrize("n,aux,dtype,bcy,bcz", CASES, ids=lambda v: str(v))
+def test_fused3_adaptive_matches_oracle_and_split(claw, n, aux, dtype, bcy, bcz):
+    prob, q0, a0 = _prob(n, aux, dtype, bcy, bcz, seed=sum(n))
+    out, t, nrej, cnt = _run(claw, prob, q0, a0, True, steps=12)
+    assert cnt[0] >= 1 and cnt[1] == 0 and cnt[2] >= 1  # fused x and y kernel, then the z sweep
+    ref = oracle.advance(prob, q0, a0, 12)
+    err, per = rel_linf(out, ref["q"])
+    print(f"fused3 {n} aux={aux} {dtype}: rel err vs oracle {err:.3g}")
+    assert err <= TOL[dtype], per
+    assert nrej == ref["nreject"]
+    assert t == pytest.approx(ref["t"], rel=1e-12 if dtype == "f64" else 1e-5)
+    split, t2, nrej2, cnt2 = _run(claw, prob, q0, a0, False, steps=12)
+    assert cnt2[1] >= 1
+    print(f"  vs split sweeps: rel {rel_linf(out, split)[0]:.3g}, equal values: {np.array_equal(out, split)}")
+    assert rel_linf(out, split)[0] <= SPLIT_TOL[dtype]
+    assert nrej2 == nrej
+
+
+def test_fused3_prescribed_steps(claw):
+    prob, q0, a0 = _prob((256, 11, 7), True, "f32", ("wall", "wall"), ("periodic", "periodic"), seed=5)
+    dts = np.array([0.9, 0.4, 0.75, 0.2, 0.6]) * (1.0 / 256) / 2.0  # Courant numbers up to 0.9 in x
+    out, _, _, cnt = _run(claw, prob, q0, a0, True, dts=dts)
+    assert cnt[1] == 0
+    ref, _ = oracle.advance_fixed(prob, q0, a0, dts)
+    assert rel_linf(out, ref)[0] <= TOL["f32"]
+
+
+def test_fused3_path_choice(claw):
+    # the 256^3 FP32 layered medium (268 MB of state) takes the fused x and y
+    # step by itself and matches the split sweeps; a small state, rows of other
+    # lengths and other x boundaries keep the split sweeps
+    prob, q0, aux = inputs.acoustics3d_layers(n=256, dtype="f32", nsteps=3, seed=3)
+    prob = dict(prob)
+    out, _, _, cnt = _run(claw, prob, q0, aux, None, steps=3)
+    assert cnt[0] >= 1 and cnt[1] == 0 and cnt[2] >= 1
+    split, _, _, cnt2 = _run(claw, prob, q0, aux, False, steps=3)
+    assert cnt2[1] >= 1
+    assert rel_linf(out, split)[0] <= SPLIT_TOL["f32"]
+    small, qs, as_ = _prob((256, 16, 8), True, "f32", ("wall", "wall"), ("wall", "wall"), seed=1)
+    assert _run(claw, small, qs, as_, None, steps=2)[3][1] >= 1
+    for n, bc in (((200, 9, 4), "extrap"), ((256, 9, 4), "wall"), ((256, 9, 4), "periodic")):
+        p, q1, a1 = _prob(n, True, "f32", ("wall", "wall"), ("wall", "wall"), seed=2)
+        p["bc_lo"] = (bc,) + p["bc_lo"][1:]
+        p["bc_hi"] = (bc,) + p["bc_hi"][1:]
+        out1, _, _, c1 = _run(claw, p, q1, a1, True, steps=3)
+        assert c1[1] >= 1  # the flag asks for the fused step; these grids keep the sweeps
+        assert rel_linf(out1, oracle.advance(p, q1, a1, 3)["q"])[0] <= TOL["f32"]
