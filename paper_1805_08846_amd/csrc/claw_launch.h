@@ -37,7 +37,8 @@ hipError_t launch_step2d(const FusedArgs<R>& F, hipStream_t s);
 // exactly 64 CPL cells (256 FP32, 128 FP64) with extrapolation at both x ends;
 // the z sweep follows as a column sweep.  a: the x-sweep arguments; ny, nz
 // and the y boundaries complete the grid; chunk: rows of one z plane per
-// workgroup.  The result goes to buffer cur + 1, as the 2D step's does.
+// workgroup.  The result goes to buffer cur + 1, as the 2D step's does.  The
+// kernel opens the trial (it decides the previous one, as a first sweep does).
 template <typename R>
 struct Fused3Args {
     SweepArgs<R> a;

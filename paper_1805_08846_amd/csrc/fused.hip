@@ -303,6 +303,10 @@ void k_step2d(FusedArgs<R> F) {
 // LDS rows; the x velocity of Q* and the z velocity go straight to the
 // destination (the y sweep leaves both unchanged).  Phase B marches p and v
 // down the columns.  Same arithmetic per interface as the x and y sweeps.
+// Step control as in the split sweeps: this kernel opens the trial (every
+// workgroup decides the previous trial, workgroup (0, 0) records the state)
+// and the z sweep closes it (it clears the other parity's speed slots), so a
+// trial needs no opening kernel of its own.
 template <typename R, int SYS, int CPL, int LIMK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FUSED_WPE)))
 void k_step_xy3(Fused3Args<R> F) {
@@ -317,8 +321,13 @@ void k_step_xy3(Fused3Args<R> F) {
     __shared__ R ring[2][FR][NL][NX];
 
     const SweepArgs<R>& a = F.a;
-    const StepState& S = a.ctrl->st[a.parity];
-    if (S.done) return;  // the whole grid skips
+    StepState S;
+    decide(a.ctrl, a.parity ^ 1, sizeof(R) == 4, S);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+        S.pending = S.done ? 0 : 1;
+        a.ctrl->st[a.parity] = S;
+    }
+    if (wave_uniform(S.done)) return;  // the whole grid skips
     const int cur = wave_uniform(S.cur);
     const R nux = wave_uniform(state_nu<R>(S, 0)), nuy = wave_uniform(state_nu<R>(S, 1));
     const R* __restrict__ src = pick_buf(a, cur);

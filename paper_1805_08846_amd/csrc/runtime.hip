@@ -378,13 +378,12 @@ claw_status enqueue_trial(claw_solver* h, hipStream_t s, hipEvent_t* ev) {
         h->parity ^= 1;
         return CLAW_OK;
     }
-    if (h->fused3) {
-        HIP_TRY(launch_open(h->ctrl, h->parity, h->fp32, s));
+    if (h->fused3) {  // opened by the x and y kernel, closed by the z sweep
         if (ev) HIP_TRY(hipEventRecord(ev[0], s));
         if (h->fp32) HIP_TRY(launch_step_xy3<float>(fused3_args<float>(h, h->parity), h->sys, s));
         else HIP_TRY(launch_step_xy3<double>(fused3_args<double>(h, h->parity), h->sys, s));
         if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-        HIP_TRY(enqueue_sweep(h, 2, 1, 2, false, h->parity, false, false, s));
+        HIP_TRY(enqueue_sweep(h, 2, 1, 2, false, h->parity, false, true, s));
         if (ev) HIP_TRY(hipEventRecord(ev[2], s));
         h->parity ^= 1;
         return CLAW_OK;
