@@ -378,6 +378,11 @@ def bench_ac3d(args, torch, claw, inputs):
                      "kernel": names[dom], "alg_bytes_per_launch": alg_bytes, "avg_launch_us": dom_s * 1e6},
         "kernel_avg_us": avg_us, "rejected_trials": nrej,
         "path": "fused x and y step, then the z sweep" if fused else "x, y and z sweeps",
+        # the metric's whole-step figure: the method's bytes per cell-update
+        # (three sweeps of 40 B in FP32) at the measured rate, against 8 TB/s;
+        # the fused path moves two sweeps' worth, so this can exceed what its
+        # kernels move (the roofline above charges each launch its own bytes)
+        "hbm_frac_whole_step": (ncell * steps / elapsed) * 3 * alg_bytes / ncell / (HBM_PEAK_GBPS * 1e9),
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, q0, args.cpu_steps or 10, aux)
