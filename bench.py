@@ -25,6 +25,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -462,6 +463,32 @@ def bench_dpsp(args, torch, claw, inputs):
     }
 
 
+def run_record(torch):
+    """Provenance of a run for the JSONL record: time, command, sources (git
+    commit where a checkout is present, and the kernel classes' source
+    hashes), host CPU, GPU and software versions."""
+    sha = None
+    try:
+        sha = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True,
+                             timeout=10).stdout.strip() or None
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return {"time_utc": time.strftime("%Y-%m-%dT%H:%M:%SZ", time.gmtime()), "argv": sys.argv[1:],
+            "git_sha": sha, "source_hashes": {k: kernel_source_hash(k) for k in ("step2d", "x_sweep")},
+            "host": host_cpu(), "gpu": torch.cuda.get_device_name(0), "torch": torch.__version__,
+            "hip": getattr(torch.version, "hip", None)}
+
+
+def emit(line, args, torch):
+    """Prints the result line; with --record (or CLAW_RECORD) also appends it,
+    with the run's provenance, to a JSONL file."""
+    print(json.dumps(line), flush=True)
+    path = args.record or os.environ.get("CLAW_RECORD")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(dict(line, record=run_record(torch))) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -484,6 +511,8 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the 2048^2 run that follows the headline size (profiling runs)")
     ap.add_argument("--traffic-file", default=None)
+    ap.add_argument("--record", default=None,
+                    help="append the result line with its provenance to this JSONL file (default: $CLAW_RECORD)")
     ap.add_argument("--workload", default="sw2048", choices=["sw2048", "ensemble", "learned", "plugin", "dpsp", "ac3d", "sizes"])
     ap.add_argument("--fused-step", dest="fused_step", action="store_const", const=True, default=None,
                     help="one fused kernel per 2D step (CLAW_FLAG_FUSED_STEP) at every size")
@@ -510,22 +539,22 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.workload == "ensemble":
-        print(json.dumps(bench_ensemble(args, torch, claw, inputs)), flush=True)
+        emit(bench_ensemble(args, torch, claw, inputs), args, torch)
         return
     if args.workload == "learned":
-        print(json.dumps(bench_learned(args, torch, claw, inputs)), flush=True)
+        emit(bench_learned(args, torch, claw, inputs), args, torch)
         return
     if args.workload == "plugin":
-        print(json.dumps(bench_plugin(args, torch, claw, inputs)), flush=True)
+        emit(bench_plugin(args, torch, claw, inputs), args, torch)
         return
     if args.workload == "sizes":
-        print(json.dumps(bench_sizes(args, torch, claw, inputs)), flush=True)
+        emit(bench_sizes(args, torch, claw, inputs), args, torch)
         return
     if args.workload == "ac3d":
-        print(json.dumps(bench_ac3d(args, torch, claw, inputs)), flush=True)
+        emit(bench_ac3d(args, torch, claw, inputs), args, torch)
         return
     if args.workload == "dpsp":
-        print(json.dumps(bench_dpsp(args, torch, claw, inputs)), flush=True)
+        emit(bench_dpsp(args, torch, claw, inputs), args, torch)
         return
 
     n = args.n
@@ -558,7 +587,7 @@ def main():
         csteps = args.cpu_steps if args.cpu_steps else max(2, int(round(1e9 / (n * n))))
         print(f"# cpu baseline: oracle on {csteps} steps of {n}^2", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(prob, q0, csteps)
-    print(json.dumps(line), flush=True)
+    emit(line, args, torch)
 
 
 def bench_grid(args, torch, claw, inputs, n, steps, warmup, headline):

@@ -49,3 +49,35 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_run_record_appends_line_with_provenance(tmp_path, capsys):
+    # the JSONL record: the printed line plus time, command, source hashes and
+    # host; a stand-in for torch supplies the GPU name off the GPU
+    sys.path.insert(0, ROOT)
+    import bench
+
+    class _Cuda:
+        @staticmethod
+        def get_device_name(i):
+            return "stand-in GPU"
+
+    class _Torch:
+        cuda = _Cuda()
+        __version__ = "0"
+
+        class version:
+            hip = None
+
+    class _Args:
+        record = str(tmp_path / "runs.jsonl")
+
+    line = {"metric": "m", "value": 1.0}
+    bench.emit(line, _Args(), _Torch())
+    bench.emit(dict(line, value=2.0), _Args(), _Torch())
+    assert json.loads(capsys.readouterr().out.splitlines()[0]) == line
+    recs = [json.loads(ln) for ln in open(_Args.record)]
+    assert [r["value"] for r in recs] == [1.0, 2.0]
+    rec = recs[0]["record"]
+    assert rec["gpu"] == "stand-in GPU" and rec["host"]["logical_cpus"] >= 1
+    assert set(rec["source_hashes"]) == {"step2d", "x_sweep"} and all(len(v) == 16 for v in rec["source_hashes"].values())
