@@ -19,16 +19,17 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# (nx, ny, nz or None, aux, dtype)
-SWEEPS = [(256, 67, None, False, "f32"), (128, 45, None, False, "f64"), (256, 13, 7, True, "f32"),
-          (128, 9, 5, True, "f64"), (256, 5, 3, False, "f32"), (256, 1, None, False, "f32")]
+# (nx, ny, nz or None, aux, dtype, limiter)
+SWEEPS = [(256, 67, None, False, "f32", "mc"), (128, 45, None, False, "f64", "mc"), (256, 13, 7, True, "f32", "mc"),
+          (128, 9, 5, True, "f64", "mc"), (256, 5, 3, False, "f32", "mc"), (256, 1, None, False, "f32", "mc"),
+          (256, 9, 4, True, "f32", "superbee"), (128, 7, None, False, "f64", "minmod")]
 
 
 def seed(*case):
     return zlib.crc32(repr(case).encode())
 
 
-def sweep_case(nx, ny, nz, aux, dtype):
+def sweep_case(nx, ny, nz, aux, dtype, limiter):
     """Problem, initial state and coefficients of one single-sweep case."""
     from paper_1805_08846_amd import inputs
     rng = np.random.default_rng(seed(nx, ny, nz, aux, dtype))
@@ -43,6 +44,7 @@ def sweep_case(nx, ny, nz, aux, dtype):
         shape, meqn = (nz, ny, nx), 4
     prob["bc_lo"] = ("extrap",) + tuple(rng.choice(bcs) for _ in range(2))
     prob["bc_hi"] = ("extrap",) + tuple(rng.choice(bcs) for _ in range(2))
+    prob["limiter"] = limiter
     q0 = inputs.round_to(rng.uniform(-1, 1, (meqn,) + shape), dtype)
     a0 = inputs.round_to(rng.uniform(0.5, 2.0, (2,) + shape), dtype) if aux else None
     cmax = 2.0 if aux else (2.9 / 1.7) ** 0.5
@@ -79,7 +81,7 @@ def run(claw):
     out = {}
     for case in SWEEPS:
         prob, q0, a0, dt = sweep_case(*case)
-        dtype = case[-1]
+        dtype = case[4]
         q = dev(q0, dtype)
         s = claw.Solver(prob, q, None if a0 is None else dev(a0, dtype))
         sm = s.sweep(0, dt)

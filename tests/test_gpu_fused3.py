@@ -121,3 +121,27 @@ def test_fused3_path_choice(claw):
         out1, _, _, c1 = _run(claw, p, q1, a1, True, steps=3)
         assert c1[1] >= 1  # the flag asks for the fused step; these grids keep the sweeps
         assert rel_linf(out1, oracle.advance(p, q1, a1, 3)["q"])[0] <= TOL["f32"]
+
+
+@pytest.mark.parametrize("limiter,aux,dtype", [("minmod", True, "f32"), ("superbee", False, "f64"),
+                                               ("vanleer", True, "f64")])
+def test_fused3_other_limiters(claw, limiter, aux, dtype):
+    # the kernels that read the limiter from the arguments
+    nx = 256 if dtype == "f32" else 128
+    prob, q0, a0 = _prob((nx, 13, 4), aux, dtype, ("wall", "periodic"), ("extrap", "wall"), seed=9)
+    prob["limiter"] = limiter
+    out, t, nrej, cnt = _run(claw, prob, q0, a0, True, steps=10)
+    assert cnt[1] == 0
+    ref = oracle.advance(prob, q0, a0, 10)
+    assert rel_linf(out, ref["q"])[0] <= TOL[dtype]
+    assert nrej == ref["nreject"]
+    split = _run(claw, prob, q0, a0, False, steps=10)[0]
+    assert rel_linf(out, split)[0] <= SPLIT_TOL[dtype]
+
+
+def test_fused3_not_taken_with_strang_splitting(claw):
+    prob, q0, a0 = _prob((256, 9, 4), True, "f32", ("wall", "wall"), ("wall", "wall"), seed=4)
+    prob["splitting"] = "strang"
+    out, _, _, cnt = _run(claw, prob, q0, a0, True, steps=4)
+    assert cnt[1] >= 1  # Strang splitting keeps the sweeps (x/2 y/2 z y/2 x/2)
+    assert rel_linf(out, oracle.advance(prob, q0, a0, 4)["q"])[0] <= TOL["f32"]

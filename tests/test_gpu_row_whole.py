@@ -44,7 +44,7 @@ def test_whole_row_sweep_matches_oracle(results, case):
     name = "sweep_" + "_".join(str(c) for c in case)
     ref, sm_ref = oracle.sweep(prob, q0, a0, 0, dt)
     err, per = rel_linf(results[name].reshape(ref.shape), ref)
-    f64 = case[-1] == "f64"
+    f64 = case[4] == "f64"
     assert err <= (1e-13 if f64 else 2e-6), per
     assert results[name + "_smax"][0] == pytest.approx(sm_ref, rel=1e-14 if f64 else 1e-6)
 
