@@ -39,7 +39,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 
 
 # the sources each kernel class is built from (the shared headers and its own file)
-SOURCE_FILES = {"step2d": ("fused.hip", "sweep_body.h", "claw_device.h", "plugins.h"),
+SOURCE_FILES = {"step2d": ("fused.hip", "step2d_body.inc", "sweep_body.h", "claw_device.h", "plugins.h"),
                 "sweeps": ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h")}
 
 
@@ -142,33 +142,47 @@ def achievable_bandwidth(torch, claw, nbytes=1 << 30, reps=10):
 
 def bench_ensemble(args, torch, claw, inputs):
     """Batched ensemble of 256 shallow-water instances (sides U{128..1024},
-    Gaussian humps, walls, FP32) for `steps` accepted steps each, against the
-    same instances advanced one after another through the single-grid path.
-    Results are bitwise identical between the two (tested), so the L1 error is
-    equal by construction and the speedup is T_single / T_batch."""
+    Gaussian humps, walls, FP32) for `steps` accepted steps each.  The batch
+    runs the fused 2D step (one opening and one fused launch per trial for all
+    instances; --split-step: the batched x and y sweeps); it is compared with
+    the batch on the other step and with the same instances advanced one
+    after another through the single-grid path on the library's default step
+    (the x and y sweeps at these sizes).  A batch equals its single grids on
+    the same step bit for bit (tested); the fused and the split step agree to
+    FP32 rounding, so the L1 error is the same and the speedups are ratios of
+    times."""
     steps = args.steps if args.steps_given else 500
     members = inputs.sw_ensemble(count=args.count, seed=0, dtype="f32", nsteps=steps)
     cells = sum(p["n"][0] * p["n"][1] for p, _ in members)
-    qs = [torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous() for _, q0 in members]
-    b = claw.BatchSolver([p for p, _ in members], qs)
-    tuned = b.tune(os.environ.get("CLAW_AUTOTUNE_CACHE"))
-    print(f"# ensemble: {len(members)} instances, {cells} cells; tuned {tuned}", file=sys.stderr, flush=True)
-    # one untimed step, as for the single-grid runs below: both time steps 2..steps+1
-    # (the autotuning above has warmed the GPU)
-    b.advance(args.warmup if args.warmup_given else 1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, rej = b.advance(steps)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    b.close()
-    del qs
+    warm = args.warmup if args.warmup_given else 1
+
+    def run_batch(fused):
+        probs = [dict(p, fused_step=True if fused else None) for p, _ in members]
+        qs = [torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous() for _, q0 in members]
+        b = claw.BatchSolver(probs, qs)
+        tuned = b.tune(os.environ.get("CLAW_AUTOTUNE_CACHE"))
+        print(f"# ensemble ({'fused' if fused else 'split'}): {len(members)} instances, {cells} cells; "
+              f"tuned {tuned}", file=sys.stderr, flush=True)
+        # untimed steps, as for the single-grid runs below: all time steps
+        # warm+1 .. warm+steps (the autotuning above has warmed the GPU)
+        b.advance(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rej = b.advance(steps)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        b.close()
+        return t, tuned, int(sum(rej))
+
+    fused = args.fused_step is not False
+    t_batch, tuned, nrej = run_batch(fused)
+    t_other, tuned_other, _ = run_batch(not fused)
     # the same instances one after another through the single-grid path
     t_single = 0.0
     for p, q0 in members:
         q = torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous()
         s = claw.Solver(p, q)
-        s.advance(1)
+        s.advance(warm)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         s.advance(steps)
@@ -182,7 +196,7 @@ def bench_ensemble(args, torch, claw, inputs):
         "unit": "Gcell-updates/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": args.warmup if args.warmup_given else 1,
+        "warmup": warm,
         "ms_per_step": t_batch / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
@@ -192,12 +206,15 @@ def bench_ensemble(args, torch, claw, inputs):
         "config": {"workload": "batched 2D shallow-water ensemble, walls, MC, CFL 0.9, adaptive dt per "
                                "instance", "instances": len(members), "cells": cells,
                    "parallelism": "single GPU"},
+        "step": "fused 2D step" if fused else "x and y sweeps",
         "tuned": tuned,
-        "rejected_trials": int(sum(rej)),
-        "single_grid_seconds": t_single,
+        "rejected_trials": nrej,
         "batch_seconds": t_batch,
-        "speedup_vs_single_grid": t_single / t_batch,
+        ("split" if fused else "fused") + "_batch": {"value": cells * steps / t_other / 1e9, "seconds": t_other,
+                                                     "tuned": tuned_other},
+        "single_grid_seconds": t_single,
         "single_grid_value": cells * steps / t_single / 1e9,
+        "speedup_vs_single_grid": t_single / t_batch,
     }
 
 

@@ -276,7 +276,11 @@ claw_status claw_destroy(claw_solver* h);
  * step count).  Every sweep of every instance runs in one launch per sweep
  * direction; a table maps each workgroup to (instance, block), and the
  * whole multi-step run replays a captured HIP graph.  Each instance's result is
- * bitwise the single-grid result.
+ * bitwise the single-grid result on the same step.  With CLAW_FLAG_FUSED_STEP
+ * on every descriptor the batch runs the fused 2D step instead: per trial one
+ * opening launch (one thread per instance) and one fused launch for all
+ * instances.  Descriptors carry no other flag, and all carry the same one
+ * (CLAW_E_INVALID otherwise).
  * ------------------------------------------------------------------------- */
 typedef struct claw_batch claw_batch; /* opaque */
 
@@ -292,14 +296,16 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
 /* Autotuner: times state-preserving trial steps (dt = 0) for each candidate
  * column chunk {16, 32, 64, 128} x block schedule (0 largest instances
  * first, 1 round-robin) x rows each row-sweep wavefront takes in turn
- * {2, 4, 8}, keeps the fastest, and records it in the JSON cache file
+ * {2, 4, 8} (fused batches: rows per fused workgroup {16, 24, 32, 48, 64} x
+ * schedule), keeps the fastest, and records it in the JSON cache file
  * cache_path (may be NULL) keyed by arch, dtype, system, instance count and
  * total-cell bucket; a cached key is used without timing.  Outputs may be
  * NULL.  Synchronises.
  * Defined by: section 5.2 (block shapes chosen for the hardware). */
 claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chunk, int32_t* schedule,
                             int32_t* rows_per_wave, double* us_per_step);
-/* Fixes the tile choice by hand (chunk >= 8; schedule 0 or 1; rows_per_wave
+/* Fixes the tile choice by hand (chunk >= 8, fused batches >= 16: their rows
+ * per fused workgroup; schedule 0 or 1; rows_per_wave
  * 2, 4 or 8; the default after claw_batch_create is 32, 0, 8).
  * Defined by: section 5.2 (block shapes). */
 claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule, int32_t rows_per_wave);

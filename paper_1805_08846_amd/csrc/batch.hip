@@ -53,6 +53,15 @@ __global__ void k_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, doubl
             clear_speeds(c, q);
             c->nonphys[q] = 0;
             break;
+        case BOP_OPEN: {  // a fused trial of parity q opens: decide copy q ^ 1 into copy q
+            StepState N;
+            decide(c, q ^ 1, fp32 != 0, N);
+            N.pending = N.done ? 0 : 1;
+            c->st[q] = N;
+            clear_speeds(c, q);
+            c->nonphys[q] = 0;
+            break;
+        }
         case BOP_BEGIN_FIXED:  // trial step dt in mode `mode`
             set_trial_dt(c, s, dt);
             s.mode = mode;

@@ -76,7 +76,21 @@ struct BatchLaunch {
     int limiter;  // the limiter every instance uses, or -1 if they differ
     int rpw;      // rows per row-sweep wavefront (2, 4 or 8; the row table is built for it)
 };
-enum { BOP_COMMIT = 0, BOP_ZERO_SPEEDS = 1, BOP_BEGIN_FIXED = 2, BOP_BEGIN_ADAPT = 3 };
+// Batched fused 2D steps (fused.hip): blocks[i] maps workgroup i to an
+// instance, a strip of columns (x) and a chunk of rows (y); args holds each
+// instance's fused-step arguments.
+template <typename R>
+struct BatchFusedLaunch {
+    const BatchBlock* blocks;
+    const FusedArgs<R>* args;
+    int parity;
+    int limiter;  // the limiter every instance uses, or -1 if they differ
+};
+template <typename R>
+hipError_t launch_batch_step2d(const BatchFusedLaunch<R>& L, int nblocks, hipStream_t s);
+// BOP_OPEN: decide the previous trial into copy q and clear copy q's speed
+// slots (what the single-grid fused step's opening kernel does).
+enum { BOP_COMMIT = 0, BOP_ZERO_SPEEDS = 1, BOP_BEGIN_FIXED = 2, BOP_BEGIN_ADAPT = 3, BOP_OPEN = 4 };
 template <typename R>
 hipError_t launch_batch_sweep(const BatchLaunch<R>& L, int sys, int dir, int nblocks, bool speeds,
                               hipStream_t s);

@@ -1051,12 +1051,13 @@ struct claw_batch {
     hipStream_t stream;
     hipStream_t cap_stream;
     char* ws;
-    size_t off_ptrs, off_args, off_rows, off_cols, off_bufs;
+    size_t off_ptrs, off_args, off_rows, off_cols, off_fused, off_fargs, off_bufs;
     size_t args_stride;  // bytes per SweepArgs of the dtype
+    bool fused;          // one fused step kernel per trial for every instance (fused.hip)
     Ctrl** ctrl_ptrs;    // device array of the instances' control blocks
     std::vector<Ctrl*> ctrl;
     std::vector<std::array<void*, 3>> buf;
-    int n_row_blocks, n_col_blocks, max_col_blocks;
+    int n_row_blocks, n_col_blocks, max_col_blocks, n_fused_blocks, max_fused_blocks;
     int chunk, schedule, rpw;
     double tuned_us;
     bool have_dt_next;
@@ -1070,9 +1071,13 @@ namespace {
 constexpr int kBatchChunkMin = 8;
 const int kTuneChunks[] = {16, 32, 64, 128};
 const int kTuneRpw[] = {2, 4, 8};
+// fused batches: rows per fused workgroup (the column chunk of their speed passes too)
+constexpr int kFusedChunkMin = 16;
+const int kTuneFusedChunks[] = {16, 24, 32, 48, 64};
 
 int inst_row_blocks(const claw_desc& d, bool fp32);
 int inst_col_blocks(const claw_desc& d, int chunk);
+int inst_fused_blocks(const claw_desc& d, bool fp32, int chunk);
 
 claw_status batch_validate(const claw_desc* d, int32_t count) {
     if (!d || count < 1 || count > 65535) return fail(CLAW_E_INVALID, "need 1..65535 descriptors");
@@ -1082,25 +1087,29 @@ claw_status batch_validate(const claw_desc* d, int32_t count) {
         if (d[i].riemann != CLAW_RP_SHALLOW_WATER || d[i].ndim != 2)
             return fail(CLAW_E_UNSUPPORTED, "batches hold 2D shallow-water instances (instance %d)", i);
         if (d[i].dtype != d[0].dtype) return fail(CLAW_E_INVALID, "all instances need the same dtype");
-        if (d[i].flags) return fail(CLAW_E_UNSUPPORTED, "batches run the default split step (instance %d)", i);
+        if (d[i].flags & ~(CLAW_FLAG_FUSED_STEP | CLAW_FLAG_SPLIT_STEP))
+            return fail(CLAW_E_UNSUPPORTED, "batches run the split or the fused 2D step (instance %d)", i);
+        if ((d[i].flags & CLAW_FLAG_FUSED_STEP) != (d[0].flags & CLAW_FLAG_FUSED_STEP))
+            return fail(CLAW_E_INVALID, "all instances need the same step (instance %d)", i);
     }
     // a batched sweep is one 1-D launch of 256-thread workgroups, and a
     // dispatch counts its work-items in 32 bits: at most 2^24 - 1 workgroups
-    int64_t rows = 0, cols = 0;
+    int64_t rows = 0, cols = 0, fused = 0;
     for (int i = 0; i < count; ++i) {
         rows += inst_row_blocks(d[i], d[0].dtype == CLAW_FP32);
         cols += inst_col_blocks(d[i], kBatchChunkMin);
+        if (d[0].flags & CLAW_FLAG_FUSED_STEP) fused += inst_fused_blocks(d[i], d[0].dtype == CLAW_FP32, kFusedChunkMin);
     }
     const int64_t max_blocks = ((int64_t)1 << 24) - 1;
-    if (rows > max_blocks || cols > max_blocks)
+    if (rows > max_blocks || cols > max_blocks || fused > max_blocks)
         return fail(CLAW_E_UNSUPPORTED, "batch too large for one launch (%lld row blocks, %lld column blocks)",
                     (long long)rows, (long long)cols);
     return CLAW_OK;
 }
 
 struct BatchPlan {
-    size_t ctrl_stride, off_ptrs, off_args, off_rows, off_cols, off_bufs, total, args_stride;
-    int max_row_blocks, max_col_blocks;
+    size_t ctrl_stride, off_ptrs, off_args, off_rows, off_cols, off_fused, off_fargs, off_bufs, total, args_stride;
+    int max_row_blocks, max_col_blocks, max_fused_blocks;
 };
 
 int row_cpl(bool fp32) { return fp32 ? 4 : 2; }
@@ -1114,6 +1123,12 @@ int inst_col_blocks(const claw_desc& d, int chunk) {
     const int64_t c = chunk < d.n[1] ? chunk : d.n[1];
     return (int)(sg * ((d.n[1] + c - 1) / c));
 }
+// fused step: strips of 62 CPL columns times chunks of rows
+int inst_fused_blocks(const claw_desc& d, bool fp32, int chunk) {
+    const int64_t W = 62 * row_cpl(fp32);
+    const int64_t c = chunk < d.n[1] ? chunk : d.n[1];
+    return (int)(((d.n[0] + W - 1) / W) * ((d.n[1] + c - 1) / c));
+}
 
 BatchPlan batch_plan(const claw_desc* d, int count) {
     BatchPlan p;
@@ -1125,12 +1140,18 @@ BatchPlan batch_plan(const claw_desc* d, int count) {
     p.off_rows = p.off_args + round_up(p.args_stride * 2 * count);
     p.max_row_blocks = 0;
     p.max_col_blocks = 0;
+    p.max_fused_blocks = 0;
+    const bool fused = (d[0].flags & CLAW_FLAG_FUSED_STEP) != 0;
     for (int i = 0; i < count; ++i) {
         p.max_row_blocks += inst_row_blocks(d[i], fp32);
         p.max_col_blocks += inst_col_blocks(d[i], kBatchChunkMin);
+        if (fused) p.max_fused_blocks += inst_fused_blocks(d[i], fp32, kFusedChunkMin);
     }
     p.off_cols = p.off_rows + round_up(sizeof(BatchBlock) * p.max_row_blocks);
-    p.off_bufs = p.off_cols + round_up(sizeof(BatchBlock) * p.max_col_blocks);
+    p.off_fused = p.off_cols + round_up(sizeof(BatchBlock) * p.max_col_blocks);
+    p.off_fargs = p.off_fused + round_up(sizeof(BatchBlock) * p.max_fused_blocks);
+    p.off_bufs = p.off_fargs + (fused ? round_up((fp32 ? sizeof(FusedArgs<float>) : sizeof(FusedArgs<double>)) *
+                                                 count) : 0);
     p.total = p.off_bufs;
     for (int i = 0; i < count; ++i) p.total += 2 * round_up(make_plan(&d[i]).state_bytes);
     return p;
@@ -1146,7 +1167,7 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return b->plan[x].ncell > b->plan[y].ncell;
     });
-    std::vector<std::vector<BatchBlock>> rows(n), cols(n);
+    std::vector<std::vector<BatchBlock>> rows(n), cols(n), fus(n);
     const int P = 62 * row_cpl(b->fp32);
     for (int i = 0; i < n; ++i) {
         const claw_desc& d = b->d[i];
@@ -1160,6 +1181,11 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
         const int nch = (int)((d.n[1] + c - 1) / c);
         for (int y = 0; y < nch; ++y)
             for (int x = 0; x < sg; ++x) cols[i].push_back({i, x, y, 0});
+        if (b->fused) {  // the fused step's chunks are the columns' chunks
+            const int strips = (int)((d.n[0] + 62 * row_cpl(b->fp32) - 1) / (62 * row_cpl(b->fp32)));
+            for (int y = 0; y < nch; ++y)
+                for (int x = 0; x < strips; ++x) fus[i].push_back({i, x, y, 0});
+        }
     }
     auto flatten = [&](std::vector<std::vector<BatchBlock>>& per) {
         std::vector<BatchBlock> out;
@@ -1180,8 +1206,9 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
         }
         return out;
     };
-    std::vector<BatchBlock> rt = flatten(rows), ct = flatten(cols);
+    std::vector<BatchBlock> rt = flatten(rows), ct = flatten(cols), ft = flatten(fus);
     if ((int)ct.size() > b->max_col_blocks) return fail(CLAW_E_INVALID, "column chunk too small");
+    if ((int)ft.size() > b->max_fused_blocks) return fail(CLAW_E_INVALID, "fused chunk too small");
     // per-instance arguments (x: cur -> cur+1, y: cur+1 -> cur+2)
     std::vector<char> args(b->args_stride * 2 * n);
     for (int i = 0; i < n; ++i) {
@@ -1200,6 +1227,36 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
         }
     }
     HIP_TRY(hipMemcpyAsync(b->ws + b->off_args, args.data(), args.size(), hipMemcpyHostToDevice, b->stream));
+    if (b->fused) {  // per-instance fused-step arguments: x sweep from cur to cur + 1, rows per chunk
+        const size_t fs = b->fp32 ? sizeof(FusedArgs<float>) : sizeof(FusedArgs<double>);
+        std::vector<char> fargs(fs * n);
+        for (int i = 0; i < n; ++i) {
+            void* bufs[3] = {b->buf[i][0], b->buf[i][1], b->buf[i][2]};
+            const int c = chunk < b->d[i].n[1] ? chunk : (int)b->d[i].n[1];
+            if (b->fp32) {
+                FusedArgs<float> F;
+                memset(&F, 0, sizeof F);
+                F.a = grid_args<float>(b->d[i], SYS_SW, b->plan[i].ncell, bufs, nullptr, b->ctrl[i], 0, 0, 1, 0);
+                F.ny = (int32_t)b->d[i].n[1];
+                F.bcy_lo = b->d[i].bc_lo[1];
+                F.bcy_hi = b->d[i].bc_hi[1];
+                F.chunk = c;
+                memcpy(fargs.data() + fs * i, &F, sizeof F);
+            } else {
+                FusedArgs<double> F;
+                memset(&F, 0, sizeof F);
+                F.a = grid_args<double>(b->d[i], SYS_SW, b->plan[i].ncell, bufs, nullptr, b->ctrl[i], 0, 0, 1, 0);
+                F.ny = (int32_t)b->d[i].n[1];
+                F.bcy_lo = b->d[i].bc_lo[1];
+                F.bcy_hi = b->d[i].bc_hi[1];
+                F.chunk = c;
+                memcpy(fargs.data() + fs * i, &F, sizeof F);
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(b->ws + b->off_fargs, fargs.data(), fargs.size(), hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipMemcpyAsync(b->ws + b->off_fused, ft.data(), ft.size() * sizeof(BatchBlock),
+                               hipMemcpyHostToDevice, b->stream));
+    }
     HIP_TRY(hipMemcpyAsync(b->ws + b->off_rows, rt.data(), rt.size() * sizeof(BatchBlock), hipMemcpyHostToDevice,
                            b->stream));
     HIP_TRY(hipMemcpyAsync(b->ws + b->off_cols, ct.data(), ct.size() * sizeof(BatchBlock), hipMemcpyHostToDevice,
@@ -1207,6 +1264,7 @@ claw_status batch_tables(claw_batch* b, int chunk, int schedule, int rpw) {
     HIP_TRY(hipStreamSynchronize(b->stream));
     b->n_row_blocks = (int)rt.size();
     b->n_col_blocks = (int)ct.size();
+    b->n_fused_blocks = (int)ft.size();
     b->chunk = chunk;
     b->schedule = schedule;
     b->rpw = rpw;
@@ -1239,7 +1297,30 @@ hipError_t batch_sweep_any(claw_batch* b, int dir, bool speeds, int parity, bool
                    : batch_sweep<double>(b, dir, speeds, parity, first, last, s);
 }
 
+template <typename R>
+hipError_t batch_step2d(claw_batch* b, hipStream_t s) {
+    BatchFusedLaunch<R> L;
+    L.blocks = (const BatchBlock*)(b->ws + b->off_fused);
+    L.args = (const FusedArgs<R>*)(b->ws + b->off_fargs);
+    L.parity = b->parity;
+    L.limiter = b->d[0].limiter;
+    for (const claw_desc& d : b->d)
+        if (d.limiter != L.limiter) L.limiter = -1;
+    return launch_batch_step2d<R>(L, b->n_fused_blocks, s);
+}
+
+// Result buffer offset of a trial: the fused step writes cur + 1, the x and y
+// sweeps cur + 2.
+int batch_result_off(const claw_batch* b) { return b->fused ? 1 : 2; }
+
 claw_status batch_trial(claw_batch* b, hipStream_t s) {
+    if (b->fused) {  // every instance's opening (one thread each), then one fused launch
+        HIP_TRY(launch_batch_ctrl(b->ctrl_ptrs, b->count, BOP_OPEN, b->parity, 0.0, 0, batch_result_off(b), 0,
+                                  b->fp32, s));
+        HIP_TRY(b->fp32 ? batch_step2d<float>(b, s) : batch_step2d<double>(b, s));
+        b->parity ^= 1;
+        return CLAW_OK;
+    }
     HIP_TRY(batch_sweep_any(b, 0, false, b->parity, true, false, s));
     HIP_TRY(batch_sweep_any(b, 1, false, b->parity, false, true, s));
     b->parity ^= 1;
@@ -1247,8 +1328,8 @@ claw_status batch_trial(claw_batch* b, hipStream_t s) {
 }
 
 claw_status batch_ctrl(claw_batch* b, int op, double dt = 0, int mode = 0, long long nsteps = 0) {
-    HIP_TRY(launch_batch_ctrl(b->ctrl_ptrs, b->count, op, b->parity ^ 1, dt, mode, 2, nsteps, b->fp32,
-                              b->stream));
+    HIP_TRY(launch_batch_ctrl(b->ctrl_ptrs, b->count, op, b->parity ^ 1, dt, mode, batch_result_off(b), nsteps,
+                              b->fp32, b->stream));
     return CLAW_OK;
 }
 
@@ -1290,7 +1371,8 @@ std::string tune_key(const claw_batch* b) {
     int lg = 0;
     while ((int64_t(1) << (lg + 1)) <= cells) ++lg;
     char key[128];
-    snprintf(key, sizeof key, "gfx950/%s/sw/n%d/cells2^%d", b->fp32 ? "f32" : "f64", b->count, lg);
+    snprintf(key, sizeof key, "gfx950/%s/sw%s/n%d/cells2^%d", b->fp32 ? "f32" : "f64", b->fused ? "-fused" : "",
+             b->count, lg);
     return key;
 }
 
@@ -1378,7 +1460,11 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
     b->off_args = bp.off_args;
     b->off_rows = bp.off_rows;
     b->off_cols = bp.off_cols;
+    b->off_fused = bp.off_fused;
+    b->off_fargs = bp.off_fargs;
     b->off_bufs = bp.off_bufs;
+    b->fused = (descs[0].flags & CLAW_FLAG_FUSED_STEP) != 0;
+    b->max_fused_blocks = bp.max_fused_blocks;
     b->args_stride = bp.args_stride;
     b->max_col_blocks = bp.max_col_blocks;
     b->ctrl_ptrs = (Ctrl**)(b->ws + bp.off_ptrs);
@@ -1408,7 +1494,7 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
         double dx[3];
         for (int k = 0; k < 3; ++k) dx[k] = k < 2 ? (descs[i].upper[k] - descs[i].lower[k]) / (double)descs[i].n[k] : 1.0;
         e = launch_ctrl_init(b->ctrl[i], dx, 2, descs[i].cfl_desired, descs[i].cfl_max, descs[i].dt_max, false,
-                             result_offset(2), b->stream);
+                             batch_result_off(b), b->stream);
         if (e != hipSuccess) return bail(fail(CLAW_E_HIP, "control init failed: %s", hipGetErrorString(e)));
     }
     e = hipMemcpyAsync(b->ctrl_ptrs, b->ctrl.data(), sizeof(Ctrl*) * count, hipMemcpyHostToDevice, b->stream);
@@ -1428,7 +1514,8 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
     double best = 0;
     bool cached = cache_lookup(cache_path, key, &chunk, &schedule, &rpw, &best);
     // an entry that is no valid tile choice (an edited or damaged file) counts as a miss
-    if (cached && (chunk < kBatchChunkMin || chunk > 4096 || (schedule != 0 && schedule != 1) ||
+    const int chunk_min = b->fused ? kFusedChunkMin : kBatchChunkMin;
+    if (cached && (chunk < chunk_min || chunk > 4096 || (schedule != 0 && schedule != 1) ||
                    !batch_rpw_ok(rpw) || !(best > 0)))
         cached = false;
     if (!cached) {
@@ -1443,10 +1530,17 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
         HIP_TRY(hipEventCreate(&e1));
         best = 1e300;
         // candidates: schedule x column chunk x rows per row wavefront
+        // (fused batches: schedule x rows per fused workgroup; the row table
+        // serves only their speed passes)
         std::vector<std::array<int, 3>> cand;
-        for (int sched = 0; sched < 2; ++sched)
-            for (int c : kTuneChunks)
-                for (int r : kTuneRpw) cand.push_back({sched, c, r});
+        for (int sched = 0; sched < 2; ++sched) {
+            if (b->fused) {
+                for (int c : kTuneFusedChunks) cand.push_back({sched, c, ROW_RPW_BATCH_DEFAULT});
+            } else {
+                for (int c : kTuneChunks)
+                    for (int r : kTuneRpw) cand.push_back({sched, c, r});
+            }
+        }
         for (const auto& cd : cand) {
             st = batch_tables(b, cd[1], cd[0], cd[2]);
             if (st) break;
@@ -1490,7 +1584,8 @@ claw_status claw_batch_tune(claw_batch* b, const char* cache_path, int32_t* chun
 
 claw_status claw_batch_set_tiles(claw_batch* b, int32_t chunk, int32_t schedule, int32_t rows_per_wave) {
     if (!b) return fail(CLAW_E_INVALID, "batch is NULL");
-    if (chunk < kBatchChunkMin || (schedule != 0 && schedule != 1) || !batch_rpw_ok(rows_per_wave))
+    if (chunk < (b->fused ? kFusedChunkMin : kBatchChunkMin) || (schedule != 0 && schedule != 1) ||
+        !batch_rpw_ok(rows_per_wave))
         return fail(CLAW_E_INVALID, "bad tile choice");
     return batch_tables(b, chunk, schedule, rows_per_wave);
 }

@@ -56,7 +56,7 @@ def _col_normal(name):
     return args[3].strip() if len(args) > 3 else None
 
 
-SOURCE_FILES = {"step2d": ("fused.hip", "sweep_body.h", "claw_device.h", "plugins.h"),
+SOURCE_FILES = {"step2d": ("fused.hip", "step2d_body.inc", "sweep_body.h", "claw_device.h", "plugins.h"),
                 "sweeps": ("sweeps.hip", "sweep_body.h", "claw_device.h", "plugins.h")}
 
 

@@ -142,6 +142,18 @@ def run(claw, take=None):
     for k, q in enumerate(qs):
         done(f"batch_{k}", host(q))
     b.close()
+    # batched fused steps
+    probs, qs = [], []
+    for k, side in enumerate((64, 77, 300)):
+        p, q0, _ = inputs.sw_hump(n=side, seed=20 + k, dtype="f32")
+        p["fused_step"] = True
+        probs.append(p)
+        qs.append(dev(q0, "f32"))
+    b = claw.BatchSolver(probs, qs)
+    b.advance(4)
+    for k, q in enumerate(qs):
+        done(f"batch_fused_{k}", host(q))
+    b.close()
     # plug-in solver (Burgers-type law)
     prob, q0, _ = inputs.burgers2d(n=80, seed=1, dtype="f64", nsteps=5)
     q = dev(q0, "f64")

@@ -154,6 +154,24 @@ def test_batch_size_limits(claw):
     assert claw.claw_batch_workspace_bytes([_sw_desc(claw)] * 4) > 0
 
 
+def test_batch_step_flags(claw):
+    # a batch runs one kind of step: every instance split, or every instance
+    # fused (the fused batch holds its workgroup table and per-instance
+    # arguments in the workspace too); mixed or other flags are refused
+    split = _sw_desc(claw)
+    fused = _sw_desc(claw)
+    fused.flags = claw.CLAW_FLAG_FUSED_STEP
+    assert claw.claw_batch_workspace_bytes([fused] * 3) > claw.claw_batch_workspace_bytes([split] * 3)
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_batch_workspace_bytes([split, fused])
+    assert e.value.status == claw.CLAW_E_INVALID
+    strang = _sw_desc(claw)
+    strang.flags = claw.CLAW_FLAG_STRANG
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_batch_workspace_bytes([strang])
+    assert e.value.status == claw.CLAW_E_UNSUPPORTED
+
+
 def _burgers_desc(claw, ndim=2):
     from paper_1805_08846_amd import inputs
     prob, _, _ = (inputs.burgers2d(n=32) if ndim == 2 else inputs.burgers3d(n=16))
