@@ -348,7 +348,8 @@ def claw_batch_destroy(h):
 
 class BatchSolver:
     """An ensemble of 2D shallow-water problems advanced together; qs are torch
-    device tensors, one per problem (same dtype)."""
+    device tensors, one per problem (same dtype).  Problems with fused_step=True
+    (all or none) run the batched fused 2D step."""
 
     def __init__(self, probs, qs, stream=None):
         import torch
