@@ -157,7 +157,7 @@ def bench_ensemble(args, torch, claw, inputs):
     warm = args.warmup if args.warmup_given else 1
 
     def run_batch(fused):
-        probs = [dict(p, fused_step=True if fused else None) for p, _ in members]
+        probs = [dict(p, fused_step=fused) for p, _ in members]
         qs = [torch.tensor(q0, dtype=torch.float32, device="cuda").contiguous() for _, q0 in members]
         b = claw.BatchSolver(probs, qs)
         tuned = b.tune(os.environ.get("CLAW_AUTOTUNE_CACHE"))

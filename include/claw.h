@@ -276,10 +276,12 @@ claw_status claw_destroy(claw_solver* h);
  * step count).  Every sweep of every instance runs in one launch per sweep
  * direction; a table maps each workgroup to (instance, block), and the
  * whole multi-step run replays a captured HIP graph.  Each instance's result is
- * bitwise the single-grid result on the same step.  With CLAW_FLAG_FUSED_STEP
- * on every descriptor the batch runs the fused 2D step instead: per trial one
- * opening launch (one thread per instance) and one fused launch for all
- * instances.  Descriptors carry no other flag, and all carry the same one
+ * bitwise the single-grid result on the same step.  A batch runs the fused 2D
+ * step (per trial one opening launch, one thread per instance, and one fused
+ * launch for all instances) under the single grid's rule applied to the
+ * batch's whole state: with CLAW_FLAG_FUSED_STEP, or FP32 with at least
+ * CLAW_FUSED_AUTO_BYTES of state and no CLAW_FLAG_SPLIT_STEP; else the x and
+ * y sweeps.  Descriptors carry no other flag, and all carry the same ones
  * (CLAW_E_INVALID otherwise).
  * ------------------------------------------------------------------------- */
 typedef struct claw_batch claw_batch; /* opaque */

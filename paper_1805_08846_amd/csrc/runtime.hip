@@ -1079,6 +1079,17 @@ int inst_row_blocks(const claw_desc& d, bool fp32);
 int inst_col_blocks(const claw_desc& d, int chunk);
 int inst_fused_blocks(const claw_desc& d, bool fp32, int chunk);
 
+// A batch takes the fused 2D step under the single grid's rule applied to
+// its whole state: asked for (CLAW_FLAG_FUSED_STEP), or FP32 with at least
+// CLAW_FUSED_AUTO_BYTES of state and not CLAW_FLAG_SPLIT_STEP.
+bool batch_is_fused(const claw_desc* d, int count) {
+    if (d[0].flags & CLAW_FLAG_FUSED_STEP) return true;
+    if ((d[0].flags & CLAW_FLAG_SPLIT_STEP) || d[0].dtype != CLAW_FP32) return false;
+    uint64_t bytes = 0;
+    for (int i = 0; i < count; ++i) bytes += (uint64_t)d[i].n[0] * (uint64_t)d[i].n[1] * 3u * 4u;
+    return bytes >= (uint64_t)CLAW_FUSED_AUTO_BYTES;
+}
+
 claw_status batch_validate(const claw_desc* d, int32_t count) {
     if (!d || count < 1 || count > 65535) return fail(CLAW_E_INVALID, "need 1..65535 descriptors");
     for (int i = 0; i < count; ++i) {
@@ -1089,16 +1100,20 @@ claw_status batch_validate(const claw_desc* d, int32_t count) {
         if (d[i].dtype != d[0].dtype) return fail(CLAW_E_INVALID, "all instances need the same dtype");
         if (d[i].flags & ~(CLAW_FLAG_FUSED_STEP | CLAW_FLAG_SPLIT_STEP))
             return fail(CLAW_E_UNSUPPORTED, "batches run the split or the fused 2D step (instance %d)", i);
-        if ((d[i].flags & CLAW_FLAG_FUSED_STEP) != (d[0].flags & CLAW_FLAG_FUSED_STEP))
-            return fail(CLAW_E_INVALID, "all instances need the same step (instance %d)", i);
+        if ((d[i].flags & (CLAW_FLAG_FUSED_STEP | CLAW_FLAG_SPLIT_STEP)) !=
+            (d[0].flags & (CLAW_FLAG_FUSED_STEP | CLAW_FLAG_SPLIT_STEP)))
+            return fail(CLAW_E_INVALID, "all instances need the same step flags (instance %d)", i);
+        if ((d[i].flags & CLAW_FLAG_FUSED_STEP) && (d[i].flags & CLAW_FLAG_SPLIT_STEP))
+            return fail(CLAW_E_INVALID, "fused and split step both asked for (instance %d)", i);
     }
     // a batched sweep is one 1-D launch of 256-thread workgroups, and a
     // dispatch counts its work-items in 32 bits: at most 2^24 - 1 workgroups
     int64_t rows = 0, cols = 0, fused = 0;
+    const bool is_fused = batch_is_fused(d, count);
     for (int i = 0; i < count; ++i) {
         rows += inst_row_blocks(d[i], d[0].dtype == CLAW_FP32);
         cols += inst_col_blocks(d[i], kBatchChunkMin);
-        if (d[0].flags & CLAW_FLAG_FUSED_STEP) fused += inst_fused_blocks(d[i], d[0].dtype == CLAW_FP32, kFusedChunkMin);
+        if (is_fused) fused += inst_fused_blocks(d[i], d[0].dtype == CLAW_FP32, kFusedChunkMin);
     }
     const int64_t max_blocks = ((int64_t)1 << 24) - 1;
     if (rows > max_blocks || cols > max_blocks || fused > max_blocks)
@@ -1141,7 +1156,7 @@ BatchPlan batch_plan(const claw_desc* d, int count) {
     p.max_row_blocks = 0;
     p.max_col_blocks = 0;
     p.max_fused_blocks = 0;
-    const bool fused = (d[0].flags & CLAW_FLAG_FUSED_STEP) != 0;
+    const bool fused = batch_is_fused(d, count);
     for (int i = 0; i < count; ++i) {
         p.max_row_blocks += inst_row_blocks(d[i], fp32);
         p.max_col_blocks += inst_col_blocks(d[i], kBatchChunkMin);
@@ -1463,7 +1478,7 @@ claw_status claw_batch_create(const claw_desc* descs, int32_t count, void* const
     b->off_fused = bp.off_fused;
     b->off_fargs = bp.off_fargs;
     b->off_bufs = bp.off_bufs;
-    b->fused = (descs[0].flags & CLAW_FLAG_FUSED_STEP) != 0;
+    b->fused = batch_is_fused(descs, count);
     b->max_fused_blocks = bp.max_fused_blocks;
     b->args_stride = bp.args_stride;
     b->max_col_blocks = bp.max_col_blocks;

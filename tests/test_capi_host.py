@@ -165,6 +165,22 @@ def test_batch_step_flags(claw):
     with pytest.raises(claw.ClawError) as e:
         claw.claw_batch_workspace_bytes([split, fused])
     assert e.value.status == claw.CLAW_E_INVALID
+    # without flags a batch follows the single grid's rule on its whole
+    # state: 4 x 3000^2 FP32 (432 MB) takes the fused step, 3 small grids not
+    big = _sw_desc(claw)
+    big.n[0] = big.n[1] = 3000
+    big_fused = _sw_desc(claw)
+    big_fused.n[0] = big_fused.n[1] = 3000
+    big_fused.flags = claw.CLAW_FLAG_FUSED_STEP
+    big_split = _sw_desc(claw)
+    big_split.n[0] = big_split.n[1] = 3000
+    big_split.flags = claw.CLAW_FLAG_SPLIT_STEP
+    assert claw.claw_batch_workspace_bytes([big] * 4) == claw.claw_batch_workspace_bytes([big_fused] * 4)
+    assert claw.claw_batch_workspace_bytes([big] * 4) > claw.claw_batch_workspace_bytes([big_split] * 4)
+    assert claw.claw_batch_workspace_bytes([split] * 3) < claw.claw_batch_workspace_bytes([fused] * 3)
+    with pytest.raises(claw.ClawError) as e:
+        claw.claw_batch_workspace_bytes([big, big_split])
+    assert e.value.status == claw.CLAW_E_INVALID
     strang = _sw_desc(claw)
     strang.flags = claw.CLAW_FLAG_STRANG
     with pytest.raises(claw.ClawError) as e:
