@@ -57,6 +57,7 @@ __global__ void k_batch_ctrl(Ctrl* const* ctrls, int count, int op, int q, doubl
             StepState N;
             decide(c, q ^ 1, fp32 != 0, N);
             N.pending = N.done ? 0 : 1;
+            if (N.mode == MODE_ADAPT && !N.done) N.result_off = planned_result_off(N.cur, N.target - N.accepted);
             c->st[q] = N;
             clear_speeds(c, q);
             c->nonphys[q] = 0;

@@ -46,6 +46,20 @@ struct Fused3Args {
 };
 template <typename R>
 hipError_t launch_step_xy3(const Fused3Args<R>& F, int sys, hipStream_t s);
+// Result buffer of a trial that one kernel runs (the fused 2D step), chosen
+// when the trial opens: with r accepted steps to go in an adaptive run (r
+// counts this trial), the last one writes buffer 0, the caller's array, so
+// the run ends with no copy.  Two steps before the end the result goes to the
+// buffer that is neither the current one nor 0; earlier ones rotate.  A
+// result is never written over the trial's own input (a rejected trial keeps
+// it).  Returns the offset from the current buffer (1 or 2).
+__device__ __forceinline__ int planned_result_off(int cur, long long r) {
+    int dst;
+    if (r == 1) dst = cur != 0 ? 0 : 1;  // one step from buffer 0 cannot end in it
+    else if (r == 2) dst = cur != 0 ? 3 - cur : 1;
+    else dst = (cur + 1) % 3;
+    return (dst - cur + 3) % 3;
+}
 // Decides the previous trial into step-state copy p and clears p's speed slots.
 hipError_t launch_open(Ctrl* c, int p, bool fp32, hipStream_t s);
 int fused_rows_per_iteration();

@@ -34,11 +34,13 @@ constexpr int FR = 4;  // rows per iteration: one x-swept row per wavefront
 #endif
 
 // Decides the previous trial (copy p ^ 1), writes the step state this trial
-// runs with into copy p and clears copy p's speed slots.
+// runs with into copy p (an adaptive run's result buffer planned so that its
+// last step ends in buffer 0) and clears copy p's speed slots.
 __global__ void k_open(Ctrl* c, int p, int fp32) {
     StepState S;
     decide(c, p ^ 1, fp32 != 0, S);
     S.pending = S.done ? 0 : 1;
+    if (S.mode == MODE_ADAPT && !S.done) S.result_off = planned_result_off(S.cur, S.target - S.accepted);
     c->st[p] = S;
     clear_speeds(c, p);
     c->nonphys[p] = 0;

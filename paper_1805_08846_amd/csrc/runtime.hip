@@ -591,13 +591,19 @@ claw_status run_adaptive(claw_solver* h, int64_t nsteps, double dt0, bool graphs
             for (int64_t k = 0; k < remaining && st == CLAW_OK; ++k) st = enqueue_trial(h, h->stream, nullptr);
         }
         if (!st) st = commit(h);
-        if (!st) st = sync_state(h);
         if (!st) st = read_state(h, &S);
         if (st) return st;
-        if (S.err) return ctrl_status(S);
+        if (S.err) {  // the state stays the last accepted one
+            st = sync_state(h);
+            return st ? st : ctrl_status(S);
+        }
         remaining = S.target - S.accepted;
         if (S.done || remaining <= 0) break;
     }
+    // the caller's array receives the state once, after the last round (no
+    // copy when the last step already wrote it)
+    st = sync_state(h);
+    if (st) return st;
     if (t) *t = S.t;
     if (nreject) *nreject = S.rejected - S.base_rejected;
     if (S.accepted - S.base_accepted != nsteps) return fail(CLAW_E_STATE, "advance stopped early");

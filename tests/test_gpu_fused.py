@@ -118,3 +118,34 @@ def test_large_states_take_the_fused_step_by_default(claw):
     small, qs, _ = inputs.sw_radial_dam(n=512, dtype="f32", nsteps=2, seed=2)
     _, _, _, cnt3 = _run(claw, small, qs, None, steps=2)
     assert cnt3[1] >= 1  # a small state keeps the x and y sweep kernels
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_advance_in_pieces_equals_one_call_bitwise(claw, dtype):
+    # the fused step plans each trial's result buffer so that an adaptive call
+    # ends in the caller's array: calls of 1, 2, 3 and 5 steps (a one-step call
+    # from buffer 0 still ends elsewhere and is copied) equal one call of 11
+    prob, q0, _ = inputs.sw_radial_dam(n=200, dtype=dtype, nsteps=11, seed=9)
+    prob = dict(prob, fused_step=True)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
+    s = claw.Solver(prob, q)
+    t_one, rej_one = s.advance(11)
+    torch.cuda.synchronize()
+    one = q.double().cpu().numpy()
+    s.close()
+    q = torch.tensor(q0, dtype=tdt, device="cuda").contiguous()
+    s = claw.Solver(prob, q)
+    rej = 0
+    for k in (1, 2, 3, 5):
+        t, r = s.advance(k)
+        rej += r
+    torch.cuda.synchronize()
+    pieces = q.double().cpu().numpy()
+    ms, cnt = s.advance_timed(1)
+    s.close()
+    assert cnt[0] >= 1 and cnt[1] == 0
+    assert np.array_equal(pieces, one)
+    assert t == t_one and rej == rej_one
+    ref = oracle.advance(prob, q0, None, 11)
+    assert rel_linf(one, ref["q"])[0] <= TOL[dtype]
